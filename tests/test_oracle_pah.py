@@ -1,0 +1,110 @@
+"""Pins of the oracle's PAH steady-state solver (transient heating, P(T))."""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import oracle
+import synth
+
+LAM = synth.lambda_grid(200)
+M = 500
+
+
+def grid_for(pm, M=M, Ttop=5000.0):
+    T = 2.7 * (Ttop / 2.7) ** (np.arange(M) / (M - 1))
+    return T, pm.enthalpy(T)
+
+
+def solve(pm, J, M=M, **kw):
+    T, U = grid_for(pm, M)
+    return oracle.pah_solve(T, U, LAM, pm.cabs, pm.cband, pm.ccont, J, want_P=True, **kw)
+
+
+@pytest.mark.parametrize("nc", [30, 200])
+def test_recurrence_equals_dense_solve(nc):
+    pm = synth.pah_model(nc, LAM)
+    T, U = grid_for(pm)
+    J = synth.blackbody_field(LAM, [10.0, 1e5], [20000.0, 4000.0])
+    _, P, _ = solve(pm, J)
+    for c in range(2):
+        A, Ad = oracle.pah_rates(T, U, LAM, pm.cabs, J[c])
+        W = np.tril(A, -1).copy()            # W[f, i]: rate i -> f
+        W[np.arange(M - 1), np.arange(1, M)] = Ad[1:]
+        Q = W - np.diag(W.sum(0))
+        Q[0, :] = 1.0
+        b = np.zeros(M)
+        b[0] = 1.0
+        Pd = np.linalg.solve(Q, b)
+        # a dense LU resolves entries only down to ~1e-14 of the largest
+        m = P[c] > 1e-9 * P[c].max()
+        assert m.sum() > 100
+        assert np.max(np.abs(Pd[m] / P[c][m] - 1)) < 1e-10
+
+
+def test_three_state_by_hand():
+    pm = synth.pah_model(30, LAM)
+    T = np.array([20.0, 600.0, 1500.0])
+    U = pm.enthalpy(T)
+    J = synth.blackbody_field(LAM, [1e4], [15000.0])
+    A, Ad = oracle.pah_rates(T, U, LAM, pm.cabs, J[0])
+    out, P, _ = oracle.pah_solve(T, U, LAM, pm.cabs, pm.cband, pm.ccont, J, want_P=True)
+    # flux balance across each boundary:  P1 Ad1 = P0 (A10 + A20);  P2 Ad2 = P0 A20 + P1 A21
+    p0 = 1.0
+    p1 = p0 * (A[1, 0] + A[2, 0]) / Ad[1]
+    p2 = (p0 * A[2, 0] + p1 * A[2, 1]) / Ad[2]
+    ref = np.array([p0, p1, p2]) / (p0 + p1 + p2)
+    assert np.allclose(P[0], ref, rtol=1e-13)
+
+
+@pytest.mark.parametrize("nc", [30, 200])
+def test_discrete_energy_identity(nc):
+    # absorbed: sum_{i<f} P_i A_fi (U_f - U_i) ; emitted: all outputs
+    pm = synth.pah_model(nc, LAM)
+    T, U = grid_for(pm)
+    J = synth.blackbody_field(LAM, [3.0, 3e3, 1e6], [30000.0, 8000.0, 20000.0])
+    out, P, pabs = solve(pm, J)
+    for c in range(3):
+        A, Ad = oracle.pah_rates(T, U, LAM, pm.cabs, J[c])
+        dU = U[:, None] - U[None, :]
+        absorbed = (np.tril(A, -1) * dU * P[c][None, :]).sum()
+        assert abs(out[c].sum() / absorbed - 1) < 1e-11
+        # the discrete absorbed power approximates 4 pi int C J dnu (rate prefactors)
+        assert abs(absorbed / pabs[c] - 1) < 0.03
+
+
+@pytest.mark.parametrize("nc", [30, 200])
+def test_linear_regime(nc):
+    # weak fields: single-photon heating, band and mid-IR emission scale with G0
+    # (the far-IR of barely excited molecules also feels ground-state depletion)
+    pm = synth.pah_model(nc, LAM)
+    J = synth.blackbody_field(LAM, [1e-3, 1e-2], [10000.0, 10000.0])
+    out, P, _ = solve(pm, J)
+    assert P[1][0] > 0.99
+    mid_ir = np.concatenate([np.ones(17, bool), LAM < 30.0])
+    m = (out[0] > 1e-6 * out[0].sum()) & mid_ir
+    assert m.sum() > 40
+    assert np.max(np.abs(out[1][m] / out[0][m] / 10.0 - 1)) < 1e-5
+
+
+def test_strong_field_large_molecule_reaches_equilibrium():
+    pm = synth.pah_model(20000, LAM)
+    J = synth.blackbody_field(LAM, [1e6], [10000.0])
+    out, P, pabs = solve(pm, J)
+    T, _ = grid_for(pm)
+    nu, dnu = oracle.lambda_bins(LAM)
+    pem = lambda t: 4 * np.pi * sum(pm.cabs[j] * oracle.planck_nu(nu[j], t) * dnu[j] for j in range(LAM.size))
+    Teq = brentq(lambda t: pem(t) - pabs[0], 3.0, 4999.0)
+    assert abs(T[np.argmax(P[0])] / Teq - 1) < 0.02
+    assert abs((P[0] * T).sum() / Teq - 1) < 0.02
+
+
+def test_small_molecule_fluctuates_and_top_bin_empty():
+    # transient heating: a 30 C PAH in a moderate field spends most time cold
+    # but reaches far above the equilibrium temperature
+    pm = synth.pah_model(30, LAM)
+    J = synth.blackbody_field(LAM, [1e2, 1e6], [20000.0, 40000.0])
+    out, P, pabs = solve(pm, J)
+    T, _ = grid_for(pm)
+    assert T[np.argmax(P[0])] < 30.0
+    assert P[0][T > 500].sum() > 1e-6
+    assert P[0][-1] < 1e-10 and P[1][-1] < 1e-10

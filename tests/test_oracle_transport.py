@@ -1,0 +1,200 @@
+"""Pins of the oracle's packet transport: closed forms, hand traces,
+exact bookkeeping identities, scattering moments, shard additivity."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import synth
+
+AU = synth.AU
+
+
+def cnt(r, name):
+    return int(r["counters"][oracle.CNT[name]])
+
+
+def conservation(r, S_nabs=None):
+    assert cnt(r, "launched") == cnt(r, "escaped") + cnt(r, "killed") + cnt(r, "terminated")
+    assert int(r["nabs"].sum()) == cnt(r, "absorptions")
+    assert int(r["sed"].sum()) == cnt(r, "escaped")
+
+
+def test_conservation_sphere_and_disk():
+    for w in (synth.c1_sphere(n_packets=5000), synth.small_disk(n_packets=3000)):
+        r = oracle.Session(w).transport()
+        conservation(r)
+        assert cnt(r, "killed") == 0 and cnt(r, "escaped") == w.n_packets
+
+
+def test_slab_transmission_binomial():
+    # pencil beam at normal incidence through a pure absorber of tau = 2
+    w = synth.uniform_cube(4, 0.5, albedo=0.0, n_packets=40000)
+    w.source.pos = np.array([2.3, 1.7, 0.0])
+    w.source.beam = np.array([0.0, 0.0, 1.0])
+    s = oracle.Session(w, flags=oracle.FLAG_KILL_ON_ABSORB | oracle.FLAG_TALLY_J)
+    r = s.transport()
+    conservation(r)
+    p = math.exp(-2.0)
+    n = w.n_packets
+    k = cnt(r, "escaped")
+    assert abs(k - n * p) < 4.5 * math.sqrt(n * p * (1 - p))
+    # the transmitted packets leave through the top face: theta bin of mu = +1
+    assert int(r["sed"][-1].sum()) == k
+
+
+def _cube_escape_fraction(alpha, a=1.0):
+    # (1/4pi) * closed surface integral of exp(-alpha r) over the solid angle
+    f = lambda y, x: math.exp(-alpha * math.sqrt(x * x + y * y + a * a)) * a / (x * x + y * y + a * a) ** 1.5
+    v, err = integrate.dblquad(f, -a, a, -a, a, epsabs=1e-13, epsrel=1e-12)
+    return 6.0 * v / (4 * math.pi)
+
+
+def test_cube_escape_fraction_quadrature():
+    # star at the centre of a uniform pure absorber, alpha = 0.4 per cell, 6^3
+    w = synth.uniform_cube(6, 0.4, albedo=0.0, n_packets=60000)
+    r = oracle.Session(w, flags=oracle.FLAG_KILL_ON_ABSORB).transport()
+    conservation(r)
+    p = _cube_escape_fraction(0.4, 3.0)
+    n = w.n_packets
+    assert abs(_cube_escape_fraction(0.0) - 1.0) < 1e-9
+    assert abs(cnt(r, "escaped") - n * p) < 4.5 * math.sqrt(n * p * (1 - p))
+
+
+def _trace(w, n=1, **kw):
+    s = oracle.Session(w, **kw)
+    return s.transport(n=n, trace_cap=64)["trace"]
+
+
+def test_hand_trace_vertex_start_plus_x():
+    # 4^3 cells of side 1, alpha = 1 per cell, start on the vertex (2,2,2), +x
+    for seed in range(1, 30):
+        w = synth.uniform_cube(4, 1.0, albedo=0.0, seed=seed)
+        w.source.pos = np.array([2.0, 2.0, 2.0])
+        w.source.beam = np.array([1.0, 0.0, 0.0])
+        tr = _trace(w, flags=oracle.FLAG_KILL_ON_ABSORB)[0]
+        tau0 = tr[0]["tau"]
+        assert tr[0]["cell"] == 2 + 4 * (2 + 4 * 2)            # floor rule: + side cell
+        if tau0 < 2.0:
+            k = int(math.floor(tau0))                           # faces crossed
+            assert [e["type"] for e in tr] == [0] + [1] * k + [3]
+            for i in range(k):
+                assert tr[1 + i]["x"][0] == 3.0 + i and tr[1 + i]["cell"] == 3 + i + 4 * (2 + 4 * 2)
+            assert abs(tr[-1]["x"][0] - (2.0 + tau0)) < 1e-12
+            assert tr[-1]["cell"] == int(2.0 + tau0) + 4 * (2 + 4 * 2)
+        else:
+            assert [e["type"] for e in tr] == [0, 1, 4]
+
+
+def test_hand_trace_vertex_start_minus_x_zero_length_step():
+    w = synth.uniform_cube(4, 1.0, albedo=0.0, seed=3)
+    w.source.pos = np.array([2.0, 2.0, 2.0])
+    w.source.beam = np.array([-1.0, 0.0, 0.0])
+    tr = _trace(w, flags=oracle.FLAG_KILL_ON_ABSORB)[0]
+    assert tr[1]["type"] == 1 and tr[1]["x"][0] == 2.0          # zero-length crossing
+    assert tr[1]["cell"] == 1 + 4 * (2 + 4 * 2)
+    assert abs(tr[1]["tau"] - tr[0]["tau"]) == 0.0
+
+
+def test_hand_trace_corner_tie_lowest_axis_first():
+    # direction (1,1,0)/sqrt2 from (2.5,2.5,2.5): reaches the edge x=y=3 at once
+    w = synth.uniform_cube(4, 1e-9, albedo=0.0, seed=3)
+    w.source.pos = np.array([2.5, 2.5, 2.5])
+    w.source.beam = np.array([1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    tr = _trace(w, flags=oracle.FLAG_KILL_ON_ABSORB)[0]
+    cells = [int(e["cell"]) for e in tr]
+    idx = lambda i, j, k: i + 4 * (j + 4 * k)
+    assert cells[:3] == [idx(2, 2, 2), idx(3, 2, 2), idx(3, 3, 2)]
+    assert tr[2]["x"][1] == 3.0 and tr[1]["x"][0] == 3.0
+    assert tr[-1]["type"] == 4
+
+
+def test_segments_stay_in_their_cells_and_directions_unit():
+    w = synth.small_disk(n_packets=200, nl=16, n_sizes=1)
+    s = oracle.Session(w)
+    g = w.grid
+    nf = 1 << g.max_level
+    tr = s.transport(n=200, trace_cap=4000)["trace"]
+    for t in tr:
+        for e in t:
+            assert abs(np.linalg.norm(e["d"]) - 1.0) < 1e-12
+            if e["type"] in (1, 2, 3):
+                c = e["cell"]
+                lo = g.leaf_lo[c] / nf
+                hi = lo + 2.0 ** -float(g.leaf_level[c])
+                assert np.all(e["x"] >= lo - 1e-9) and np.all(e["x"] <= hi + 1e-9)
+
+
+def test_hg_and_isotropic_moments():
+    # pure scatterer, g = 0.5: deflection cosines from consecutive directions
+    w = synth.uniform_cube(8, 2.0, albedo=1.0, g=0.5, n_packets=400)
+    tr = _trace(w, n=400)
+    mus = []
+    for t in tr:
+        for a, b in zip(t[:-1], t[1:]):
+            if b["type"] == 2:
+                mus.append(float(np.dot(a["d"], b["d"])))
+    mus = np.array(mus)
+    n = mus.size
+    assert n > 5000
+    g = 0.5
+    assert abs(mus.mean() - g) < 4 * math.sqrt((1 + 2 * g * g) / 3 - g * g) / math.sqrt(n)
+    assert abs((mus ** 2).mean() - (1 + 2 * g * g) / 3) < 0.02
+    # absorbing medium: re-emission isotropic
+    w = synth.uniform_cube(8, 2.0, albedo=0.0, n_packets=300)
+    tr = _trace(w, n=300)
+    d = np.array([e["d"] for t in tr for e in t if e["type"] == 3])
+    assert d.shape[0] > 2000
+    assert np.all(np.abs(d.mean(0)) < 4 / math.sqrt(3 * d.shape[0]))
+    assert abs((d[:, 2] ** 2).mean() - 1 / 3) < 0.03
+
+
+def test_frozen_T_shards_add_up_and_threads_agree():
+    w = synth.small_disk(n_packets=3000)
+    base = oracle.Session(w).transport()["nabs"]
+    s1 = oracle.Session(w, frozen_nabs=base)
+    full = s1.transport(0, 3000)
+    a = s1.transport(0, 1700)
+    b = s1.transport(1700, 1300)
+    for key in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(full[key], a[key] + b[key])
+    thr = oracle.Session(w, frozen_nabs=base, n_threads=4).transport(0, 3000)
+    for key in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(full[key], thr[key])
+
+
+def test_optically_thin_gray_temperature():
+    # T^4 = L <r^-2>_cell / (16 pi sigma) for gray grains in a thin medium
+    nb = 4
+    Rb = 2.0 * AU
+    w = synth.uniform_cube(nb, 1.0, albedo=0.0, nl=400, n_packets=1000000, seed=17)
+    w.species.lam_um = synth.lambda_grid(400, 0.05, 5000.0)
+    w.grid.box_min = np.full(3, -Rb)
+    w.grid.base_size = 2 * Rb / nb
+    w.source.pos = np.zeros(3)
+    w.source.lum = synth.L_SUN
+    w.source.teff = 5800.0
+    w.T_lo, w.T_hi = 3.0, 5000.0
+    kap = 1e-2 / (w.grid.base_size * 1.0)     # tau = 0.01 per cell side at rho = 1
+    w.species.kabs = np.full((1, 400), kap)
+    w.species.ksca = np.zeros((1, 400))
+    s = oracle.Session(w, flags=oracle.FLAG_KILL_ON_ABSORB, n_threads=4)
+    r = s.transport()
+    T = s.temperatures(r["nabs"])[:, 0]
+    N = r["nabs"][:, 0].astype(float)
+    sigma = 5.670374419e-5
+    rng = np.random.default_rng(1)
+    lo, side = w.grid.leaf_boxes_cm()
+    checked = 0
+    for c in range(w.grid.n_cells):
+        if N[c] < 200:
+            continue
+        pts = lo[c] + side[c] * rng.random((200000, 3))
+        r2 = (1.0 / (pts ** 2).sum(1)).mean()
+        Tref = (w.source.lum * r2 / (16 * np.pi * sigma)) ** 0.25
+        # attenuation over tau <= 0.02 lowers T by at most ~0.5%
+        assert abs(T[c] / Tref - 1) < 4.5 / (4 * math.sqrt(N[c])) + 5e-3
+        checked += 1
+    assert checked >= 8
