@@ -1,0 +1,199 @@
+/*
+ * mcrt.h -- C ABI of the MI355X Monte Carlo dust radiative-transfer engine.
+ *
+ * Method (Siebenmorgen, Heymann & Kruegel, "PAH in vectorized three
+ * dimensional Monte Carlo dust radiative transfer models", Sec. 2): a point
+ * star emits photon packets of constant energy eps = L / N_total; each packet
+ * flies cell by cell through a grid of base cubes and subcubes, interacting
+ * where the extinction optical depth along its path reaches a sampled value;
+ * a scattering changes only its direction (Henyey-Greenstein phase function);
+ * an absorption adds eps to the cell and re-emits the packet isotropically
+ * from the same spot at a frequency drawn from the temperature of the cell
+ * *before* the absorption (the form without the Bjorkman & Wood correction,
+ * which lets packets fly in parallel).
+ *
+ * Conventions for every entry point:
+ *  - All arrays named "device" are caller-owned device memory (e.g. torch
+ *    tensors); the library never allocates device memory and never frees
+ *    caller memory.  Host structs are copied at the call.
+ *  - Every launch is asynchronous on the given stream; results are visible
+ *    after the stream is synchronised.  Only functions ending in _sync block.
+ *  - Return value: MCRT_OK or a negative MCRT_E_* code; the message of the
+ *    last error of a context is returned by mcrt_last_error.  No C++
+ *    exception crosses the boundary.  Kernel faults surface at the next
+ *    synchronising call as MCRT_E_HIP.
+ *  - A context holds non-owning pointers to the descriptor's device arrays:
+ *    they must outlive it.  Calls on one context must not overlap in time
+ *    (they share the run scratch held in the tables buffer).
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRT_VERSION 100
+
+#define MCRT_OK 0
+#define MCRT_E_INVALID (-1)     /* null pointer, bad size or range */
+#define MCRT_E_STATE (-2)       /* wrong call order (e.g. run before tables) */
+#define MCRT_E_HIP (-3)         /* HIP runtime error; message carries the code */
+#define MCRT_E_CAPACITY (-4)    /* caller buffer too small */
+#define MCRT_E_NUMERIC (-5)     /* NaN or negative input values */
+#define MCRT_E_UNSUPPORTED (-6)
+
+#define MCRT_F32 0              /* transport geometry in FP32 */
+#define MCRT_F64 1              /* transport geometry in FP64 */
+
+#define MCRT_FLAG_TALLY_J 1         /* path-length mean-intensity tally */
+#define MCRT_FLAG_FROZEN_T 2        /* temperature bracket from frozen_nabs */
+#define MCRT_FLAG_KILL_ON_ABSORB 4  /* test mode: absorption ends the packet */
+
+/* counter slots of mcrt_tallies.counters */
+#define MCRT_CNT_LAUNCHED 0
+#define MCRT_CNT_ESCAPED 1
+#define MCRT_CNT_KILLED 2        /* hit the per-packet event cap */
+#define MCRT_CNT_TERMINATED 3    /* ended by KILL_ON_ABSORB */
+#define MCRT_CNT_SCATTERS 4
+#define MCRT_CNT_ABSORPTIONS 5
+#define MCRT_CNT_CROSSINGS 6     /* segments ending on a cell face */
+#define MCRT_CNT_TCLAMP_LO 7     /* absorbed energy below E(T_lo) */
+#define MCRT_CNT_TCLAMP_HI 8     /* absorbed energy at or above E(T_{K-2}) bracket */
+#define MCRT_CNT_PAH_ABS 9
+#define MCRT_CNT_ZERO_CROSS 10   /* zero-length face crossings (ties) */
+#define MCRT_N_COUNTERS 16
+
+typedef struct mcrt_ctx mcrt_ctx;
+
+/* Problem description (paper Sec. 1 dust model, Sec. 2 grid).
+ * Wavelength bins: centres lambda_um[j], edges at geometric midpoints,
+ * cross-sections constant in a bin.  Opacities are cm^2 per gram of the dust
+ * mixture (species mass fractions folded in); every species follows the same
+ * density law rho (g cm^-3) per cell.  Grid: nb^3 base cubes of side
+ * base_size (cm) from box_min; base_map[ix + nb*(iy + nb*iz)] is a leaf id
+ * (>= 0) or -(node+1); nodes[8*node + o] for octant o = bx | by<<1 | bz<<2
+ * uses the same encoding; leaves are max_level deep at most. */
+typedef struct {
+  int32_t precision;           /* MCRT_F32 or MCRT_F64 */
+  int32_t n_lambda;            /* >= 2 */
+  int32_t n_species;           /* 1..256 */
+  int32_t nb;                  /* base cubes per axis */
+  int32_t max_level;           /* 0..10, nb * 2^max_level <= 2^20 */
+  int32_t K;                   /* temperature grid points, >= 2 */
+  int64_t n_cells;             /* leaves */
+  int64_t n_nodes;             /* interior nodes */
+  double box_min[3];           /* cm */
+  double base_size;            /* cm */
+  double T_lo, T_hi;           /* temperature grid, log spaced, K */
+  int32_t n_theta, n_phi;      /* escape-direction bins (equal cos, equal phi) */
+  const double *lambda_um;     /* device [n_lambda], increasing */
+  const double *kabs;          /* device [n_species * n_lambda] */
+  const double *ksca;          /* device [n_species * n_lambda] */
+  const double *g;             /* device [n_lambda] HG asymmetry */
+  const int32_t *kind;         /* device [n_species]: 0 equilibrium, 1 PAH */
+  const int32_t *base_map;     /* device [nb^3] */
+  const int32_t *nodes;        /* device [8 * n_nodes] (may be NULL if 0) */
+  const double *rho;           /* device [n_cells] */
+} mcrt_desc;
+
+/* Point source (paper Sec. 2: the star).  Blackbody of teff integrated over
+ * the bins; isotropic unless beam_on (pencil beam along beam[], unit). */
+typedef struct {
+  double pos[3];               /* cm */
+  double lum;                  /* erg s^-1 */
+  double teff;                 /* K */
+  double beam[3];
+  int32_t beam_on;
+} mcrt_source;
+
+/* Integer tallies, device, accumulated (+=) by every run. */
+typedef struct {
+  uint64_t *nabs;              /* [n_cells * n_species] absorbed packets */
+  uint64_t *sed;               /* [n_theta * n_phi * n_lambda] escaped packets */
+  uint64_t *jq;                /* [n_lambda * n_cells] path sums, unit
+                                  base_size * 2^-(max_level+16) cm; NULL if
+                                  TALLY_J is off */
+  uint64_t *counters;          /* [MCRT_N_COUNTERS] */
+} mcrt_tallies;
+
+/* Per-packet event trace (debug/test only). */
+typedef struct {
+  int32_t type, cell, j, pad;  /* type: 0 launch 1 cross 2 scatter 3 absorb 4 escape 5 killed */
+  double x[3], d[3], tau;      /* x in base-cube units */
+} mcrt_trace_rec;
+
+typedef struct {
+  uint64_t n_total;            /* packets of the whole pass: eps = lum / n_total */
+  uint64_t seed;               /* Philox key */
+  uint64_t max_events;         /* interactions per packet before it is killed */
+  int32_t flags;               /* MCRT_FLAG_* */
+  int32_t grid_blocks;         /* 0 = automatic */
+  const uint64_t *frozen_nabs; /* device [n_cells * n_species] for FROZEN_T */
+  const double *pah_rows;      /* device [n_pah][n_cells][n_lambda] re-emission
+                                  CDF rows, required when PAH species exist */
+  mcrt_trace_rec *trace;       /* device [n_packets * trace_cap] or NULL */
+  int32_t *trace_len;          /* device [n_packets] */
+  int32_t trace_cap;
+  int32_t pad;
+} mcrt_run_opts;
+
+/* Byte offsets of the tables inside the tables buffer (for inspection). */
+typedef struct {
+  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt;
+  uint64_t kext32, g32, rho_h32, level, pah_slot, scratch, total;
+} mcrt_table_layout;
+
+int32_t mcrt_version(void);
+
+/* Size of the tables buffer for a description (no device work). */
+int32_t mcrt_tables_bytes(const mcrt_desc *desc, uint64_t *bytes);
+
+/* Validates the description on the host and copies it. */
+int32_t mcrt_ctx_create(const mcrt_desc *desc, mcrt_ctx **out);
+void mcrt_ctx_destroy(mcrt_ctx *ctx);
+const char *mcrt_last_error(const mcrt_ctx *ctx);
+int32_t mcrt_table_layout_get(const mcrt_ctx *ctx, mcrt_table_layout *out);
+
+/* Builds, in FP64 on the device, every table of the method into `tables`
+ * (caller-owned, >= mcrt_tables_bytes): bin frequencies and widths, the
+ * source CDF over bins, extinction/albedo, the species choice CDF per bin,
+ * E_s(T_k) = 4 pi sum_j kabs_s B_j(T_k) dnu_j on the log T grid and the
+ * difference-emissivity rows R_{s,k}(j) (CDF over j of
+ * kabs_s [B_j(T_{k+1}) - B_j(T_k)] dnu_j), leaf levels and FP32 copies.
+ * Blocks once, before any table kernel runs, to check the device inputs:
+ * MCRT_E_NUMERIC for NaN/inf/negative opacities or densities, wavelengths not
+ * positive and increasing, or |g| >= 1; MCRT_E_INVALID for a grid whose
+ * entries are out of range, whose child nodes do not follow their parent, or
+ * which is deeper than max_level.  The table kernels then run asynchronously.
+ * The source spectrum is fixed here (teff); lum and pos are read per run. */
+int32_t mcrt_build_tables(mcrt_ctx *ctx, const mcrt_source *src, void *tables,
+                          uint64_t tables_bytes, hipStream_t stream);
+
+/* Transports packets with ids [first_id, first_id + n_packets) (paper Sec. 2)
+ * and adds their tallies.  Random numbers: Philox4x32-10 keyed by seed,
+ * counter (id_lo, id_hi, event, 0|1).  Requires mcrt_build_tables. */
+int32_t mcrt_run(mcrt_ctx *ctx, uint64_t first_id, uint64_t n_packets,
+                 const mcrt_run_opts *opts, const mcrt_tallies *tallies,
+                 hipStream_t stream);
+
+/* Equilibrium temperature of every (cell, equilibrium species): solves
+ * nabs * eps = rho V E_s(T) for T in [T_lo, T_hi] in FP64 (bracket from the
+ * E table, safeguarded Newton on the exact bin sum).  nabs == 0 gives T_lo;
+ * PAH species give 0.  T_out: device [n_cells * n_species] double. */
+int32_t mcrt_temperatures(mcrt_ctx *ctx, const uint64_t *nabs, uint64_t n_total,
+                          double *T_out, hipStream_t stream);
+
+/* Path-length mean intensity (Lucy 1999):
+ * J_nu[c][j] = eps * dq * jq[j][c] / (4 pi V_c dnu_j), erg s^-1 cm^-2 Hz^-1 sr^-1.
+ * J_out: device [n_cells * n_lambda] float. */
+int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
+                            float *J_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

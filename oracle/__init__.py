@@ -215,6 +215,23 @@ class Session:
             res["trace"] = [tr[k * trace_cap:k * trace_cap + tl[k]] for k in range(n)]
         return res
 
+    def accumulate(self, acc, first_id: int, n: int):
+        """Run packets [first_id, first_id+n) adding into acc (dict of uint64 arrays
+        nabs, sed, jq, counters as made by new_accumulator)."""
+        o = Out(nabs=_p(acc["nabs"], _u64p), sed=_p(acc["sed"], _u64p),
+                jq=_p(acc.get("jq"), _u64p), counters=_p(acc["counters"], _u64p))
+        rc = lib().orc_transport(C.byref(self.p), C.byref(self._T), first_id, n, C.byref(o))
+        if rc != 0:
+            raise RuntimeError(f"orc_transport failed: {rc}")
+        return acc
+
+    def new_accumulator(self):
+        p = self.p
+        return dict(nabs=np.zeros(p.n_cells * p.S, np.uint64),
+                    sed=np.zeros(p.n_theta * p.n_phi * p.nl, np.uint64),
+                    jq=np.zeros(p.nl * p.n_cells, np.uint64) if (p.flags & FLAG_TALLY_J) else None,
+                    counters=np.zeros(16, np.uint64))
+
     def temperatures(self, nabs):
         p = self.p
         nabs = np.ascontiguousarray(nabs, np.uint64).reshape(-1)

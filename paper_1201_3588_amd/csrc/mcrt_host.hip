@@ -1,0 +1,181 @@
+// C ABI of the transport engine: descriptor validation, error codes, launches
+// on the caller's stream.  No exception crosses the boundary.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mcrt_internal.h"
+
+using namespace mcrt;
+
+namespace {
+
+int32_t fail(mcrt_ctx* c, int32_t code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int32_t hip_fail(mcrt_ctx* c, hipError_t e, const char* where) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+  return fail(c, MCRT_E_HIP, buf);
+}
+
+const char* check_desc(const mcrt_desc* d) {
+  if (!d) return "null descriptor";
+  if (d->precision != MCRT_F32 && d->precision != MCRT_F64) return "precision must be MCRT_F32 or MCRT_F64";
+  if (d->n_lambda < 2) return "n_lambda must be >= 2";
+  if (d->n_species < 1 || d->n_species > 256) return "n_species must be in 1..256";
+  if (d->nb < 1) return "nb must be >= 1";
+  if (d->max_level < 0 || d->max_level > 10) return "max_level must be in 0..10";
+  if ((int64_t)d->nb << d->max_level > (1 << 20)) return "nb * 2^max_level must be <= 2^20";
+  if ((int64_t)d->nb * d->nb * d->nb > (int64_t)1 << 31) return "nb^3 too large";
+  if (d->K < 2) return "K must be >= 2";
+  if (d->n_cells < 1 || d->n_cells >= ((int64_t)1 << 31)) return "n_cells out of range";
+  if (d->n_nodes < 0 || d->n_nodes >= ((int64_t)1 << 28)) return "n_nodes out of range";
+  if (d->n_nodes > 0 && d->max_level < 1) return "nodes need max_level >= 1";
+  if (!(d->base_size > 0.0) || !std::isfinite(d->base_size)) return "base_size must be > 0";
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->box_min[a])) return "box_min must be finite";
+  if (!(d->T_lo > 0.0) || !(d->T_hi > d->T_lo) || !std::isfinite(d->T_hi)) return "need 0 < T_lo < T_hi";
+  if (d->n_theta < 1 || d->n_phi < 1) return "n_theta, n_phi must be >= 1";
+  if (!d->lambda_um || !d->kabs || !d->ksca || !d->g || !d->kind || !d->base_map || !d->rho)
+    return "null device array in descriptor";
+  if (d->n_nodes > 0 && !d->nodes) return "nodes is null but n_nodes > 0";
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mcrt_version(void) { return MCRT_VERSION; }
+
+int32_t mcrt_tables_bytes(const mcrt_desc* desc, uint64_t* bytes) {
+  if (check_desc(desc) || !bytes) return MCRT_E_INVALID;
+  *bytes = make_layout(*desc).total;
+  return MCRT_OK;
+}
+
+int32_t mcrt_ctx_create(const mcrt_desc* desc, mcrt_ctx** out) {
+  if (!out) return MCRT_E_INVALID;
+  *out = nullptr;
+  if (check_desc(desc)) return MCRT_E_INVALID;
+  mcrt_ctx* c = new (std::nothrow) mcrt_ctx();
+  if (!c) return MCRT_E_INVALID;
+  c->d = *desc;
+  c->lay = make_layout(*desc);
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    c->device = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      c->n_cu = ncu;
+  }
+  *out = c;
+  return MCRT_OK;
+}
+
+void mcrt_ctx_destroy(mcrt_ctx* ctx) { delete ctx; }
+
+const char* mcrt_last_error(const mcrt_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t mcrt_table_layout_get(const mcrt_ctx* ctx, mcrt_table_layout* out) {
+  if (!ctx || !out) return MCRT_E_INVALID;
+  const Layout& L = ctx->lay;
+  *out = mcrt_table_layout{L.nu, L.dnu, L.src_cdf, L.kext, L.albedo, L.gpar, L.sp_cdf, L.Tk, L.E,
+                           L.R, L.Bt, L.kext32, L.g32, L.rho_h32, L.level, L.pah_slot, L.scratch,
+                           L.total};
+  return MCRT_OK;
+}
+
+int32_t mcrt_build_tables(mcrt_ctx* ctx, const mcrt_source* src, void* tables, uint64_t tables_bytes,
+                          hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!src || !tables) return fail(ctx, MCRT_E_INVALID, "null source or tables");
+  if (tables_bytes < ctx->lay.total) return fail(ctx, MCRT_E_CAPACITY, "tables buffer too small");
+  if (!(src->teff > 0.0) || !std::isfinite(src->teff)) return fail(ctx, MCRT_E_NUMERIC, "teff must be > 0");
+  if (!(src->lum > 0.0) || !std::isfinite(src->lum)) return fail(ctx, MCRT_E_NUMERIC, "lum must be > 0");
+  if (src->beam_on) {
+    const double n = std::sqrt(src->beam[0] * src->beam[0] + src->beam[1] * src->beam[1] +
+                               src->beam[2] * src->beam[2]);
+    if (!(std::fabs(n - 1.0) < 1e-6)) return fail(ctx, MCRT_E_NUMERIC, "beam must be a unit vector");
+  }
+  ctx->tables = static_cast<unsigned char*>(tables);
+  ctx->src = *src;
+  ctx->tables_built = false;
+  hipError_t e = launch_checks(ctx, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "input check launch");
+  unsigned long long bad = 0;
+  std::vector<int32_t> kind(ctx->d.n_species);
+  e = hipMemcpyAsync(&bad, ctx->tables + ctx->lay.scratch + offsetof(RunScratch, bad_input),
+                     sizeof bad, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(kind.data(), ctx->d.kind, sizeof(int32_t) * kind.size(),
+                       hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "input check");
+  if (bad & 16ull) return fail(ctx, MCRT_E_INVALID, "grid structure invalid (range, order or depth)");
+  ctx->n_pah = 0;
+  for (int32_t k : kind) {
+    if (k != 0 && k != 1) return fail(ctx, MCRT_E_INVALID, "species kind must be 0 or 1");
+    ctx->n_pah += k == 1;
+  }
+  if (bad) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "input values invalid (flags 0x%llx: 1 rho, 2 opacity, 4 lambda, 8 g)", bad);
+    return fail(ctx, MCRT_E_NUMERIC, buf);
+  }
+  e = launch_build_tables(ctx, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "table build launch");
+  ctx->tables_built = true;
+  return MCRT_OK;
+}
+
+int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcrt_run_opts* opts,
+                 const mcrt_tallies* tallies, hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!ctx->tables_built) return fail(ctx, MCRT_E_STATE, "mcrt_run before mcrt_build_tables");
+  if (!opts || !tallies) return fail(ctx, MCRT_E_INVALID, "null opts or tallies");
+  if (!tallies->nabs || !tallies->sed || !tallies->counters)
+    return fail(ctx, MCRT_E_INVALID, "null tally array");
+  if ((opts->flags & MCRT_FLAG_TALLY_J) && !tallies->jq)
+    return fail(ctx, MCRT_E_INVALID, "TALLY_J needs tallies->jq");
+  if ((opts->flags & MCRT_FLAG_FROZEN_T) && !opts->frozen_nabs)
+    return fail(ctx, MCRT_E_INVALID, "FROZEN_T needs frozen_nabs");
+  if (opts->flags & ~7) return fail(ctx, MCRT_E_INVALID, "unknown flag bits");
+  if (opts->n_total == 0) return fail(ctx, MCRT_E_INVALID, "n_total must be > 0");
+  if (opts->trace && (!opts->trace_len || opts->trace_cap < 1))
+    return fail(ctx, MCRT_E_INVALID, "trace needs trace_len and trace_cap >= 1");
+  if (first_id + n_packets < first_id) return fail(ctx, MCRT_E_INVALID, "packet id range overflows");
+  if (ctx->n_pah > 0 && !opts->pah_rows && !(opts->flags & MCRT_FLAG_KILL_ON_ABSORB))
+    return fail(ctx, MCRT_E_INVALID, "PAH species need pah_rows");
+  if (n_packets == 0) return MCRT_OK;
+  const hipError_t e = launch_transport(ctx, first_id, n_packets, *opts, *tallies, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "transport launch");
+  return MCRT_OK;
+}
+
+int32_t mcrt_temperatures(mcrt_ctx* ctx, const uint64_t* nabs, uint64_t n_total, double* T_out,
+                          hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!ctx->tables_built) return fail(ctx, MCRT_E_STATE, "temperatures before mcrt_build_tables");
+  if (!nabs || !T_out || n_total == 0) return fail(ctx, MCRT_E_INVALID, "null array or n_total == 0");
+  const hipError_t e = launch_temperatures(ctx, nabs, n_total, T_out, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "temperature launch");
+  return MCRT_OK;
+}
+
+int32_t mcrt_mean_intensity(mcrt_ctx* ctx, const uint64_t* jq, uint64_t n_total, float* J_out,
+                            hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!ctx->tables_built) return fail(ctx, MCRT_E_STATE, "mean intensity before mcrt_build_tables");
+  if (!jq || !J_out || n_total == 0) return fail(ctx, MCRT_E_INVALID, "null array or n_total == 0");
+  const hipError_t e = launch_mean_intensity(ctx, jq, n_total, J_out, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mean intensity launch");
+  return MCRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP translation units of libmcrt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "mcrt.h"
+
+namespace mcrt {
+
+constexpr double kC = 2.99792458e10;     // cm s^-1
+constexpr double kH = 6.62607015e-27;    // erg s
+constexpr double kKB = 1.380649e-16;     // erg K^-1
+constexpr double kPi = 3.14159265358979323846;
+
+// Philox4x32-10 (Salmon et al. 2011): round multipliers and key increments.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// (0,1] uniform from the top 24 bits of a word (exact in FP32 and FP64).
+__device__ __forceinline__ double u24(uint32_t w) {
+  return (double)((w >> 8) + 1u) * (1.0 / 16777216.0);
+}
+
+__device__ __forceinline__ double planck_nu(double nu, double T) {
+  const double x = kH * nu / (kKB * T);
+  return 2.0 * kH * nu * nu * nu / (kC * kC) / expm1(x);
+}
+
+// first index j in [0,n) with cdf[j] >= u; cdf[n-1] == 1
+__device__ __forceinline__ int cdf_search(const double* __restrict__ cdf, int n, double u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cdf[mid] >= u) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+struct Layout {
+  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt;
+  uint64_t kext32, g32, rho_h32, level, pah_slot, scratch, total;
+};
+
+// run scratch inside the tables buffer (zeroed by a fill kernel per run)
+struct RunScratch {
+  unsigned long long work_counter;
+  unsigned long long bad_input;
+  unsigned long long pad[30];
+};
+
+Layout make_layout(const mcrt_desc& d);
+
+}  // namespace mcrt
+
+struct mcrt_ctx {
+  mcrt_desc d;
+  mcrt::Layout lay;
+  int n_pah = 0;
+  bool tables_built = false;
+  unsigned char* tables = nullptr;   // caller-owned device buffer
+  mcrt_source src{};
+  std::string err;
+  int device = 0;
+  int n_cu = 256;
+};
+
+namespace mcrt {
+hipError_t launch_checks(mcrt_ctx* c, hipStream_t s);
+hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s);
+hipError_t launch_transport(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_opts& o,
+                            const mcrt_tallies& t, hipStream_t s);
+hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
+                               hipStream_t s);
+hipError_t launch_mean_intensity(mcrt_ctx* c, const uint64_t* jq, uint64_t n_total, float* J,
+                                 hipStream_t s);
+}  // namespace mcrt

@@ -1,0 +1,121 @@
+// After a pass: equilibrium temperatures (FP64) from the absorbed-packet
+// tallies (paper Sec. 2: each absorption raises the cell energy by eps and
+// thereby its temperature) and the path-length mean intensity J_nu per cell
+// (Lucy 1999, the packet scheme the method goes back to).
+#include "mcrt_internal.h"
+
+namespace mcrt {
+
+namespace {
+
+// One thread per (cell, species): solve N eps = rho V E_s(T).  The bracket
+// [T_k, T_{k+1}] comes from the tabulated E_s(T_k); inside it a safeguarded
+// Newton iteration runs on the exact bin sum 4 pi sum_j kabs B_j(T) dnu_j.
+__global__ void k_temperatures(int64_t n_cells, int S, int nl, int K, double h, double eps,
+                               double T_lo, double T_hi, const int32_t* __restrict__ kind,
+                               const double* __restrict__ kabs, const double* __restrict__ nu,
+                               const double* __restrict__ dnu, const double* __restrict__ Tk,
+                               const double* __restrict__ E, const double* __restrict__ rho,
+                               const int8_t* __restrict__ level,
+                               const unsigned long long* __restrict__ nabs, double* __restrict__ T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cells * S) return;
+  const int64_t c = i / S;
+  const int s = (int)(i % S);
+  if (kind[s] != 0) { T[i] = 0.0; return; }
+  const unsigned long long N = nabs[i];
+  const double r = rho[c];
+  if (N == 0ull || !(r > 0.0)) { T[i] = T_lo; return; }
+  const double vol = pow(h * ldexp(1.0, -(int)level[c]), 3.0);
+  const double p = (double)N * eps / (r * vol);
+  const double* Es = E + (int64_t)s * K;
+  if (p <= Es[0]) { T[i] = T_lo; return; }
+  if (p >= Es[K - 1]) { T[i] = T_hi; return; }
+  int a = 0, b = K - 1;                // Es[a] < p < Es[b]
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (Es[m] <= p) a = m; else b = m;
+  }
+  double lo = Tk[a], hi = Tk[b];
+  // start: power-law interpolation between the bracket ends
+  double t = lo * pow(hi / lo, log(p / Es[a]) / log(Es[b] / Es[a]));
+  const double* ka = kabs + (int64_t)s * nl;
+  for (int it = 0; it < 60; ++it) {
+    double e = 0.0, de = 0.0;
+    for (int j = 0; j < nl; ++j) {
+      const double x = kH * nu[j] / (kKB * t);
+      const double em1 = expm1(x);
+      const double B = 2.0 * kH * nu[j] * nu[j] * nu[j] / (kC * kC) / em1;
+      e += ka[j] * B * dnu[j];
+      de += ka[j] * B * dnu[j] * (x / t) * ((em1 + 1.0) / em1);
+    }
+    e *= 4.0 * kPi;
+    de *= 4.0 * kPi;
+    const double f = e - p;
+    if (f > 0.0) hi = t; else lo = t;
+    double tn = de > 0.0 ? t - f / de : 0.5 * (lo + hi);
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (fabs(tn - t) <= 1e-15 * t || hi - lo <= 1e-15 * hi) { t = tn; break; }
+    t = tn;
+  }
+  T[i] = t;
+}
+
+// J[c][j] = eps dq Q[j][c] / (4 pi V_c dnu_j): 32x32 tiles through LDS turn
+// the [lambda][cell] tally into the [cell][lambda] field.
+__global__ void k_mean_intensity(int64_t n_cells, int nl, double h, int L, double eps,
+                                 const double* __restrict__ dnu, const int8_t* __restrict__ level,
+                                 const unsigned long long* __restrict__ jq, float* __restrict__ J) {
+  __shared__ double tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32;
+  const int j0 = blockIdx.y * 32;
+  const double dq = h * ldexp(1.0, -(L + 16));
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int j = j0 + r;
+    const int64_t c = c0 + threadIdx.x;
+    if (j < nl && c < n_cells) tile[r][threadIdx.x] = (double)jq[(int64_t)j * n_cells + c];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int64_t c = c0 + r;
+    const int j = j0 + threadIdx.x;
+    if (j < nl && c < n_cells) {
+      const double vol = pow(h * ldexp(1.0, -(int)level[c]), 3.0);
+      J[c * nl + j] = (float)(eps * dq * tile[threadIdx.x][r] / (4.0 * kPi * vol * dnu[j]));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
+                               hipStream_t s) {
+  const mcrt_desc& d = c->d;
+  const Layout& L = c->lay;
+  unsigned char* B = c->tables;
+  const int64_t n = d.n_cells * d.n_species;
+  k_temperatures<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(
+      d.n_cells, d.n_species, d.n_lambda, d.K, d.base_size, c->src.lum / (double)n_total, d.T_lo,
+      d.T_hi, d.kind, d.kabs, reinterpret_cast<const double*>(B + L.nu),
+      reinterpret_cast<const double*>(B + L.dnu), reinterpret_cast<const double*>(B + L.Tk),
+      reinterpret_cast<const double*>(B + L.E), d.rho, reinterpret_cast<const int8_t*>(B + L.level),
+      reinterpret_cast<const unsigned long long*>(nabs), T);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_intensity(mcrt_ctx* c, const uint64_t* jq, uint64_t n_total, float* J,
+                                 hipStream_t s) {
+  const mcrt_desc& d = c->d;
+  const Layout& L = c->lay;
+  unsigned char* B = c->tables;
+  dim3 grid((unsigned)((d.n_cells + 31) / 32), (unsigned)((d.n_lambda + 31) / 32));
+  dim3 block(32, 8);
+  k_mean_intensity<<<grid, block, 0, s>>>(d.n_cells, d.n_lambda, d.base_size, d.max_level,
+                                          c->src.lum / (double)n_total,
+                                          reinterpret_cast<const double*>(B + L.dnu),
+                                          reinterpret_cast<const int8_t*>(B + L.level),
+                                          reinterpret_cast<const unsigned long long*>(jq), J);
+  return hipGetLastError();
+}
+
+}  // namespace mcrt

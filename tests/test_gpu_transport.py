@@ -1,0 +1,241 @@
+"""GPU parity of the transport engine against the CPU oracle (through the C ABI).
+
+* tables: FP64 device tables equal the oracle's to rounding;
+* traces: with the temperature field frozen, a packet's history is a pure
+  function of (seed, id); FP64 geometry reproduces the oracle's histories
+  (event types and cells exact, positions to 1e-9), FP32 geometry to 1e-5;
+* integer bookkeeping identities hold exactly;
+* statistics: independent GPU and oracle runs agree within 3 sigma
+  (batch-means sigma over 32 packet-id batches);
+* temperatures and mean intensity equal the oracle's for the same tallies.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+mcrt = pytest.importorskip("paper_1201_3588_amd.mcrt")
+
+
+def engine(w, precision=None):
+    e = mcrt.Engine.from_workload(w, precision=precision)
+    e.build_tables(w.source.pos, w.source.lum, w.source.teff, beam=w.source.beam)
+    return e
+
+
+def host(tal):
+    torch.cuda.synchronize()
+    return {k: (mcrt.u64_view(v) if v is not None else None) for k, v in tal.items()}
+
+
+def conservation(r, n):
+    c = r["counters"]
+    assert c[0] == n
+    assert c[0] == c[1] + c[2] + c[3]
+    assert int(r["nabs"].sum()) == int(c[5])
+    assert int(r["sed"].sum()) == int(c[1])
+
+
+# --------------------------------------------------------------------------
+def test_tables_match_oracle():
+    for w in (synth.c1_sphere(n_packets=10), synth.small_disk(n_packets=10)):
+        e = engine(w)
+        g = e.tables_numpy()
+        t = oracle.Session(w).tables
+        for k in ("nu", "dnu", "src_cdf", "kext", "albedo", "Tk", "E"):
+            assert np.allclose(g[k], t[k], rtol=1e-13, atol=0), k
+        assert np.allclose(g["sp_cdf"], t["sp_cdf"], rtol=1e-13, atol=1e-15)
+        assert np.allclose(g["R"], t["R"], rtol=1e-12, atol=1e-15)
+        assert np.all(g["R"][..., -1] == 1.0)
+        assert np.array_equal(g["level"], w.grid.leaf_level)
+
+
+def _compare_traces(gt, ot, pos_tol):
+    """Number of packets whose (type, cell) sequences agree; positions checked."""
+    same = 0
+    for a, b in zip(gt, ot):
+        if len(a) != len(b) or np.any(a["type"] != b["type"]) or np.any(a["cell"] != b["cell"]) \
+                or np.any(a["j"] != b["j"]):
+            continue
+        same += 1
+        scale = np.maximum(1.0, np.abs(b["x"]))
+        assert np.max(np.abs(a["x"] - b["x"]) / scale) < pos_tol
+        assert np.max(np.abs(a["d"] - b["d"])) < pos_tol * 10
+        assert np.max(np.abs(a["tau"] - b["tau"]) / np.maximum(1.0, np.abs(b["tau"]))) < pos_tol * 10
+    return same
+
+
+@pytest.mark.parametrize("precision,tol,min_frac", [("f64", 1e-9, 0.999), ("f32", 1e-5, 0.98)])
+def test_fixed_random_traces(precision, tol, min_frac):
+    for w in (synth.small_disk(n_packets=400, nl=32, n_sizes=2, nb=8),
+              synth.uniform_cube(8, 0.7, albedo=0.5, g=0.6, n_packets=400)):
+        base = oracle.Session(w).transport(n=2000)["nabs"]
+        e = engine(w, precision)
+        tal = e.new_tallies(tally_j=True)
+        gt = e.run(tal, 100, 400, w.n_packets, w.seed, frozen_nabs=base, trace_cap=600,
+                   flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+        ot = oracle.Session(w, frozen_nabs=base).transport(100, 400, trace_cap=600)["trace"]
+        same = _compare_traces(gt, ot, tol)
+        assert same >= min_frac * 400, (precision, same)
+
+
+def test_fp64_frozen_tallies_equal_oracle():
+    w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
+    w.precision = "f64"
+    base = oracle.Session(w).transport()["nabs"]
+    e = engine(w)
+    tal = e.new_tallies()
+    e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    g = host(tal)
+    o = oracle.Session(w, frozen_nabs=base).transport()
+    assert np.array_equal(g["counters"], o["counters"])
+    assert np.array_equal(g["nabs"], o["nabs"].reshape(-1))
+    assert np.array_equal(g["sed"], o["sed"].reshape(-1))
+    assert np.array_equal(g["jq"], o["jq"].reshape(-1))
+
+
+def test_shards_add_up_bit_exact():
+    w = synth.small_disk(n_packets=20000, nl=32, n_sizes=2, nb=8)
+    base = np.zeros((w.grid.n_cells, w.species.n_species), np.uint64) + 3
+    e = engine(w)
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    full = e.new_tallies()
+    e.run(full, 0, 20000, 20000, 5, frozen_nabs=base, flags=flags)
+    part = e.new_tallies()
+    e.run(part, 0, 7000, 20000, 5, frozen_nabs=base, flags=flags)
+    e.run(part, 7000, 13000, 20000, 5, frozen_nabs=base, flags=flags, grid_blocks=3)
+    a, b = host(full), host(part)
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_conservation_full_sphere():
+    w = synth.c1_sphere()            # 1e5 packets, FP64
+    e = engine(w)
+    tal = e.new_tallies(tally_j=False)
+    e.run(tal, 0, w.n_packets, w.n_packets, w.seed, flags=0)
+    conservation(host(tal), w.n_packets)
+
+
+def _three_sigma(ga, oa, min_count=100.0):
+    """ga, oa: [B, n] per-batch tallies of two independent runs.  Returns
+    (fraction beyond 3 sigma, max |z|, chi2/dof, outputs compared); sigma of a
+    total is sqrt(B) times the standard deviation of its batch values."""
+    B = ga.shape[0]
+    gs, os_ = ga.sum(0), oa.sum(0)
+    var = B * ga.var(0, ddof=1) + B * oa.var(0, ddof=1)
+    m = (np.minimum(gs, os_) > min_count) & (var > 0)
+    z = (gs[m] - os_[m]) / np.sqrt(var[m])
+    return float(np.mean(np.abs(z) > 3)), float(np.max(np.abs(z))), float(np.mean(z * z)), int(m.sum())
+
+
+def shells(nabs, w, n_shell=12):
+    lo, side = w.grid.leaf_boxes_cm()
+    r = np.linalg.norm(lo + 0.5 * side[:, None] - w.source.pos, axis=1)
+    idx = np.minimum((r / (r.max() + 1e-30) * n_shell).astype(int), n_shell - 1)
+    S = w.species.n_species
+    nabs = nabs.reshape(-1, S).astype(np.float64)
+    out = np.stack([np.bincount(idx, weights=nabs[:, s], minlength=n_shell) for s in range(S)], 1)
+    return out.reshape(-1)
+
+
+def summaries(d, w):
+    """Outputs compared statistically: SED bins, absorptions in radial shells
+    per species, and the path-length tally summed over cells per bin."""
+    out = dict(sed=d["sed"].astype(np.float64), shells=shells(d["nabs"], w))
+    if d.get("jq") is not None:
+        out["jq"] = d["jq"].reshape(w.species.n_lambda, -1).astype(np.float64).sum(1)
+    return out
+
+
+def batch_runs(run, B):
+    """run(b) -> cumulative tallies after batch b; returns per-batch summaries [B, n]."""
+    prev, rows = None, []
+    for b in range(B):
+        cur = {k: v.copy() for k, v in run(b).items() if v is not None}
+        d = cur if prev is None else {k: cur[k] - prev[k] for k in cur}
+        rows.append(d)
+        prev = cur
+    return rows
+
+
+def statistical_check(w, B=32, seed_gpu=None, seed_orc=None):
+    nb_ = w.n_packets // B
+    e = engine(w)
+    tal = e.new_tallies(tally_j=w.tally_j)
+    sg = seed_gpu if seed_gpu is not None else w.seed
+    so = seed_orc if seed_orc is not None else 1000 + w.seed
+
+    def gpu_run(b):
+        e.run(tal, b * nb_, nb_, w.n_packets, sg)
+        return host(tal)
+
+    s = oracle.Session(w, seed=so, n_threads=8)
+    acc = s.new_accumulator()
+
+    def orc_run(b):
+        return s.accumulate(acc, b * nb_, nb_)
+
+    G = [summaries(d, w) for d in batch_runs(gpu_run, B)]
+    O = [summaries(d, w) for d in batch_runs(orc_run, B)]
+    res = {}
+    for k in G[0]:
+        ga = np.stack([g[k] for g in G])
+        oa = np.stack([o[k] for o in O])
+        res[k] = _three_sigma(ga, oa)
+    conservation(host(tal), w.n_packets)
+    return res
+
+
+@pytest.mark.parametrize("name", ["c1", "disk"])
+def test_statistical_parity(name):
+    if name == "c1":
+        w = synth.c1_sphere(n_packets=320000)
+    else:
+        w = synth.small_disk(n_packets=96000, nl=40, n_sizes=2, nb=16)
+    res = statistical_check(w)
+    for k, (frac, zmax, chi2, n) in res.items():
+        assert n >= 5, (k, n)
+        assert frac <= 0.02 and zmax < 6.0, (k, frac, zmax, chi2, n)
+        if n >= 50:                          # chi2/dof is only meaningful with many outputs
+            assert 0.6 < chi2 < 1.5, (k, frac, zmax, chi2, n)
+
+
+def test_temperatures_and_intensity_equal_oracle():
+    w = synth.small_disk(n_packets=20000, nl=40, n_sizes=2, nb=16)
+    s = oracle.Session(w, n_threads=8)
+    r = s.transport()
+    T_o = s.temperatures(r["nabs"])
+    J_o = s.mean_intensity(r["jq"])
+    e = engine(w)
+    nabs = torch.as_tensor(r["nabs"].reshape(-1).view(np.int64)).cuda()
+    jq = torch.as_tensor(r["jq"].reshape(-1).view(np.int64)).cuda()
+    T_g = e.temperatures(nabs, w.n_packets).cpu().numpy()
+    J_g = e.mean_intensity(jq, w.n_packets).cpu().numpy()
+    assert np.allclose(T_g, T_o, rtol=1e-11, atol=0)
+    assert (T_o > w.T_lo).sum() > 100
+    assert np.allclose(J_g, J_o, rtol=2e-7, atol=1e-30 * J_o.max())
+
+
+def test_invalid_inputs_are_rejected():
+    w = synth.small_disk(n_packets=10, nl=16, n_sizes=1, nb=8)
+    w.grid.rho = w.grid.rho.copy()
+    w.grid.rho[5] = np.nan
+    e = mcrt.Engine.from_workload(w)
+    with pytest.raises(mcrt.MCRTError) as ei:
+        e.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    assert ei.value.code == -5
+    w = synth.small_disk(n_packets=10, nl=16, n_sizes=1, nb=8)
+    bm = w.grid.base_map.copy()
+    bm[0] = w.grid.n_cells + 5
+    w.grid.base_map = bm
+    e = mcrt.Engine.from_workload(w)
+    with pytest.raises(mcrt.MCRTError) as ei:
+        e.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    assert ei.value.code == -1
