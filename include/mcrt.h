@@ -65,6 +65,7 @@ extern "C" {
 #define MCRT_CNT_TCLAMP_HI 8     /* absorbed energy at or above E(T_{K-2}) bracket */
 #define MCRT_CNT_PAH_ABS 9
 #define MCRT_CNT_ZERO_CROSS 10   /* zero-length face crossings (ties) */
+#define MCRT_CNT_JSEG 11         /* segments added to the path-length tally */
 #define MCRT_N_COUNTERS 16
 
 typedef struct mcrt_ctx mcrt_ctx;
@@ -192,6 +193,17 @@ int32_t mcrt_temperatures(mcrt_ctx *ctx, const uint64_t *nabs, uint64_t n_total,
  * J_out: device [n_cells * n_lambda] float. */
 int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
                             float *J_out, hipStream_t stream);
+
+/* Random-access microbenchmark defining the achievable ceiling of the
+ * transport kernel's memory traffic.  mode 0: ceil(n_ops / threads) * threads
+ * 64-bit atomic adds (+1) to uniformly random slots of table[n_slots]
+ * (device, caller-owned, contents incremented); mode 1: as many random 4-byte
+ * loads from loads[n_load] (device), sink (device, 1 float) keeps them live.
+ * The number of operations actually issued is n_ops rounded up to a multiple
+ * of 16 * 256 * (compute units).  Asynchronous on stream. */
+int32_t mcrt_bench_random(uint64_t *table, uint64_t n_slots, const float *loads, uint64_t n_load,
+                          uint64_t n_ops, uint64_t seed, int32_t mode, float *sink,
+                          hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -285,8 +285,10 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
       /* interaction inside this cell */
       double s = tau / alpha;
       for (int a = 0; a < 3; ++a) x[a] += s * d[a];
-      if ((p->flags & ORC_FLAG_TALLY_J) && dusty)
+      if ((p->flags & ORC_FLAG_TALLY_J) && dusty) {
         add_u64(&o->jq[(int64_t)j * p->n_cells + cell], (uint64_t)rint(s * qscale), thr);
+        add_u64(&cnt[ORC_CNT_JSEG], 1, thr);
+      }
       events += 1;
       if (events > p->max_events) {
         add_u64(&cnt[ORC_CNT_KILLED], 1, thr);
@@ -338,8 +340,10 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
     }
     /* cross the face to the neighbour */
     if (alpha > 0.0) tau -= alpha * tex;
-    if ((p->flags & ORC_FLAG_TALLY_J) && dusty)
+    if ((p->flags & ORC_FLAG_TALLY_J) && dusty) {
       add_u64(&o->jq[(int64_t)j * p->n_cells + cell], (uint64_t)rint(tex * qscale), thr);
+      add_u64(&cnt[ORC_CNT_JSEG], 1, thr);
+    }
     add_u64(&cnt[ORC_CNT_CROSSINGS], 1, thr);
     if (tex == 0.0) add_u64(&cnt[ORC_CNT_ZERO_CROSS], 1, thr);
     for (int a = 0; a < 3; ++a) x[a] += tex * d[a];

@@ -27,7 +27,7 @@
 enum {
   ORC_CNT_LAUNCHED = 0, ORC_CNT_ESCAPED, ORC_CNT_KILLED, ORC_CNT_TERMINATED,
   ORC_CNT_SCATTERS, ORC_CNT_ABSORPTIONS, ORC_CNT_CROSSINGS, ORC_CNT_TCLAMP_LO,
-  ORC_CNT_TCLAMP_HI, ORC_CNT_PAH_ABS, ORC_CNT_ZERO_CROSS, ORC_N_COUNTERS = 16
+  ORC_CNT_TCLAMP_HI, ORC_CNT_PAH_ABS, ORC_CNT_ZERO_CROSS, ORC_CNT_JSEG, ORC_N_COUNTERS = 16
 };
 
 enum { ORC_EV_LAUNCH = 0, ORC_EV_CROSS = 1, ORC_EV_SCATTER = 2, ORC_EV_ABSORB = 3,

@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
   R x0 = 0, x1 = 0, x2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0;
   int j = 0, cell = 0, lev = 0, lo0 = 0, lo1 = 0, lo2 = 0;
   unsigned long long c_launch = 0, c_esc = 0, c_kill = 0, c_term = 0, c_scat = 0, c_abs = 0,
-                     c_cross = 0, c_tlo = 0, c_thi = 0, c_pah = 0, c_zero = 0;
+                     c_cross = 0, c_tlo = 0, c_thi = 0, c_pah = 0, c_zero = 0, c_jseg = 0;
 
   for (;;) {
     if (!exhausted) {
@@ -252,8 +252,10 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
       // ---- interaction inside this cell
       const R s = tau / alpha;
       x0 += s * d0; x1 += s * d1; x2 += s * d2;
-      if (tally_j && dusty)
+      if (tally_j && dusty) {
         atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], (unsigned long long)rrint(s * P.qscale));
+        c_jseg++;
+      }
       events += 1;
       if (events > P.max_events) {
         c_kill++;
@@ -331,8 +333,10 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
 
     // ---- cross the face into the neighbour
     if (alpha > R(0)) tau -= alpha * tex;
-    if (tally_j && dusty)
+    if (tally_j && dusty) {
       atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], (unsigned long long)rrint(tex * P.qscale));
+      c_jseg++;
+    }
     c_cross++;
     if (tex == R(0)) c_zero++;
     x0 += tex * d0; x1 += tex * d1; x2 += tex * d2;
@@ -369,10 +373,10 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
   }
 
   // ---- counters: one atomic per wave per slot
-  unsigned long long vals[11] = {c_launch, c_esc, c_kill, c_term, c_scat, c_abs,
-                                 c_cross, c_tlo, c_thi, c_pah, c_zero};
+  unsigned long long vals[12] = {c_launch, c_esc, c_kill, c_term, c_scat, c_abs,
+                                 c_cross, c_tlo, c_thi, c_pah, c_zero, c_jseg};
 #pragma unroll
-  for (int i = 0; i < 11; ++i) {
+  for (int i = 0; i < 12; ++i) {
     const unsigned long long s = wave_sum(vals[i]);
     if (lane == 0 && s) atomicAdd(&P.counters[i], s);
   }

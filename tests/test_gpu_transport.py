@@ -56,16 +56,17 @@ def test_tables_match_oracle():
         assert np.array_equal(g["level"], w.grid.leaf_level)
 
 
-def _compare_traces(gt, ot, pos_tol):
-    """Number of packets whose (type, cell) sequences agree; positions checked."""
+def _compare_traces(gt, ot, pos_tol, extent):
+    """Number of packets whose (type, cell, bin) sequences agree; for those,
+    positions must agree to pos_tol relative to the grid extent (FP32 rounding
+    accumulates along a path), directions to 10 pos_tol."""
     same = 0
     for a, b in zip(gt, ot):
         if len(a) != len(b) or np.any(a["type"] != b["type"]) or np.any(a["cell"] != b["cell"]) \
                 or np.any(a["j"] != b["j"]):
             continue
         same += 1
-        scale = np.maximum(1.0, np.abs(b["x"]))
-        assert np.max(np.abs(a["x"] - b["x"]) / scale) < pos_tol
+        assert np.max(np.abs(a["x"] - b["x"])) / extent < pos_tol
         assert np.max(np.abs(a["d"] - b["d"])) < pos_tol * 10
         assert np.max(np.abs(a["tau"] - b["tau"]) / np.maximum(1.0, np.abs(b["tau"]))) < pos_tol * 10
     return same
@@ -81,7 +82,7 @@ def test_fixed_random_traces(precision, tol, min_frac):
         gt = e.run(tal, 100, 400, w.n_packets, w.seed, frozen_nabs=base, trace_cap=600,
                    flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
         ot = oracle.Session(w, frozen_nabs=base).transport(100, 400, trace_cap=600)["trace"]
-        same = _compare_traces(gt, ot, tol)
+        same = _compare_traces(gt, ot, tol, float(w.grid.nb))
         assert same >= min_frac * 400, (precision, same)
 
 
