@@ -144,8 +144,8 @@ typedef struct {
 
 /* Byte offsets of the tables inside the tables buffer (for inspection). */
 typedef struct {
-  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt;
-  uint64_t kext32, g32, rho_h32, level, pah_slot, scratch, total;
+  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt, Wt, xk;
+  uint64_t kext32, g32, rho_h32, level, binfo, pah_slot, scratch, total;
 } mcrt_table_layout;
 
 int32_t mcrt_version(void);

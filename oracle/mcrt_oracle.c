@@ -314,7 +314,7 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
         if (p->kind[sp] == 0) {
           /* temperature bracket before this absorption:
            * k = max{k : E_s(T_k) <= N_before eps / (rho V)}, clamped */
-          double vol = pow(h * side, 3.0);
+          double vol = ldexp(h * h * h, -3 * lev);
           double pw = (double)before * eps / (p->rho[cell] * vol);
           const double *E = t->E + (int64_t)sp * K;
           int kb;
@@ -402,7 +402,7 @@ static double emission(const orc_problem *p, const orc_tables *t, int s, double 
 
 /* volume (cm^3) of every leaf, from its depth in the tree */
 static void leaf_volumes_rec(const orc_problem *p, int32_t e, int lev, double *vol) {
-  if (e >= 0) { vol[e] = pow(p->base_size * ldexp(1.0, -lev), 3.0); return; }
+  if (e >= 0) { vol[e] = ldexp(p->base_size * p->base_size * p->base_size, -3 * lev); return; }
   for (int o = 0; o < 8; ++o) leaf_volumes_rec(p, p->nodes[(int64_t)(-e - 1) * 8 + o], lev + 1, vol);
 }
 

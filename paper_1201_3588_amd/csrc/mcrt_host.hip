@@ -86,7 +86,7 @@ int32_t mcrt_table_layout_get(const mcrt_ctx* ctx, mcrt_table_layout* out) {
   if (!ctx || !out) return MCRT_E_INVALID;
   const Layout& L = ctx->lay;
   *out = mcrt_table_layout{L.nu, L.dnu, L.src_cdf, L.kext, L.albedo, L.gpar, L.sp_cdf, L.Tk, L.E,
-                           L.R, L.Bt, L.kext32, L.g32, L.rho_h32, L.level, L.pah_slot, L.scratch,
+                           L.R, L.Bt, L.Wt, L.xk, L.kext32, L.g32, L.rho_h32, L.level, L.binfo, L.pah_slot, L.scratch,
                            L.total};
   return MCRT_OK;
 }

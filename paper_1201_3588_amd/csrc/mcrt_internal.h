@@ -48,8 +48,8 @@ __device__ __forceinline__ int cdf_search(const double* __restrict__ cdf, int n,
 }
 
 struct Layout {
-  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt;
-  uint64_t kext32, g32, rho_h32, level, pah_slot, scratch, total;
+  uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt, Wt, xk;
+  uint64_t kext32, g32, rho_h32, level, binfo, pah_slot, scratch, total;
 };
 
 // run scratch inside the tables buffer (zeroed by a fill kernel per run)

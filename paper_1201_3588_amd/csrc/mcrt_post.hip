@@ -10,14 +10,29 @@ namespace {
 
 // One thread per (cell, species): solve N eps = rho V E_s(T).  The bracket
 // [T_k, T_{k+1}] comes from the tabulated E_s(T_k); inside it a safeguarded
-// Newton iteration runs on the exact bin sum 4 pi sum_j kabs B_j(T) dnu_j.
-__global__ void k_temperatures(int64_t n_cells, int S, int nl, int K, double h, double eps,
-                               double T_lo, double T_hi, const int32_t* __restrict__ kind,
-                               const double* __restrict__ kabs, const double* __restrict__ nu,
-                               const double* __restrict__ dnu, const double* __restrict__ Tk,
-                               const double* __restrict__ E, const double* __restrict__ rho,
-                               const int8_t* __restrict__ level,
-                               const unsigned long long* __restrict__ nabs, double* __restrict__ T) {
+// Newton iteration runs on the exact bin sum
+//   E_s(T) = sum_j W[j][s] / expm1(x_j / T),  W = 4 pi kabs_s(j) dnu_j 2 h nu_j^3 / c^2,
+// x_j = h nu_j / k.  Newton converges quadratically from the power-law start
+// inside the bracket, so a step below 1e-8 T leaves an error far below FP64
+// resolution and ends the iteration.  W and x are staged in LDS when they fit.
+__global__ void __launch_bounds__(256) k_temperatures(
+    int64_t n_cells, int S, int nl, int K, double h, double eps, double T_lo, double T_hi,
+    const int32_t* __restrict__ kind, const double* __restrict__ Wg, const double* __restrict__ xg,
+    const double* __restrict__ Tk, const double* __restrict__ E, const double* __restrict__ rho,
+    const int8_t* __restrict__ level, const unsigned long long* __restrict__ nabs,
+    double* __restrict__ T, int use_lds) {
+  extern __shared__ double sm[];
+  const double* W = Wg;
+  const double* xk = xg;
+  if (use_lds) {
+    double* sW = sm;
+    double* sx = sm + (int64_t)nl * S;
+    for (int i = threadIdx.x; i < nl * S; i += blockDim.x) sW[i] = Wg[i];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) sx[i] = xg[i];
+    __syncthreads();
+    W = sW;
+    xk = sx;
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_cells * S) return;
   const int64_t c = i / S;
@@ -26,37 +41,37 @@ __global__ void k_temperatures(int64_t n_cells, int S, int nl, int K, double h, 
   const unsigned long long N = nabs[i];
   const double r = rho[c];
   if (N == 0ull || !(r > 0.0)) { T[i] = T_lo; return; }
-  const double vol = pow(h * ldexp(1.0, -(int)level[c]), 3.0);
+  const double vol = ldexp(h * h * h, -3 * (int)level[c]);
   const double p = (double)N * eps / (r * vol);
   const double* Es = E + (int64_t)s * K;
   if (p <= Es[0]) { T[i] = T_lo; return; }
   if (p >= Es[K - 1]) { T[i] = T_hi; return; }
-  int a = 0, b = K - 1;                // Es[a] < p < Es[b]
+  int a = 0, b = K - 1;                // Es[a] <= p < Es[b]
   while (b - a > 1) {
     const int m = (a + b) >> 1;
     if (Es[m] <= p) a = m; else b = m;
   }
   double lo = Tk[a], hi = Tk[b];
-  // start: power-law interpolation between the bracket ends
-  double t = lo * pow(hi / lo, log(p / Es[a]) / log(Es[b] / Es[a]));
-  const double* ka = kabs + (int64_t)s * nl;
-  for (int it = 0; it < 60; ++it) {
+  double t = lo * exp(log(hi / lo) * (log(p / Es[a]) / log(Es[b] / Es[a])));
+  for (int it = 0; it < 40; ++it) {
+    const double it_ = 1.0 / t;
     double e = 0.0, de = 0.0;
     for (int j = 0; j < nl; ++j) {
-      const double x = kH * nu[j] / (kKB * t);
+      const double x = xk[j] * it_;
       const double em1 = expm1(x);
-      const double B = 2.0 * kH * nu[j] * nu[j] * nu[j] / (kC * kC) / em1;
-      e += ka[j] * B * dnu[j];
-      de += ka[j] * B * dnu[j] * (x / t) * ((em1 + 1.0) / em1);
+      const double q = 1.0 / em1;          // 0 once expm1 overflows
+      const double w = W[(int64_t)j * S + s];
+      e += w * q;
+      de += w * x * q * (1.0 + q);
     }
-    e *= 4.0 * kPi;
-    de *= 4.0 * kPi;
+    de *= it_;
     const double f = e - p;
     if (f > 0.0) hi = t; else lo = t;
     double tn = de > 0.0 ? t - f / de : 0.5 * (lo + hi);
     if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-    if (fabs(tn - t) <= 1e-15 * t || hi - lo <= 1e-15 * hi) { t = tn; break; }
+    const double step = fabs(tn - t);
     t = tn;
+    if (step <= 1e-8 * t || hi - lo <= 1e-15 * hi) break;
   }
   T[i] = t;
 }
@@ -80,7 +95,7 @@ __global__ void k_mean_intensity(int64_t n_cells, int nl, double h, int L, doubl
     const int64_t c = c0 + r;
     const int j = j0 + threadIdx.x;
     if (j < nl && c < n_cells) {
-      const double vol = pow(h * ldexp(1.0, -(int)level[c]), 3.0);
+      const double vol = ldexp(h * h * h, -3 * (int)level[c]);
       J[c * nl + j] = (float)(eps * dq * tile[threadIdx.x][r] / (4.0 * kPi * vol * dnu[j]));
     }
   }
@@ -94,12 +109,14 @@ hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_tot
   const Layout& L = c->lay;
   unsigned char* B = c->tables;
   const int64_t n = d.n_cells * d.n_species;
-  k_temperatures<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(
+  const size_t lds = sizeof(double) * ((size_t)d.n_lambda * d.n_species + d.n_lambda);
+  const int use_lds = lds <= 48 * 1024;
+  k_temperatures<<<(unsigned)((n + 255) / 256), 256, use_lds ? lds : 0, s>>>(
       d.n_cells, d.n_species, d.n_lambda, d.K, d.base_size, c->src.lum / (double)n_total, d.T_lo,
-      d.T_hi, d.kind, d.kabs, reinterpret_cast<const double*>(B + L.nu),
-      reinterpret_cast<const double*>(B + L.dnu), reinterpret_cast<const double*>(B + L.Tk),
-      reinterpret_cast<const double*>(B + L.E), d.rho, reinterpret_cast<const int8_t*>(B + L.level),
-      reinterpret_cast<const unsigned long long*>(nabs), T);
+      d.T_hi, d.kind, reinterpret_cast<const double*>(B + L.Wt), reinterpret_cast<const double*>(B + L.xk),
+      reinterpret_cast<const double*>(B + L.Tk), reinterpret_cast<const double*>(B + L.E), d.rho,
+      reinterpret_cast<const int8_t*>(B + L.level), reinterpret_cast<const unsigned long long*>(nabs),
+      T, use_lds);
   return hipGetLastError();
 }
 

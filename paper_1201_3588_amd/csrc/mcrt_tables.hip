@@ -73,6 +73,18 @@ __global__ void k_emission(int nl, int S, int K, const double* __restrict__ kabs
   E[i] = 4.0 * kPi * e;
 }
 
+// Newton weights of the temperature inversion: W[j][s] = 4 pi kabs_s(j) dnu_j
+// 2 h nu_j^3 / c^2 and x_j = h nu_j / k
+__global__ void k_newton_weights(int nl, int S, const double* __restrict__ kabs,
+                                 const double* __restrict__ nu, const double* __restrict__ dnu,
+                                 double* __restrict__ W, double* __restrict__ xk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl * S) return;
+  const int j = i / S, s = i % S;
+  W[i] = 4.0 * kPi * kabs[s * nl + j] * dnu[j] * (2.0 * kH * nu[j] * nu[j] * nu[j] / (kC * kC));
+  if (s == 0) xk[j] = kH * nu[j] / kKB;
+}
+
 // R_{s,k}(j): normalised running sum over j of kabs_s(j) [B_j(T_{k+1}) - B_j(T_k)] dnu_j
 __global__ void k_rows(int nl, int S, int K, const double* __restrict__ kabs,
                        const double* __restrict__ Bt, const double* __restrict__ dnu,
@@ -163,6 +175,15 @@ __global__ void k_cells(int64_t n_cells, double h, const double* __restrict__ rh
   rho_h32[c] = (float)(rho[c] * h);
 }
 
+// base-map entry packed with the FP32 density term of an unrefined base cube
+__global__ void k_binfo(int64_t nbase, double h, const int32_t* __restrict__ base_map,
+                        const double* __restrict__ rho, int2* __restrict__ binfo) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbase) return;
+  const int32_t e = base_map[b];
+  binfo[b] = make_int2(e, e >= 0 ? __float_as_int((float)(rho[e] * h)) : 0);
+}
+
 __global__ void k_check_species(int nl, int S, const double* __restrict__ lam_um,
                                 const double* __restrict__ kabs, const double* __restrict__ ksca,
                                 const double* __restrict__ g, unsigned long long* bad) {
@@ -203,10 +224,13 @@ Layout make_layout(const mcrt_desc& d) {
   L.E = take(8 * S * K);
   L.R = take(8 * S * (K - 1) * nl);
   L.Bt = take(8 * K * nl);
+  L.Wt = take(8 * nl * S);
+  L.xk = take(8 * nl);
   L.kext32 = take(4 * nl);
   L.g32 = take(4 * nl);
   L.rho_h32 = take(4 * (uint64_t)d.n_cells);
   L.level = take((uint64_t)d.n_cells);
+  L.binfo = take(8 * (uint64_t)d.nb * d.nb * d.nb);
   L.pah_slot = take(4 * S);
   L.scratch = take(sizeof(RunScratch));
   L.total = off;
@@ -242,11 +266,14 @@ hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s) {
   k_planck_table<<<(unsigned)((nb3 + 255) / 256), 256, 0, s>>>(nl, K, D(L.nu), D(L.Tk), D(L.Bt));
   k_emission<<<(S * K + 255) / 256, 256, 0, s>>>(nl, S, K, d.kabs, D(L.Bt), D(L.dnu), D(L.E));
   k_rows<<<(S * (K - 1) + 127) / 128, 128, 0, s>>>(nl, S, K, d.kabs, D(L.Bt), D(L.dnu), D(L.R));
+  k_newton_weights<<<(nl * S + 255) / 256, 256, 0, s>>>(nl, S, d.kabs, D(L.nu), D(L.dnu), D(L.Wt), D(L.xk));
   const int64_t nbase = (int64_t)d.nb * d.nb * d.nb;
   k_levels<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(d.nb, d.max_level, d.base_map, d.nodes,
                                                             reinterpret_cast<int8_t*>(T + L.level));
   k_cells<<<(unsigned)((d.n_cells + 255) / 256), 256, 0, s>>>(d.n_cells, d.base_size, d.rho,
                                                               F(L.rho_h32));
+  k_binfo<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(nbase, d.base_size, d.base_map, d.rho,
+                                                          reinterpret_cast<int2*>(T + L.binfo));
   return hipGetLastError();
 }
 

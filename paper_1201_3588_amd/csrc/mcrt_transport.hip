@@ -23,10 +23,12 @@ struct TP {
   int nb, L, nl, S, K, n_theta, n_phi, flags, beam_on, trace_cap;
   int64_t n_cells;
   R inv_nf, qscale;
-  double h, eps;
-  R x0, y0, z0, bx, by, bz;
+  double h, h3, eps;
+  double x0, y0, z0;
+  R bx, by, bz;
   uint64_t first_id, n, seed, max_events;
   const int32_t* base_map;
+  const int2* binfo;          // FP32: {base_map entry, float bits of rho*h}
   const int32_t* nodes;
   const double* rho;
   const float* rho_h32;
@@ -34,7 +36,6 @@ struct TP {
   const float* kext32;
   const double* albedo;
   const double* gpar;
-  const float* g32;
   const double* src_cdf;
   const double* sp_cdf;
   const double* E;
@@ -56,8 +57,18 @@ __device__ __forceinline__ float rlog(float v) { return logf(v); }
 __device__ __forceinline__ double rlog(double v) { return log(v); }
 __device__ __forceinline__ float rsqrt0(float v) { return sqrtf(fmaxf(0.0f, v)); }
 __device__ __forceinline__ double rsqrt0(double v) { return sqrt(fmax(0.0, v)); }
-__device__ __forceinline__ void rsincos(float a, float* s, float* c) { sincosf(a, s, c); }
-__device__ __forceinline__ void rsincos(double a, double* s, double* c) { sincos(a, s, c); }
+// sin and cos of 2 pi u for u in (0, 1]: FP32 uses the hardware sine/cosine,
+// whose argument is in revolutions (no range reduction needed here); FP64
+// uses the library sincos.
+__device__ __forceinline__ void sincos_rev(double u, float* s, float* c) {
+  float r = (float)u;
+  r = r > 0.5f ? r - 1.0f : r;            // exact: u is a multiple of 2^-24
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void sincos_rev(double u, double* s, double* c) {
+  sincos(2.0 * kPi * u, s, c);
+}
 __device__ __forceinline__ float rfloor(float v) { return floorf(v); }
 __device__ __forceinline__ double rfloor(double v) { return floor(v); }
 __device__ __forceinline__ float rrint(float v) { return rintf(v); }
@@ -73,21 +84,35 @@ __device__ __forceinline__ double hg_mu(double g, double u) {
   return fmin(1.0, fmax(-1.0, mu));
 }
 
-// leaf holding finest-level point F; -1 outside the grid
-__device__ __forceinline__ int locate(const int32_t* __restrict__ base_map,
-                                      const int32_t* __restrict__ nodes, int nb, int L,
-                                      int F0, int F1, int F2, int& lev, int& lo0, int& lo1,
-                                      int& lo2) {
+// Leaf holding finest-level point F (-1 outside the grid) and its density
+// term: rho*h (FP32 path, packed with the base-map entry for unrefined base
+// cubes so the common case is one 8-byte load) or rho (FP64 path).
+template <typename R>
+__device__ __forceinline__ int locate(const TP<R>& P, int F0, int F1, int F2, int& lev, int& lo0,
+                                      int& lo1, int& lo2, R& dens) {
+  const int L = P.L, nb = P.nb;
   const unsigned ext = (unsigned)nb << L;
   if ((unsigned)F0 >= ext || (unsigned)F1 >= ext || (unsigned)F2 >= ext) return -1;
-  int e = base_map[(F0 >> L) + nb * ((F1 >> L) + nb * (F2 >> L))];
-  int l = 0;
-  while (e < 0) {
-    ++l;
-    const int sh = L - l;
-    const int o = ((F0 >> sh) & 1) | (((F1 >> sh) & 1) << 1) | (((F2 >> sh) & 1) << 2);
-    e = nodes[(-e - 1) * 8 + o];
+  const int b = (F0 >> L) + nb * ((F1 >> L) + nb * (F2 >> L));
+  int e;
+  if (sizeof(R) == 4) {
+    const int2 bi = P.binfo[b];
+    e = bi.x;
+    dens = (R)__int_as_float(bi.y);
+  } else {
+    e = P.base_map[b];
   }
+  int l = 0;
+  if (e < 0) {
+    do {
+      ++l;
+      const int sh = L - l;
+      const int o = ((F0 >> sh) & 1) | (((F1 >> sh) & 1) << 1) | (((F2 >> sh) & 1) << 2);
+      e = P.nodes[(-e - 1) * 8 + o];
+    } while (e < 0);
+    if (sizeof(R) == 4) dens = (R)P.rho_h32[e];
+  }
+  if (sizeof(R) == 8) dens = (R)P.rho[e];
   lev = l;
   const int sh = L - l;
   lo0 = (F0 >> sh) << sh;
@@ -107,9 +132,8 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 }
 
 template <typename R>
-__device__ __forceinline__ void record(const TP<R>& P, uint64_t k, int type, int cell, int j, R x0,
-                                       R x1, R x2, R d0, R d1, R d2, R tau) {
-  if (!P.trace) return;
+__device__ __forceinline__ void record(const TP<R>& P, uint64_t k, int type, int cell, int j,
+                                       double x0, double x1, double x2, R d0, R d1, R d2, R tau) {
   const int n = P.trace_len[k];
   if (n >= P.trace_cap) return;
   mcrt_trace_rec* r = P.trace + (int64_t)k * P.trace_cap + n;
@@ -131,12 +155,18 @@ __device__ __forceinline__ void escape_tally(const TP<R>& P, R d0, R d1, R d2, i
   atomicAdd(&P.sed[((int64_t)bt * P.n_phi + bp) * P.nl + j], 1ull);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
+// Packet state: current leaf (integer lower corner lo* in finest units, level
+// lev) and the position u* relative to that corner in base-cube units, so that
+// rounding scales with the cell, not with the distance from the grid origin;
+// crossing into a neighbour re-bases u by an exact integer offset.
+template <typename R, bool TRACE>
+__global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
+  __shared__ unsigned int s_cnt[12];
   double* s_alb = smem;
   double* s_src = s_alb + P.nl;
   R* s_kext = reinterpret_cast<R*>(s_src + P.nl);
+  if (threadIdx.x < 12) s_cnt[threadIdx.x] = 0u;
   for (int j = threadIdx.x; j < P.nl; j += blockDim.x) {
     s_alb[j] = P.albedo[j];
     s_src[j] = P.src_cdf[j];
@@ -144,7 +174,6 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
   }
   __syncthreads();
 
-  const bool f64 = sizeof(R) == 8;
   const int lane = __lane_id();
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const int L = P.L;
@@ -154,11 +183,13 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
 
   bool alive = false, exhausted = false;
   uint64_t pid = 0, kidx = 0;
-  uint64_t events = 0;
-  R x0 = 0, x1 = 0, x2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0;
+  uint32_t events = 0;
+  R u0 = 0, u1 = 0, u2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0, dens = 0;
   int j = 0, cell = 0, lev = 0, lo0 = 0, lo1 = 0, lo2 = 0;
-  unsigned long long c_launch = 0, c_esc = 0, c_kill = 0, c_term = 0, c_scat = 0, c_abs = 0,
-                     c_cross = 0, c_tlo = 0, c_thi = 0, c_pah = 0, c_zero = 0, c_jseg = 0;
+  // frequent counters in registers, rare ones in LDS
+  uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
+  auto bump = [&](int k) { atomicAdd(&s_cnt[k], 1u); };
+  auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
   for (;;) {
     if (!exhausted) {
@@ -174,7 +205,7 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
           const uint64_t k = base + (uint64_t)__popcll(dead & lt_mask);
           if (k < P.n) {
             // launch (event slot 0): bin from the source CDF, direction, optical depth
-            kidx = k;
+            if (TRACE) kidx = k;
             pid = P.first_id + k;
             events = 0;
             uint32_t w[4];
@@ -185,20 +216,23 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
               const R mu = (R)(2.0 * u24(w[1]) - 1.0);
               const R st = rsqrt0(R(1) - mu * mu);
               R sp, cp;
-              rsincos((R)(2.0 * kPi * u24(w[2])), &sp, &cp);
+              sincos_rev(u24(w[2]), &sp, &cp);
               d0 = st * cp; d1 = st * sp; d2 = mu;
             }
             tau = -rlog((R)u24(w[3]));
-            x0 = P.x0; x1 = P.y0; x2 = P.z0;
-            const R nf = (R)(1 << L);
-            cell = locate(P.base_map, P.nodes, P.nb, L, (int)rfloor(x0 * nf), (int)rfloor(x1 * nf),
-                          (int)rfloor(x2 * nf), lev, lo0, lo1, lo2);
-            c_launch++;
-            record(P, kidx, 0, cell, j, x0, x1, x2, d0, d1, d2, tau);
+            const double nf = (double)(1 << L);
+            cell = locate(P, (int)floor(P.x0 * nf), (int)floor(P.y0 * nf), (int)floor(P.z0 * nf),
+                          lev, lo0, lo1, lo2, dens);
+            const double ifn = (double)inv_nf;
+            u0 = (R)(P.x0 - (double)lo0 * ifn);
+            u1 = (R)(P.y0 - (double)lo1 * ifn);
+            u2 = (R)(P.z0 - (double)lo2 * ifn);
+            bump(0);
+            if (TRACE) record(P, kidx, 0, cell, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
             if (cell < 0) {
-              c_esc++;
+              bump(1);
               escape_tally(P, d0, d1, d2, j);
-              record(P, kidx, 4, -1, j, x0, x1, x2, d0, d1, d2, tau);
+              if (TRACE) record(P, kidx, 4, -1, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
             } else {
               alive = true;
             }
@@ -218,57 +252,46 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
     R tex = (R)INFINITY;
     int ax = -1;
     {
-      const R b0 = (R)lo0 * inv_nf, b1 = (R)lo1 * inv_nf, b2 = (R)lo2 * inv_nf;
       R t;
       if (d0 != R(0)) {
-        t = d0 > R(0) ? (b0 + side - x0) / d0 : (b0 - x0) / d0;
+        t = (d0 > R(0) ? side - u0 : -u0) / d0;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 0; }
       }
       if (d1 != R(0)) {
-        t = d1 > R(0) ? (b1 + side - x1) / d1 : (b1 - x1) / d1;
+        t = (d1 > R(0) ? side - u1 : -u1) / d1;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 1; }
       }
       if (d2 != R(0)) {
-        t = d2 > R(0) ? (b2 + side - x2) / d2 : (b2 - x2) / d2;
+        t = (d2 > R(0) ? side - u2 : -u2) / d2;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 2; }
       }
     }
-    R alpha;
-    bool dusty;
-    if (f64) {
-      const double r = P.rho[cell];
-      alpha = (R)(r * (double)s_kext[j] * P.h);
-      dusty = r > 0.0;
-    } else {
-      const float r = P.rho_h32[cell];
-      alpha = (R)(r * (float)s_kext[j]);
-      dusty = r > 0.0f;
-    }
+    const bool dusty = dens > R(0);
+    const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)s_kext[j] * P.h)
+                                   : (R)(dens * s_kext[j]);
 
     if (alpha > R(0) && tau < alpha * tex) {
       // ---- interaction inside this cell
       const R s = tau / alpha;
-      x0 += s * d0; x1 += s * d1; x2 += s * d2;
+      u0 += s * d0; u1 += s * d1; u2 += s * d2;
       if (tally_j && dusty) {
         atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], (unsigned long long)rrint(s * P.qscale));
         c_jseg++;
       }
       events += 1;
-      if (events > P.max_events) {
-        c_kill++;
+      if ((uint64_t)events > P.max_events) {
+        bump(2);
         alive = false;
-        record(P, kidx, 5, cell, j, x0, x1, x2, d0, d1, d2, tau);
+        if (TRACE) record(P, kidx, 5, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
         continue;
       }
-      uint32_t w[4], v[4];
-      philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), (uint32_t)events, 0u, key0, key1, w);
-      philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), (uint32_t)events, 1u, key0, key1, v);
-      const double phi = 2.0 * kPi * u24(w[2]);
+      uint32_t w[4];
+      philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 0u, key0, key1, w);
       R sp, cp;
-      rsincos((R)phi, &sp, &cp);
+      sincos_rev(u24(w[2]), &sp, &cp);
       if (u24(w[0]) <= s_alb[j]) {
         // scattering: new direction from the phase function
         const R mu = (R)hg_mu(P.gpar[j], u24(w[1]));
@@ -282,29 +305,31 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
           const R n2 = -st * cp * tmp + d2 * mu;
           d0 = n0; d1 = n1; d2 = n2;
         }
-        c_scat++;
+        bump(4);
         tau = -rlog((R)u24(w[3]));
-        record(P, kidx, 2, cell, j, x0, x1, x2, d0, d1, d2, tau);
+        if (TRACE) record(P, kidx, 2, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
       } else {
         // absorption: species, tally, new frequency, isotropic re-emission
+        uint32_t v[4];
+        philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 1u, key0, key1, v);
         const int sp_i = cdf_search(P.sp_cdf + (int64_t)j * P.S, P.S, u24(w[1]));
         unsigned long long before = atomicAdd(&P.nabs[(int64_t)cell * P.S + sp_i], 1ull);
-        c_abs++;
+        bump(5);
         if (P.flags & MCRT_FLAG_FROZEN_T) before = P.frozen[(int64_t)cell * P.S + sp_i];
         if (P.flags & MCRT_FLAG_KILL_ON_ABSORB) {
-          c_term++;
+          bump(3);
           alive = false;
-          record(P, kidx, 3, cell, j, x0, x1, x2, d0, d1, d2, tau);
+          if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
           continue;
         }
         if (P.kind[sp_i] == 0) {
-          const double vol = pow(P.h * ldexp(1.0, -lev), 3.0);
+          const double vol = ldexp(P.h3, -3 * lev);
           const double pw = (double)before * P.eps / (P.rho[cell] * vol);
           const double* E = P.E + (int64_t)sp_i * P.K;
           int kb;
           if (pw < E[0]) {
             kb = 0;
-            c_tlo++;
+            bump(7);
           } else {
             int a = 0, b = P.K - 1;
             if (E[P.K - 1] <= pw) a = P.K - 1;
@@ -314,19 +339,19 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
                 if (E[m] <= pw) a = m; else b = m;
               }
             kb = a;
-            if (kb > P.K - 2) { kb = P.K - 2; c_thi++; }
+            if (kb > P.K - 2) { kb = P.K - 2; bump(8); }
           }
           j = cdf_search(P.Rrows + ((int64_t)sp_i * (P.K - 1) + kb) * P.nl, P.nl, u24(v[0]));
         } else {
           const double* row = P.pah_rows + ((int64_t)P.pah_slot[sp_i] * P.n_cells + cell) * P.nl;
           j = cdf_search(row, P.nl, u24(v[0]));
-          c_pah++;
+          bump(9);
         }
         const R mu = (R)(2.0 * u24(v[1]) - 1.0);
         const R st = rsqrt0(R(1) - mu * mu);
         d0 = st * cp; d1 = st * sp; d2 = mu;
         tau = -rlog((R)u24(w[3]));
-        record(P, kidx, 3, cell, j, x0, x1, x2, d0, d1, d2, tau);
+        if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
       }
       continue;
     }
@@ -339,47 +364,55 @@ __global__ void __launch_bounds__(256) k_transport(const TP<R> P) {
     }
     c_cross++;
     if (tex == R(0)) c_zero++;
-    x0 += tex * d0; x1 += tex * d1; x2 += tex * d2;
+    u0 += tex * d0; u1 += tex * d1; u2 += tex * d2;
     const R nf = (R)(1 << L);
     int G0, G1, G2;
     {
-      const int f0 = (int)rfloor(x0 * nf), f1 = (int)rfloor(x1 * nf), f2 = (int)rfloor(x2 * nf);
-      G0 = f0 < lo0 ? lo0 : (f0 > lo0 + span - 1 ? lo0 + span - 1 : f0);
-      G1 = f1 < lo1 ? lo1 : (f1 > lo1 + span - 1 ? lo1 + span - 1 : f1);
-      G2 = f2 < lo2 ? lo2 : (f2 > lo2 + span - 1 ? lo2 + span - 1 : f2);
+      const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
+      G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
+      G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
+      G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
     }
     if (ax == 0) {
-      const int face = d0 > R(0) ? lo0 + span : lo0;
-      x0 = (R)face * inv_nf;
+      u0 = d0 > R(0) ? side : R(0);
       G0 = d0 > R(0) ? lo0 + span : lo0 - 1;
     } else if (ax == 1) {
-      const int face = d1 > R(0) ? lo1 + span : lo1;
-      x1 = (R)face * inv_nf;
+      u1 = d1 > R(0) ? side : R(0);
       G1 = d1 > R(0) ? lo1 + span : lo1 - 1;
     } else {
-      const int face = d2 > R(0) ? lo2 + span : lo2;
-      x2 = (R)face * inv_nf;
+      u2 = d2 > R(0) ? side : R(0);
       G2 = d2 > R(0) ? lo2 + span : lo2 - 1;
     }
-    cell = locate(P.base_map, P.nodes, P.nb, L, G0, G1, G2, lev, lo0, lo1, lo2);
+    const int o0 = lo0, o1 = lo1, o2 = lo2;
+    cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
     if (cell < 0) {
-      c_esc++;
+      bump(1);
       alive = false;
       escape_tally(P, d0, d1, d2, j);
-      record(P, kidx, 4, -1, j, x0, x1, x2, d0, d1, d2, tau);
+      if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
     } else {
-      record(P, kidx, 1, cell, j, x0, x1, x2, d0, d1, d2, tau);
+      // re-base the local position on the new leaf (exact integer offsets)
+      u0 += (R)(o0 - lo0) * inv_nf;
+      u1 += (R)(o1 - lo1) * inv_nf;
+      u2 += (R)(o2 - lo2) * inv_nf;
+      if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
     }
   }
 
-  // ---- counters: one atomic per wave per slot
-  unsigned long long vals[12] = {c_launch, c_esc, c_kill, c_term, c_scat, c_abs,
-                                 c_cross, c_tlo, c_thi, c_pah, c_zero, c_jseg};
-#pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const unsigned long long s = wave_sum(vals[i]);
-    if (lane == 0 && s) atomicAdd(&P.counters[i], s);
+  // ---- counters: registers reduced per wave, LDS per block
+  {
+    const unsigned long long s6 = wave_sum((unsigned long long)c_cross);
+    const unsigned long long s10 = wave_sum((unsigned long long)c_zero);
+    const unsigned long long s11 = wave_sum((unsigned long long)c_jseg);
+    if (lane == 0) {
+      if (s6) atomicAdd(&P.counters[6], s6);
+      if (s10) atomicAdd(&P.counters[10], s10);
+      if (s11) atomicAdd(&P.counters[11], s11);
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < 12 && s_cnt[threadIdx.x])
+    atomicAdd(&P.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -401,19 +434,20 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   P.inv_nf = (R)ldexp(1.0, -d.max_level);
   P.qscale = (R)ldexp(1.0, d.max_level + 16);
   P.h = d.base_size;
+  P.h3 = d.base_size * d.base_size * d.base_size;
   P.eps = c->src.lum / (double)o.n_total;
-  P.x0 = (R)((c->src.pos[0] - d.box_min[0]) / d.base_size);
-  P.y0 = (R)((c->src.pos[1] - d.box_min[1]) / d.base_size);
-  P.z0 = (R)((c->src.pos[2] - d.box_min[2]) / d.base_size);
+  P.x0 = (c->src.pos[0] - d.box_min[0]) / d.base_size;
+  P.y0 = (c->src.pos[1] - d.box_min[1]) / d.base_size;
+  P.z0 = (c->src.pos[2] - d.box_min[2]) / d.base_size;
   P.bx = (R)c->src.beam[0]; P.by = (R)c->src.beam[1]; P.bz = (R)c->src.beam[2];
   P.first_id = first_id; P.n = n; P.seed = o.seed; P.max_events = o.max_events;
   P.base_map = d.base_map; P.nodes = d.nodes; P.rho = d.rho;
+  P.binfo = reinterpret_cast<const int2*>(T + L.binfo);
   P.rho_h32 = reinterpret_cast<const float*>(T + L.rho_h32);
   P.kext64 = reinterpret_cast<const double*>(T + L.kext);
   P.kext32 = reinterpret_cast<const float*>(T + L.kext32);
   P.albedo = reinterpret_cast<const double*>(T + L.albedo);
   P.gpar = reinterpret_cast<const double*>(T + L.gpar);
-  P.g32 = reinterpret_cast<const float*>(T + L.g32);
   P.src_cdf = reinterpret_cast<const double*>(T + L.src_cdf);
   P.sp_cdf = reinterpret_cast<const double*>(T + L.sp_cdf);
   P.E = reinterpret_cast<const double*>(T + L.E);
@@ -432,11 +466,19 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   P.trace_len = o.trace_len;
   k_zero_u64<<<1, 64, 0, s>>>(&scr->work_counter, 1);
   const uint64_t want = (n + 255) / 256;
-  uint64_t blocks = o.grid_blocks > 0 ? (uint64_t)o.grid_blocks : (uint64_t)c->n_cu * 8;
+  const size_t lds = (size_t)d.n_lambda * (2 * sizeof(double) + sizeof(R));
+  // persistent grid: as many blocks as can be resident at once
+  int per_cu = 0;
+  if (o.trace)
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, true>, 256, lds);
+  else
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, false>, 256, lds);
+  if (per_cu < 1) per_cu = 1;
+  uint64_t blocks = o.grid_blocks > 0 ? (uint64_t)o.grid_blocks : (uint64_t)c->n_cu * per_cu;
   if (blocks > want) blocks = want;
   if (blocks < 1) blocks = 1;
-  const size_t lds = (size_t)d.n_lambda * (2 * sizeof(double) + sizeof(R));
-  k_transport<R><<<(unsigned)blocks, 256, lds, s>>>(P);
+  if (o.trace) k_transport<R, true><<<(unsigned)blocks, 256, lds, s>>>(P);
+  else k_transport<R, false><<<(unsigned)blocks, 256, lds, s>>>(P);
   return hipGetLastError();
 }
 

@@ -55,8 +55,8 @@ class RunOpts(C.Structure):
 
 class TableLayout(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("nu", "dnu", "src_cdf", "kext", "albedo", "gpar", "sp_cdf",
-                                          "Tk", "E", "R", "Bt", "kext32", "g32", "rho_h32", "level",
-                                          "pah_slot", "scratch", "total")]
+                                          "Tk", "E", "R", "Bt", "Wt", "xk", "kext32", "g32", "rho_h32", "level",
+                                          "binfo", "pah_slot", "scratch", "total")]
 
 
 TRACE_DTYPE = np.dtype([("type", np.int32), ("cell", np.int32), ("j", np.int32),

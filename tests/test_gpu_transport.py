@@ -57,16 +57,19 @@ def test_tables_match_oracle():
 
 
 def _compare_traces(gt, ot, pos_tol, extent):
-    """Number of packets whose (type, cell, bin) sequences agree; for those,
-    positions must agree to pos_tol relative to the grid extent (FP32 rounding
-    accumulates along a path), directions to 10 pos_tol."""
+    """Number of packets whose (type, cell, bin) sequences agree.  For those,
+    the position at every event must agree to pos_tol relative to the larger of
+    the grid extent and the path length travelled so far (rounding accumulates
+    along a path), directions and optical depths to 10 pos_tol."""
     same = 0
     for a, b in zip(gt, ot):
         if len(a) != len(b) or np.any(a["type"] != b["type"]) or np.any(a["cell"] != b["cell"]) \
                 or np.any(a["j"] != b["j"]):
             continue
         same += 1
-        assert np.max(np.abs(a["x"] - b["x"])) / extent < pos_tol
+        path = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(b["x"], axis=0), axis=1))])
+        err = np.linalg.norm(a["x"] - b["x"], axis=1) / np.maximum(extent, path)
+        assert np.max(err) < pos_tol
         assert np.max(np.abs(a["d"] - b["d"])) < pos_tol * 10
         assert np.max(np.abs(a["tau"] - b["tau"]) / np.maximum(1.0, np.abs(b["tau"]))) < pos_tol * 10
     return same
@@ -166,18 +169,19 @@ def batch_runs(run, B):
     return rows
 
 
-def statistical_check(w, B=32, seed_gpu=None, seed_orc=None):
+def statistical_check(w, B=32, seed_gpu=None, seed_orc=None, frozen=None):
     nb_ = w.n_packets // B
     e = engine(w)
     tal = e.new_tallies(tally_j=w.tally_j)
     sg = seed_gpu if seed_gpu is not None else w.seed
     so = seed_orc if seed_orc is not None else 1000 + w.seed
+    flags = (mcrt.FLAG_TALLY_J if w.tally_j else 0) | (mcrt.FLAG_FROZEN_T if frozen is not None else 0)
 
     def gpu_run(b):
-        e.run(tal, b * nb_, nb_, w.n_packets, sg)
+        e.run(tal, b * nb_, nb_, w.n_packets, sg, frozen_nabs=frozen, flags=flags)
         return host(tal)
 
-    s = oracle.Session(w, seed=so, n_threads=8)
+    s = oracle.Session(w, seed=so, n_threads=8, frozen_nabs=frozen)
     acc = s.new_accumulator()
 
     def orc_run(b):
@@ -194,13 +198,21 @@ def statistical_check(w, B=32, seed_gpu=None, seed_orc=None):
     return res
 
 
-@pytest.mark.parametrize("name", ["c1", "disk"])
+@pytest.mark.parametrize("name", ["c1", "disk_frozen", "disk_frozen_f64"])
 def test_statistical_parity(name):
+    """c1: the full method (running absorption counts) on the sphere.
+    disk: FP32 and FP64 transport with the temperature bracket taken from a
+    frozen absorption field, so the comparison does not depend on the order in
+    which concurrently flying packets update the counts."""
+    frozen = None
     if name == "c1":
         w = synth.c1_sphere(n_packets=320000)
     else:
         w = synth.small_disk(n_packets=96000, nl=40, n_sizes=2, nb=16)
-    res = statistical_check(w)
+        if name.endswith("f64"):
+            w.precision = "f64"
+        frozen = oracle.Session(w, n_threads=8).transport()["nabs"]
+    res = statistical_check(w, frozen=frozen)
     for k, (frac, zmax, chi2, n) in res.items():
         assert n >= 5, (k, n)
         assert frac <= 0.02 and zmax < 6.0, (k, frac, zmax, chi2, n)
