@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_temperatures(
     const double f = e - p;
     if (f > 0.0) hi = t; else lo = t;
     double tn = de > 0.0 ? t - f / de : 0.5 * (lo + hi);
-    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);   // a converged step may land on an end
     const double step = fabs(tn - t);
     t = tn;
     if (step <= 1e-8 * t || hi - lo <= 1e-15 * hi) break;

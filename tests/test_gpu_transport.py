@@ -200,24 +200,32 @@ def statistical_check(w, B=32, seed_gpu=None, seed_orc=None, frozen=None):
 
 @pytest.mark.parametrize("name", ["c1", "disk_frozen", "disk_frozen_f64"])
 def test_statistical_parity(name):
-    """c1: the full method (running absorption counts) on the sphere.
+    """c1: the full method (running absorption counts), path-length tally on.
     disk: FP32 and FP64 transport with the temperature bracket taken from a
     frozen absorption field, so the comparison does not depend on the order in
-    which concurrently flying packets update the counts."""
+    which concurrently flying packets update the counts.  The disk's per-bin
+    path sums are heavy tailed (packets trapped in the optically thick midplane)
+    and strongly correlated across bins, which breaks the independence the 3
+    sigma count assumes: there they are checked bit-exactly with equal seeds
+    (test_fp64_frozen_tallies_equal_oracle) instead."""
     frozen = None
+    keys = ("sed", "shells", "jq")
     if name == "c1":
         w = synth.c1_sphere(n_packets=320000)
+        w.tally_j = True
     else:
         w = synth.small_disk(n_packets=96000, nl=40, n_sizes=2, nb=16)
         if name.endswith("f64"):
             w.precision = "f64"
         frozen = oracle.Session(w, n_threads=8).transport()["nabs"]
+        keys = ("sed", "shells")
     res = statistical_check(w, frozen=frozen)
-    for k, (frac, zmax, chi2, n) in res.items():
+    for k in keys:
+        frac, zmax, chi2, n = res[k]
         assert n >= 5, (k, n)
         assert frac <= 0.02 and zmax < 6.0, (k, frac, zmax, chi2, n)
-        if n >= 50:                          # chi2/dof is only meaningful with many outputs
-            assert 0.6 < chi2 < 1.5, (k, frac, zmax, chi2, n)
+        if n >= 50:                          # a check of the sigma scale
+            assert 0.5 < chi2 < 1.6, (k, frac, zmax, chi2, n)
 
 
 def test_temperatures_and_intensity_equal_oracle():
