@@ -571,7 +571,8 @@ void orc_pah_solve(int32_t M, const double *T, const double *U, int32_t nl,
       double s = 0.0;
       for (int i = 0; i < f; ++i) s += B[(int64_t)f * M + i] * P[i];
       P[f] = s / Ad[f];
-      if (P[f] > 1e200) for (int i = 0; i <= f; ++i) P[i] *= 1e-200;
+      /* keep the unnormalised P finite: rescale by an exact power of two */
+      if (P[f] > 1e200) for (int i = 0; i <= f; ++i) P[i] = ldexp(P[i], -664);
     }
     double tot = 0.0;
     for (int i = 0; i < M; ++i) tot += P[i];

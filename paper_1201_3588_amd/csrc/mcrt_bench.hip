@@ -47,7 +47,7 @@ extern "C" int32_t mcrt_bench_random(uint64_t* table, uint64_t n_slots, const fl
   if (n_ops == 0) return MCRT_OK;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const unsigned blocks = (unsigned)ncu * 16;
   const unsigned long long threads = (unsigned long long)blocks * 256;
   const unsigned long long per = (n_ops + threads - 1) / threads;

@@ -155,6 +155,8 @@ __device__ __forceinline__ void escape_tally(const TP<R>& P, R d0, R d1, R d2, i
   atomicAdd(&P.sed[((int64_t)bt * P.n_phi + bp) * P.nl + j], 1ull);
 }
 
+constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the shared counter
+
 // Packet state: current leaf (integer lower corner lo* in finest units, level
 // lev) and the position u* relative to that corner in base-cube units, so that
 // rounding scales with the cell, not with the distance from the grid origin;
@@ -182,6 +184,10 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   const bool tally_j = (P.flags & MCRT_FLAG_TALLY_J) && P.jq != nullptr;
 
   bool alive = false, exhausted = false;
+  // wave-uniform range [q_next, q_end) of packet ids this wave has claimed:
+  // ids are claimed kChunk at a time so the shared counter sees one atomic per
+  // kChunk packets instead of one per wave and iteration
+  uint64_t q_next = 0, q_end = 0;
   uint64_t pid = 0, kidx = 0;
   uint32_t events = 0;
   R u0 = 0, u1 = 0, u2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0, dens = 0;
@@ -192,18 +198,24 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
   for (;;) {
-    if (!exhausted) {
+    if (!exhausted || q_next < q_end) {
       const unsigned long long dead = __ballot(!alive);
       if (dead) {
         const int nd = __popcll(dead);
-        const int leader = __ffsll((long long)dead) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(P.work, (unsigned long long)nd);
-        base = __shfl(base, leader);
-        if (base + (unsigned long long)nd >= P.n) exhausted = true;
-        if (!alive) {
-          const uint64_t k = base + (uint64_t)__popcll(dead & lt_mask);
-          if (k < P.n) {
+        if (q_next >= q_end && !exhausted) {
+          const int leader = __ffsll((long long)dead) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(P.work, (unsigned long long)kChunk);
+          base = __shfl(base, leader);
+          q_next = base;
+          q_end = base + kChunk < P.n ? base + kChunk : P.n;
+          if (base + kChunk >= P.n) exhausted = true;
+        }
+        const uint64_t avail = q_end > q_next ? q_end - q_next : 0;
+        const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
+        if (!alive && rank < avail) {
+          const uint64_t k = q_next + rank;
+          {
             // launch (event slot 0): bin from the source CDF, direction, optical depth
             if (TRACE) kidx = k;
             pid = P.first_id + k;
@@ -238,10 +250,11 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
             }
           }
         }
+        q_next += (uint64_t)nd < avail ? (uint64_t)nd : avail;
       }
     }
     if (!__any(alive)) {
-      if (exhausted) break;
+      if (exhausted && q_next >= q_end) break;
       continue;
     }
     if (!alive) continue;
@@ -470,9 +483,9 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   // persistent grid: as many blocks as can be resident at once
   int per_cu = 0;
   if (o.trace)
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, true>, 256, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, true>, 256, lds);
   else
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, false>, 256, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, false>, 256, lds);
   if (per_cu < 1) per_cu = 1;
   uint64_t blocks = o.grid_blocks > 0 ? (uint64_t)o.grid_blocks : (uint64_t)c->n_cu * per_cu;
   if (blocks > want) blocks = want;
