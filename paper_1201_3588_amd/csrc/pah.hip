@@ -1,0 +1,465 @@
+// Exact steady-state temperature distribution P(T) of transiently heated PAHs
+// and their band/continuum emission, per cell, in FP64 (paper Sec. 1, Sec. 4,
+// Fig. 3: P(T) depends on the strength and the hardness of the field).
+//
+// P_f A_{f-1,f} = sum_{i<f} P_i B_{f,i},  B_{f,i} = sum_{k>=f} A_{k,i}.
+// Forming B_{f,i} by running subtraction loses the hot tail to cancellation
+// and storing it costs M^2/2 doubles per cell, so the f range is cut into
+// blocks of kBk and every sum is kept positive:
+//   pass 1 (top-down): D^b_i = sum_{k >= end of block b} A_{k,i}, per block,
+//                      into a per-workgroup global scratch;
+//   pass 2 (bottom-up, block b = [f_b, e_b)):
+//     in_k  = sum_{i<f_b} P_i A_{k,i}  (k in the block),  Sin_f = sum_{k>=f} in_k
+//     C0    = sum_{i<f_b} P_i D^b_i
+//     Bin[f][i] = sum_{k=f}^{e_b-1} A_{k,i}  (f_b <= i < f < e_b)
+//     P_f = (C0 + Sin_f + sum_{i=f_b}^{f-1} P_i (D^b_i + Bin[f][i])) / A_{f-1,f}.
+// One 256-thread workgroup per cell (persistent grid); the in-block recurrence
+// runs on one wave with shuffle reductions.
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "mcrt_internal.h"
+#include "pah.h"
+
+using namespace mcrt;
+
+namespace {
+
+constexpr int kBk = 32;
+constexpr int kThreads = 256;
+
+struct PahLayout {
+  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, adown, em, total;
+};
+
+PahLayout pah_layout(const pah_desc& d) {
+  PahLayout L{};
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) {
+    const uint64_t o = off;
+    off += (b + 255) & ~uint64_t(255);
+    return o;
+  };
+  const uint64_t M = d.M, nl = d.n_lambda, no = (uint64_t)d.n_bands + nl;
+  L.nu = take(8 * nl);
+  L.dnu = take(8 * nl);
+  L.ed = take(8 * (nl + 1));
+  L.Elo = take(8 * nl);
+  L.Ehi = take(8 * nl);
+  L.Ue = take(8 * (M + 1));
+  L.wup = take(8 * M * M);
+  L.jb = take(2 * M * M);
+  L.wtop = take(8 * M * nl);
+  L.adown = take(8 * M);
+  L.em = take(8 * M * no);
+  L.total = off;
+  return L;
+}
+
+// wavelength bins: centres, widths, ascending edges (micron), photon-energy edges
+__global__ void k_pah_bins(int nl, int M, const double* __restrict__ lam, const double* __restrict__ U,
+                           double* nu, double* dnu, double* ed, double* Elo, double* Ehi, double* Ue) {
+  for (int j = threadIdx.x; j <= nl; j += blockDim.x) {
+    double e;
+    if (j == 0) e = lam[0] * lam[0] / sqrt(lam[0] * lam[1]);
+    else if (j == nl) e = lam[nl - 1] * lam[nl - 1] / sqrt(lam[nl - 2] * lam[nl - 1]);
+    else e = sqrt(lam[j - 1] * lam[j]);
+    ed[j] = e;
+  }
+  for (int i = threadIdx.x; i <= M; i += blockDim.x) {
+    if (i == 0) Ue[0] = U[0];
+    else if (i == M) Ue[M] = U[M - 1] + 0.5 * (U[M - 1] - U[M - 2]);
+    else Ue[i] = 0.5 * (U[i - 1] + U[i]);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
+    nu[j] = kC / (lam[j] * 1e-4);
+    dnu[j] = kC / (ed[j] * 1e-4) - kC / (ed[j + 1] * 1e-4);
+    Ehi[j] = kH * kC / (ed[j] * 1e-4);
+    Elo[j] = kH * kC / (ed[j + 1] * 1e-4);
+  }
+}
+
+// heating weight and wavelength bin of every jump i -> k (k < M-1)
+__global__ void k_pah_up(int M, int nl, const double* __restrict__ U, const double* __restrict__ Ue,
+                         const double* __restrict__ ed, double* __restrict__ wup,
+                         uint16_t* __restrict__ jb) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * M) return;
+  const int k = (int)(q / M), i = (int)(q % M);
+  double w = 0.0;
+  int bin = 0;
+  if (i < k && k < M - 1) {
+    const double E = U[k] - U[i];
+    const double lam = kH * kC / E * 1e4;   // micron
+    if (lam >= ed[0] && lam < ed[nl]) {
+      int lo = 0, hi = nl - 1;              // largest j with ed[j] <= lam
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ed[mid] <= lam) lo = mid; else hi = mid - 1;
+      }
+      bin = lo;
+      w = (Ue[k + 1] - Ue[k]) * 4.0 * kPi / (kH * E);
+    }
+  }
+  wup[q] = w;
+  jb[q] = (uint16_t)bin;
+}
+
+// top bin: integral over every jump at or above its lower edge
+__global__ void k_pah_top(int M, int nl, const double* __restrict__ U, const double* __restrict__ Ue,
+                          const double* __restrict__ Elo, const double* __restrict__ Ehi,
+                          double* __restrict__ wtop) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * nl) return;
+  const int i = (int)(q / nl), j = (int)(q % nl);
+  double w = 0.0;
+  if (i < M - 1) {
+    const double Emin = Ue[M - 1] - U[i];
+    const double a = Elo[j] > Emin ? Elo[j] : Emin;
+    if (Ehi[j] > a) w = 4.0 * kPi / kH * log(Ehi[j] / a);
+  }
+  wtop[q] = w;
+}
+
+// cooling rates and emission table
+__global__ void k_pah_em(int M, int nl, int nbd, const double* __restrict__ T,
+                         const double* __restrict__ U, const double* __restrict__ nu,
+                         const double* __restrict__ dnu, const double* __restrict__ cabs,
+                         const double* __restrict__ cband, const double* __restrict__ ccont,
+                         double* __restrict__ adown, double* __restrict__ em) {
+  const int i = blockIdx.x;
+  const int no = nbd + nl;
+  __shared__ double red[256];
+  double pe = 0.0;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
+    const double B = planck_nu(nu[j], T[i]);
+    pe += cabs[j] * B * dnu[j];
+    em[(int64_t)i * no + nbd + j] = 4.0 * kPi * ccont[j] * B * dnu[j];
+  }
+  red[threadIdx.x] = pe;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) adown[i] = i > 0 ? 4.0 * kPi * red[0] / (U[i] - U[i - 1]) : 0.0;
+  for (int b = threadIdx.x; b < nbd; b += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < nl; ++j) s += cband[(int64_t)b * nl + j] * planck_nu(nu[j], T[i]) * dnu[j];
+    em[(int64_t)i * no + b] = 4.0 * kPi * s;
+  }
+}
+
+struct SolveP {
+  int M, nl, nbd, nblk, j_f32;
+  int64_t n;
+  const void* J;
+  const double* cabs;
+  const double* dnu;
+  const double* wup;
+  const uint16_t* jb;
+  const double* wtop;
+  const double* adown;
+  const double* em;
+  double* out;
+  double* P_out;
+  double* pabs;
+  double* ws;
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// sum over the workgroup (all threads get the result); red: >= 4 doubles
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum_d(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < kThreads / 64; ++k) s += red[k];
+  return s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
+  extern __shared__ double sm[];
+  const int M = P.M, nl = P.nl, nbd = P.nbd, nblk = P.nblk;
+  const int no = nbd + nl;
+  double* sP = sm;                       // [M]
+  double* sTop = sP + M;                 // [M]
+  double* sCJ = sTop + M;                // [nl]
+  double* sBin = sCJ + nl;               // [kBk * kBk]
+  double* sIn = sBin + kBk * kBk;        // [kBk] -> suffix sums
+  double* red = sIn + kBk;               // [8]
+  int* sScale = reinterpret_cast<int*>(red + 8);
+  double* D = P.ws + (int64_t)blockIdx.x * nblk * M;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+
+  auto A = [&](int k, int i) -> double {
+    if (k == M - 1) return sTop[i];
+    const int64_t q = (int64_t)k * M + i;
+    return P.wup[q] * sCJ[P.jb[q]];
+  };
+
+  for (int64_t c = blockIdx.x; c < P.n; c += gridDim.x) {
+    // ---- field times cross-section, absorbed power, top-bin rates
+    for (int j = t; j < nl; j += kThreads) {
+      const double Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[c * nl + j]
+                                : reinterpret_cast<const double*>(P.J)[c * nl + j];
+      sCJ[j] = P.cabs[j] * Jj;
+    }
+    __syncthreads();
+    for (int i = t; i < M; i += kThreads) {
+      double acc = 0.0;
+      const double* w = P.wtop + (int64_t)i * nl;
+      for (int j = 0; j < nl; ++j) acc += w[j] * sCJ[j];
+      sTop[i] = acc;
+    }
+    {
+      double pa = 0.0;
+      for (int j = t; j < nl; j += kThreads) pa += sCJ[j] * P.dnu[j];
+      pa = block_sum(pa, red);
+      if (t == 0 && P.pabs) P.pabs[c] = 4.0 * kPi * pa;
+    }
+    __syncthreads();
+
+    // ---- pass 1: D^b_i, columns paired (i, M-1-i) to balance the work
+    for (int h = t; h < (M + 1) / 2; h += kThreads) {
+      for (int side = 0; side < 2; ++side) {
+        const int i = side == 0 ? h : M - 1 - h;
+        if (side == 1 && i == h) break;
+        double S = 0.0;
+        D[(int64_t)(nblk - 1) * M + i] = 0.0;    // last block ends at M
+        for (int k = M - 1; k > i; --k) {
+          S += A(k, i);
+          // k is the first index past block b = (k-1)/kBk - 1
+          if (k > kBk && ((k - 1) % kBk) == 0) D[(int64_t)((k - 1) / kBk - 1) * M + i] = S;
+        }
+      }
+    }
+    if (t == 0) { sP[0] = 1.0; *sScale = 0; }
+    __syncthreads();
+
+    // ---- pass 2: blocks of f upward
+    for (int b = 0; b < nblk; ++b) {
+      const int fb = 1 + kBk * b;
+      const int eb = fb + kBk < M ? fb + kBk : M;
+      const int bk = eb - fb;
+      const double* Db = D + (int64_t)b * M;
+      // in_k for k in the block: 32 k-slots x 8 i-groups
+      {
+        const int kk = t >> 3, g = t & 7;
+        double acc = 0.0;
+        if (kk < bk) {
+          const int k = fb + kk;
+          for (int i = g; i < fb; i += 8) acc += sP[i] * A(k, i);
+        }
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (g == 0 && kk < kBk) sIn[kk] = kk < bk ? acc : 0.0;
+      }
+      // C0 = sum_{i<fb} P_i D^b_i
+      double C0 = 0.0;
+      for (int i = t; i < fb; i += kThreads) C0 += sP[i] * Db[i];
+      C0 = block_sum(C0, red);
+      // Bin[f][i] = sum_{k=f}^{eb-1} A_{k,i}: one thread per column i of the block
+      if (t < bk) {
+        const int i = fb + t;
+        double acc = 0.0;
+        for (int k = eb - 1; k > i; --k) {
+          acc += A(k, i);
+          sBin[(k - fb) * kBk + t] = acc;
+        }
+      }
+      __syncthreads();
+      if (t == 0) {                      // suffix sums of in_k
+        double acc = 0.0;
+        for (int kk = bk - 1; kk >= 0; --kk) { acc += sIn[kk]; sIn[kk] = acc; }
+      }
+      __syncthreads();
+      // sequential recurrence on wave 0; lane l holds P_{fb+l}
+      if (t < 64) {
+        const double Dl = lane < bk ? Db[fb + lane] : 0.0;
+        double myP = 0.0;
+        int nsc = 0;                     // rescales by 2^-664 inside this block
+        double c0 = C0;
+        for (int fl = 0; fl < bk; ++fl) {
+          const int f = fb + fl;
+          const double term = lane < fl ? myP * (Dl + sBin[fl * kBk + lane]) : 0.0;
+          const double s = wave_sum_d(term);
+          const double sin_f = nsc ? ldexp(sIn[fl], -664 * nsc) : sIn[fl];
+          double Pf = (c0 + sin_f + s) / P.adown[f];
+          if (lane == fl) myP = Pf;
+          if (Pf > 1e200) {               // keep the unnormalised P finite
+            ++nsc;
+            if (lane <= fl) myP = ldexp(myP, -664);
+            c0 = ldexp(c0, -664);
+          }
+        }
+        if (lane < bk) sP[fb + lane] = myP;
+        if (lane == 0) *sScale = nsc;
+      }
+      __syncthreads();
+      const int nsc = *sScale;
+      if (nsc) {
+        for (int i = t; i < fb; i += kThreads) sP[i] = ldexp(sP[i], -664 * nsc);
+      }
+      __syncthreads();
+    }
+
+    // ---- normalise and emit
+    double tot = 0.0;
+    for (int i = t; i < M; i += kThreads) tot += sP[i];
+    tot = block_sum(tot, red);
+    for (int i = t; i < M; i += kThreads) sP[i] /= tot;
+    __syncthreads();
+    if (P.P_out)
+      for (int i = t; i < M; i += kThreads) P.P_out[c * M + i] = sP[i];
+    for (int q = t; q < no; q += kThreads) {
+      double acc = 0.0;
+      for (int i = 1; i < M; ++i) acc += sP[i] * P.em[(int64_t)i * no + q];
+      P.out[c * no + q] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+size_t solve_lds(const pah_desc& d) {
+  return sizeof(double) * (2 * (size_t)d.M + d.n_lambda + kBk * kBk + kBk + 8) + 16;
+}
+
+}  // namespace
+
+struct pah_ctx {
+  pah_desc d;
+  PahLayout lay;
+  unsigned char* tables = nullptr;
+  bool built = false;
+  int n_cu = 256;
+  int blocks = 0;
+  std::string err;
+};
+
+namespace {
+int32_t pfail(pah_ctx* c, int32_t code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+const char* pcheck(const pah_desc* d) {
+  if (!d) return "null descriptor";
+  if (d->M < 3 || d->M > 4096) return "M must be in 3..4096";
+  if (d->n_lambda < 2 || d->n_lambda > 4096) return "n_lambda must be in 2..4096";
+  if (d->n_bands < 0 || d->n_bands > 64) return "n_bands must be in 0..64";
+  if (!d->T || !d->U || !d->lambda_um || !d->cabs || !d->ccont || (d->n_bands > 0 && !d->cband))
+    return "null device array";
+  return nullptr;
+}
+int nblocks_of(int M) { return (M - 1 + kBk - 1) / kBk; }
+}  // namespace
+
+extern "C" {
+
+int32_t pah_tables_bytes(const pah_desc* d, uint64_t* bytes) {
+  if (pcheck(d) || !bytes) return MCRT_E_INVALID;
+  *bytes = pah_layout(*d).total;
+  return MCRT_OK;
+}
+
+int32_t pah_ctx_create(const pah_desc* d, pah_ctx** out) {
+  if (!out) return MCRT_E_INVALID;
+  *out = nullptr;
+  if (pcheck(d)) return MCRT_E_INVALID;
+  pah_ctx* c = new (std::nothrow) pah_ctx();
+  if (!c) return MCRT_E_INVALID;
+  c->d = *d;
+  c->lay = pah_layout(*d);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pah_solve, kThreads, solve_lds(*d)) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 4;
+  c->blocks = c->n_cu * per_cu;
+  *out = c;
+  return MCRT_OK;
+}
+
+void pah_ctx_destroy(pah_ctx* c) { delete c; }
+
+const char* pah_last_error(const pah_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s) {
+  if (!c) return MCRT_E_INVALID;
+  if (!tables) return pfail(c, MCRT_E_INVALID, "null tables");
+  if (bytes < c->lay.total) return pfail(c, MCRT_E_CAPACITY, "tables buffer too small");
+  c->tables = static_cast<unsigned char*>(tables);
+  const pah_desc& d = c->d;
+  const PahLayout& L = c->lay;
+  unsigned char* T = c->tables;
+  auto D = [&](uint64_t o) { return reinterpret_cast<double*>(T + o); };
+  const int M = d.M, nl = d.n_lambda;
+  k_pah_bins<<<1, 256, 0, s>>>(nl, M, d.lambda_um, d.U, D(L.nu), D(L.dnu), D(L.ed), D(L.Elo),
+                               D(L.Ehi), D(L.Ue));
+  const int64_t mm = (int64_t)M * M;
+  k_pah_up<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.Ue), D(L.ed), D(L.wup),
+                                                        reinterpret_cast<uint16_t*>(T + L.jb));
+  const int64_t ml = (int64_t)M * nl;
+  k_pah_top<<<(unsigned)((ml + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.Ue), D(L.Elo), D(L.Ehi),
+                                                         D(L.wtop));
+  k_pah_em<<<M, 256, 0, s>>>(M, nl, d.n_bands, d.T, d.U, D(L.nu), D(L.dnu), d.cabs, d.cband, d.ccont,
+                             D(L.adown), D(L.em));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah table launch: ") + hipGetErrorString(e));
+  c->built = true;
+  return MCRT_OK;
+}
+
+int32_t pah_workspace_bytes(const pah_ctx* c, uint64_t* bytes) {
+  if (!c || !bytes) return MCRT_E_INVALID;
+  *bytes = (uint64_t)c->blocks * nblocks_of(c->d.M) * c->d.M * sizeof(double);
+  return MCRT_OK;
+}
+
+int32_t pah_solve_exact(pah_ctx* c, const void* J, int32_t j_is_f32, int64_t n, double* out,
+                        double* P_out, double* pabs_out, void* ws, uint64_t ws_bytes, hipStream_t s) {
+  if (!c) return MCRT_E_INVALID;
+  if (!c->built) return pfail(c, MCRT_E_STATE, "pah_solve_exact before pah_build_tables");
+  if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
+  if (n == 0) return MCRT_OK;
+  if (!J || !out || !ws) return pfail(c, MCRT_E_INVALID, "null J, out or workspace");
+  uint64_t need = 0;
+  pah_workspace_bytes(c, &need);
+  if (ws_bytes < need) return pfail(c, MCRT_E_CAPACITY, "workspace too small");
+  const PahLayout& L = c->lay;
+  unsigned char* T = c->tables;
+  SolveP P{};
+  P.M = c->d.M; P.nl = c->d.n_lambda; P.nbd = c->d.n_bands; P.nblk = nblocks_of(c->d.M);
+  P.j_f32 = j_is_f32 ? 1 : 0;
+  P.n = n; P.J = J; P.cabs = c->d.cabs;
+  P.dnu = reinterpret_cast<const double*>(T + L.dnu);
+  P.wup = reinterpret_cast<const double*>(T + L.wup);
+  P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
+  P.wtop = reinterpret_cast<const double*>(T + L.wtop);
+  P.adown = reinterpret_cast<const double*>(T + L.adown);
+  P.em = reinterpret_cast<const double*>(T + L.em);
+  P.out = out; P.P_out = P_out; P.pabs = pabs_out;
+  P.ws = static_cast<double*>(ws);
+  const int64_t blocks = n < c->blocks ? n : c->blocks;
+  k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah solve launch: ") + hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+"""GPU parity of the exact PAH P(T) solver against the oracle (FP64)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+pah = pytest.importorskip("paper_1201_3588_amd.pah")
+
+LAM = synth.lambda_grid(200)
+
+
+def fields(n, seed=4):
+    J, G0, Th = synth.pah_fields(n, LAM, seed=seed)
+    # add the extremes of the field range
+    J = np.vstack([J, synth.blackbody_field(LAM, [1.0, 1e6, 1e6, 1e-3], [3000.0, 40000.0, 3000.0, 10000.0])])
+    return J
+
+
+@pytest.mark.parametrize("nc,M", [(30, 500), (200, 500), (30, 37), (200, 64)])
+def test_exact_solver_matches_oracle(nc, M):
+    pm = synth.pah_model(nc, LAM)
+    T = 2.7 * (5000.0 / 2.7) ** (np.arange(M) / (M - 1))
+    U = pm.enthalpy(T)
+    J = fields(60)
+    o_out, o_P, o_pabs = oracle.pah_solve(T, U, LAM, pm.cabs, pm.cband, pm.ccont, J, want_P=True, n_threads=8)
+    s = pah.PahSolver(T, U, LAM, pm.cabs, pm.cband, pm.ccont)
+    g_out, g_P, g_pabs = s.solve(torch.as_tensor(J).cuda(), want_P=True)
+    torch.cuda.synchronize()
+    g_out, g_P, g_pabs = g_out.cpu().numpy(), g_P.cpu().numpy(), g_pabs.cpu().numpy()
+    assert np.allclose(g_pabs, o_pabs, rtol=1e-13, atol=0)
+    for c in range(J.shape[0]):
+        m = o_P[c] > 1e-12 * o_P[c].max()
+        assert np.max(np.abs(g_P[c][m] / o_P[c][m] - 1)) < 1e-10, c
+        mo = o_out[c] > 1e-12 * o_out[c].max()
+        assert np.max(np.abs(g_out[c][mo] / o_out[c][mo] - 1)) < 1e-10, c
+        assert np.all(np.abs(g_out[c][~mo]) <= 1e-11 * o_out[c].max())
+
+
+def test_float_input_and_many_cells():
+    pm = synth.pah_model(30, LAM)
+    s = pah.PahSolver.from_model(pm)
+    J = fields(3000, seed=9).astype(np.float32)
+    g_out, _, g_pabs = s.solve(torch.as_tensor(J).cuda())
+    T = 2.7 * (5000.0 / 2.7) ** (np.arange(500) / 499)
+    idx = np.array([0, 1, 777, 1500, 2999, J.shape[0] - 1])
+    o_out, _, o_pabs = oracle.pah_solve(T, pm.enthalpy(T), LAM, pm.cabs, pm.cband, pm.ccont,
+                                        J[idx].astype(np.float64))
+    g_out = g_out.cpu().numpy()[idx]
+    for r in range(len(idx)):
+        mo = o_out[r] > 1e-12 * o_out[r].max()
+        assert np.max(np.abs(g_out[r][mo] / o_out[r][mo] - 1)) < 1e-10
+    # energy balance of every cell: emitted / absorbed within the enthalpy-grid error
+    allout = s.solve(torch.as_tensor(J).cuda())[0].sum(1).cpu().numpy()
+    ratio = allout / g_pabs.cpu().numpy()
+    assert np.all(np.abs(ratio - 1) < 0.05)
