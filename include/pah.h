@@ -75,6 +75,71 @@ int32_t pah_solve_exact(pah_ctx *ctx, const void *J, int32_t j_is_f32, int64_t n
                         double *P_out, double *pabs_out, void *ws, uint64_t ws_bytes,
                         hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the exact step: a perceptron n_in -> n_h -> n_h -> n_out
+ * with SiLU activations, z = W x + b per layer (W stored [out][in]).
+ * Inputs are standardised log10 J_nu per wavelength bin; outputs standardised
+ * log10(F_q / P_abs) per output q (P_abs = absorbed power).  Products run on
+ * the matrix cores with bfloat16 operands (round to nearest even) and FP32
+ * accumulation; weights keep FP32 masters, updated by Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected), and bfloat16 working copies.
+ * All state lives in one caller-owned device buffer of pah_mlp_state_bytes;
+ * `batch` bounds the rows of one forward/backward call.
+ * ------------------------------------------------------------------------ */
+typedef struct pah_mlp pah_mlp;
+
+int32_t pah_mlp_state_bytes(int32_t n_in, int32_t n_h, int32_t n_out, int32_t batch, uint64_t *bytes);
+int32_t pah_mlp_create(int32_t n_in, int32_t n_h, int32_t n_out, int32_t batch, void *state,
+                       uint64_t state_bytes, pah_mlp **out);
+void pah_mlp_destroy(pah_mlp *m);
+const char *pah_mlp_last_error(const pah_mlp *m);
+
+/* Byte offsets inside the state buffer (for inspection), in this order:
+ * params, grads, adam_m, adam_v, n_params (a count), then element offsets of
+ * W1 b1 W2 b2 W3 b3 inside a parameter block, then byte offsets of the bf16
+ * weights W1 W2 W3, x_mu x_sd x_lo x_hi y_mu y_sd, activations X Z1 H1 Z2 H2
+ * Y dY dZ2 dZ1, loss, total.  off: host array of >= 32 entries. */
+int32_t pah_mlp_offsets(const pah_mlp *m, uint64_t *off, int32_t n_off);
+
+/* Copies FP32 parameters (device, flat [W1 b1 W2 b2 W3 b3]) into the masters,
+ * zeroes the Adam moments and refreshes the bfloat16 copies. */
+int32_t pah_mlp_load(pah_mlp *m, const float *params, hipStream_t stream);
+
+/* Normalisation (device FP32 arrays): input mean, sd, and the standardised
+ * training range [x_lo, x_hi] per input; output mean and sd per output. */
+int32_t pah_mlp_set_norm(pah_mlp *m, const float *x_mu, const float *x_sd, const float *x_lo,
+                         const float *x_hi, const float *y_mu, const float *y_sd, hipStream_t stream);
+
+/* Forward pass on standardised inputs X [n][n_in] (device FP32, rounded to
+ * bfloat16), writing standardised outputs Y [n][n_out] (device FP32); n <= batch. */
+int32_t pah_mlp_forward(pah_mlp *m, const float *X, int32_t n, float *Y, hipStream_t stream);
+
+/* One training step on a batch: forward, mean-squared-error loss against
+ * standardised targets T [n][n_out], backward into the grads block, and (if
+ * lr != 0) an Adam update with step count `step` (>= 1). */
+int32_t pah_mlp_train_step(pah_mlp *m, const float *X, const float *T, int32_t n, float lr,
+                           int32_t step, hipStream_t stream);
+
+/* Surrogate emission for n cells from their fields J (device float
+ * [n][n_lambda]): out (device double [n][n_bands + n_lambda]) as the exact
+ * solver defines it, pabs (device double [n]), and ood (device uint8 [n]):
+ * bit 0 set when a standardised input lies more than in_margin outside the
+ * training range, bit 1 when the emitted total differs from P_abs by more than
+ * balance_tol (relative).  The network must match the PAH model's shape and
+ * the PAH tables must be built. */
+int32_t pah_surrogate_infer(pah_mlp *m, const pah_ctx *ctx, const float *J, int64_t n, double *out,
+                            uint8_t *ood, double *pabs, float in_margin, float balance_tol,
+                            hipStream_t stream);
+
+/* Exact solution for the flagged cells only: every cell c with ood[c] != 0
+ * is solved by the exact solver and its row of out overwritten.  The flagged
+ * cells are gathered on the device into idx (device int64 [n + 1]; idx[n]
+ * receives their count), so no host round trip is needed.  ws as for
+ * pah_solve_exact. */
+int32_t pah_exact_fallback(pah_ctx *ctx, const float *J, int64_t n, const uint8_t *ood,
+                           double *out, int64_t *idx, void *ws, uint64_t ws_bytes,
+                           hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,507 @@
+// PAH emission surrogate: a 3-layer perceptron (n_in -> n_h -> n_h -> n_out,
+// SiLU) trained on cells that the exact P(T) solver has solved.  Products run
+// on the CDNA4 matrix cores (v_mfma_f32_32x32x16_bf16: bfloat16 operands,
+// FP32 accumulation); weights keep FP32 masters updated by Adam and bfloat16
+// working copies; the tile loader reads either operand layout, so one
+// bfloat16 copy of each weight matrix serves forward and backward products.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mcrt_internal.h"
+#include "pah.h"
+#include "pah_internal.h"
+
+using namespace mcrt;
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+enum { EPI_F32 = 0, EPI_SILU = 1, EPI_DSILU = 2 };
+
+// C[m][n] = sum_k A(m,k) B(k,n); A(m,k) = ta ? A[k*lda+m] : A[m*lda+k];
+// B(k,n) = tb ? B[n*ldb+k] : B[k*ldb+n].  bfloat16 operands (as uint16).
+struct GemmP {
+  int M, N, K, lda, ldb, ta, tb;
+  const uint16_t* A;
+  const uint16_t* B;
+  const float* bias;    // [N] or null
+  float* C;             // EPI_F32: [M][ldc]; EPI_SILU: pre-activation out (or null)
+  int ldc;
+  uint16_t* H;          // EPI_SILU: bf16 activation; EPI_DSILU: bf16 gradient
+  int ldh;
+  const float* Z;       // EPI_DSILU: stored pre-activation [M][ldz]
+  int ldz;
+};
+
+constexpr int BM = 64, BN = 64, BK = 32, PADK = 40;
+
+// 64 x 32 tile of X(r, k) (r = row of the tile, k contiguous in LDS)
+__device__ __forceinline__ void load_tile(uint16_t (*S)[PADK], const uint16_t* __restrict__ G, int ld,
+                                          bool kmajor, int r0, int k0, int R, int K) {
+  const int t = threadIdx.x;
+  if (!kmajor) {                 // G[r*ld + k]: 8 consecutive k per thread
+    const int r = t >> 2, kc = (t & 3) * 8;
+    const int gr = r0 + r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int gk = k0 + kc + i;
+      S[r][kc + i] = (gr < R && gk < K) ? G[(int64_t)gr * ld + gk] : (uint16_t)0;
+    }
+  } else {                       // G[k*ld + r]: 8 consecutive r per thread
+    const int kr = t >> 3, rc = (t & 7) * 8;
+    const int gk = k0 + kr;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int gr = r0 + rc + i;
+      S[rc + i][kr] = (gr < R && gk < K) ? G[(int64_t)gk * ld + gr] : (uint16_t)0;
+    }
+  }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const GemmP p) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM][PADK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][PADK];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x16 acc = {};
+  for (int k0 = 0; k0 < p.K; k0 += BK) {
+    load_tile(As, p.A, p.lda, p.ta != 0, m0, k0, p.M, p.K);
+    load_tile(Bs, p.B, p.ldb, p.tb == 0, n0, k0, p.N, p.K);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const u16x8 a = *reinterpret_cast<const u16x8*>(&As[wm + (lane & 31)][kk + 8 * (lane >> 5)]);
+      const u16x8 b = *reinterpret_cast<const u16x8*>(&Bs[wn + (lane & 31)][kk + 8 * (lane >> 5)]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator element r of lane l: row 8*(r/4) + 4*(l/32) + r%4, column l%32
+  const int col = n0 + wn + (lane & 31);
+  if (col >= p.N) return;
+  const float bcol = p.bias ? p.bias[col] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (row >= p.M) continue;
+    const float v = acc[r] + bcol;
+    if (EPI == EPI_F32) {
+      p.C[(int64_t)row * p.ldc + col] = v;
+    } else if (EPI == EPI_SILU) {
+      if (p.C) p.C[(int64_t)row * p.ldc + col] = v;
+      p.H[(int64_t)row * p.ldh + col] = f2bf(silu(v));
+    } else {
+      p.H[(int64_t)row * p.ldh + col] = f2bf(v * dsilu(p.Z[(int64_t)row * p.ldz + col]));
+    }
+  }
+}
+
+template <int EPI>
+hipError_t gemm(const GemmP& p, hipStream_t s) {
+  dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM);
+  k_gemm<EPI><<<grid, 256, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+struct MlpLayout {
+  // fp32 parameter block [W1 b1 W2 b2 W3 b3] and three blocks like it
+  uint64_t params, grads, adam_m, adam_v, n_params;
+  uint64_t oW1, ob1, oW2, ob2, oW3, ob3;     // element offsets inside a block
+  uint64_t W1h, W2h, W3h;                    // bf16 copies
+  uint64_t x_mu, x_sd, x_lo, x_hi, y_mu, y_sd;
+  uint64_t X16, Z1, H1, Z2, H2, Y, dY16, dZ2, dZ1, loss, total;
+};
+
+MlpLayout mlp_layout(int ni, int nh, int no, int batch) {
+  MlpLayout L{};
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) {
+    const uint64_t o = off;
+    off += (b + 255) & ~uint64_t(255);
+    return o;
+  };
+  L.oW1 = 0;
+  L.ob1 = L.oW1 + (uint64_t)nh * ni;
+  L.oW2 = L.ob1 + nh;
+  L.ob2 = L.oW2 + (uint64_t)nh * nh;
+  L.oW3 = L.ob2 + nh;
+  L.ob3 = L.oW3 + (uint64_t)no * nh;
+  L.n_params = L.ob3 + no;
+  L.params = take(4 * L.n_params);
+  L.grads = take(4 * L.n_params);
+  L.adam_m = take(4 * L.n_params);
+  L.adam_v = take(4 * L.n_params);
+  L.W1h = take(2ull * nh * ni);
+  L.W2h = take(2ull * nh * nh);
+  L.W3h = take(2ull * no * nh);
+  L.x_mu = take(4ull * ni);
+  L.x_sd = take(4ull * ni);
+  L.x_lo = take(4ull * ni);
+  L.x_hi = take(4ull * ni);
+  L.y_mu = take(4ull * no);
+  L.y_sd = take(4ull * no);
+  const uint64_t B = (uint64_t)batch;
+  L.X16 = take(2 * B * ni);
+  L.Z1 = take(4 * B * nh);
+  L.H1 = take(2 * B * nh);
+  L.Z2 = take(4 * B * nh);
+  L.H2 = take(2 * B * nh);
+  L.Y = take(4 * B * no);
+  L.dY16 = take(2 * B * no);
+  L.dZ2 = take(2 * B * nh);
+  L.dZ1 = take(2 * B * nh);
+  L.loss = take(256);
+  L.total = off;
+  return L;
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// bf16 working copy of one weight matrix
+__global__ void k_refresh(const float* __restrict__ W, int64_t n, uint16_t* __restrict__ Wh) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) Wh[q] = f2bf(W[q]);
+}
+
+// dY = 2 (Y - T) / (n n_out) in bf16, and the loss sum
+__global__ void k_loss(const float* __restrict__ Y, const float* __restrict__ T, int64_t n, int no,
+                       uint16_t* __restrict__ dY, float* loss) {
+  __shared__ float red[256];
+  const int64_t N = n * no;
+  const float sc = 2.0f / (float)N;
+  float acc = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = Y[i] - T[i];
+    acc += d * d;
+    dY[i] = f2bf(sc * d);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)N);
+}
+
+// column sums of a bf16 [n][N] matrix
+__global__ void k_colsum(const uint16_t* __restrict__ G, int64_t n, int N, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  float acc = 0.0f;
+  for (int64_t r = 0; r < n; ++r) acc += bf2f(G[r * N + c]);
+  out[c] = acc;
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 masters, bias-corrected with step t
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// inference input: standardised log10 J in bf16, absorbed power, input range flag
+__global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const double* __restrict__ cabs,
+                         const double* __restrict__ dnu, const float* __restrict__ mu,
+                         const float* __restrict__ sd, const float* __restrict__ lo,
+                         const float* __restrict__ hi, float margin, uint16_t* __restrict__ X,
+                         double* __restrict__ pabs, uint8_t* __restrict__ ood) {
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  __shared__ double red[256];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double pa = 0.0;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
+    const float Jj = J[c * nl + j];
+    pa += cabs[j] * (double)Jj * dnu[j];
+    const float x = (log10f(fmaxf(Jj, 1e-40f)) - mu[j]) / sd[j];
+    if (x < lo[j] - margin || x > hi[j] + margin) bad = 1;
+    X[c * nl + j] = f2bf(x);
+  }
+  red[threadIdx.x] = pa;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pabs[c] = 4.0 * kPi * red[0];
+    ood[c] = bad ? 1 : 0;
+  }
+}
+
+// inference output: F = 10^(y sd + mu) P_abs, energy-balance flag
+__global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const float* __restrict__ mu,
+                          const float* __restrict__ sd, const double* __restrict__ pabs, float tol,
+                          double* __restrict__ out, uint8_t* __restrict__ ood) {
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < no; q += blockDim.x) {
+    const double f = pow(10.0, (double)(Y[c * no + q] * sd[q] + mu[q])) * pabs[c];
+    out[c * no + q] = f;
+    s += f;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(fabs(red[0] - pabs[c]) <= tol * pabs[c])) ood[c] |= 2;
+}
+
+}  // namespace
+
+struct pah_mlp {
+  int ni, nh, no, batch;
+  MlpLayout L;
+  unsigned char* st = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int32_t mfail(pah_mlp* m, int32_t code, const std::string& s) {
+  if (m) m->err = s;
+  return code;
+}
+
+template <typename T>
+T* at(pah_mlp* m, uint64_t off) { return reinterpret_cast<T*>(m->st + off); }
+
+hipError_t refresh_all(pah_mlp* m, hipStream_t s) {
+  const MlpLayout& L = m->L;
+  float* P = at<float>(m, L.params);
+  struct { uint64_t o; int64_t n; uint64_t h; } mats[3] = {
+      {L.oW1, (int64_t)m->nh * m->ni, L.W1h}, {L.oW2, (int64_t)m->nh * m->nh, L.W2h},
+      {L.oW3, (int64_t)m->no * m->nh, L.W3h}};
+  for (auto& w : mats)
+    k_refresh<<<(unsigned)((w.n + 255) / 256), 256, 0, s>>>(P + w.o, w.n, at<uint16_t>(m, w.h));
+  return hipGetLastError();
+}
+
+// forward on bf16 inputs already in X16 (rows n <= batch); Y fp32 standardised
+hipError_t forward(pah_mlp* m, int64_t n, const uint16_t* X16, float* Y, hipStream_t s) {
+  const MlpLayout& L = m->L;
+  const float* P = at<float>(m, L.params);
+  GemmP g{};
+  g.M = (int)n; g.N = m->nh; g.K = m->ni; g.A = X16; g.lda = m->ni; g.ta = 0;
+  g.B = at<uint16_t>(m, L.W1h); g.ldb = m->ni; g.tb = 1; g.bias = P + L.ob1;
+  g.C = at<float>(m, L.Z1); g.ldc = m->nh; g.H = at<uint16_t>(m, L.H1); g.ldh = m->nh;
+  hipError_t e = gemm<EPI_SILU>(g, s);
+  if (e != hipSuccess) return e;
+  g.K = m->nh; g.A = at<uint16_t>(m, L.H1); g.lda = m->nh; g.B = at<uint16_t>(m, L.W2h); g.ldb = m->nh;
+  g.bias = P + L.ob2; g.C = at<float>(m, L.Z2); g.H = at<uint16_t>(m, L.H2);
+  e = gemm<EPI_SILU>(g, s);
+  if (e != hipSuccess) return e;
+  g.N = m->no; g.A = at<uint16_t>(m, L.H2); g.B = at<uint16_t>(m, L.W3h); g.bias = P + L.ob3;
+  g.C = Y; g.ldc = m->no; g.H = nullptr;
+  return gemm<EPI_F32>(g, s);
+}
+
+// backward from dY16 (bf16, rows n): grads of all parameters into the grads block
+hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
+  const MlpLayout& L = m->L;
+  float* G = at<float>(m, L.grads);
+  const int ni = m->ni, nh = m->nh, no = m->no;
+  const uint16_t* dY = at<uint16_t>(m, L.dY16);
+  GemmP g{};
+  // dW3 [no][nh] = dY^T H2
+  g.M = no; g.N = nh; g.K = (int)n; g.A = dY; g.lda = no; g.ta = 1;
+  g.B = at<uint16_t>(m, L.H2); g.ldb = nh; g.tb = 0; g.C = G + L.oW3; g.ldc = nh;
+  hipError_t e = gemm<EPI_F32>(g, s);
+  k_colsum<<<(no + 255) / 256, 256, 0, s>>>(dY, n, no, G + L.ob3);
+  // dZ2 = (dY W3) * silu'(Z2); W3 [no][nh] read as (k=o, n=j) -> W3h with tb = 0
+  g = GemmP{};
+  g.M = (int)n; g.N = nh; g.K = no; g.A = dY; g.lda = no; g.ta = 0;
+  g.B = at<uint16_t>(m, L.W3h); g.ldb = nh; g.tb = 0;
+  g.H = at<uint16_t>(m, L.dZ2); g.ldh = nh; g.Z = at<float>(m, L.Z2); g.ldz = nh;
+  if (e == hipSuccess) e = gemm<EPI_DSILU>(g, s);
+  // dW2 [nh][nh] = dZ2^T H1
+  g = GemmP{};
+  g.M = nh; g.N = nh; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ2); g.lda = nh; g.ta = 1;
+  g.B = at<uint16_t>(m, L.H1); g.ldb = nh; g.tb = 0; g.C = G + L.oW2; g.ldc = nh;
+  if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
+  k_colsum<<<(nh + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.dZ2), n, nh, G + L.ob2);
+  // dZ1 = (dZ2 W2) * silu'(Z1)
+  g = GemmP{};
+  g.M = (int)n; g.N = nh; g.K = nh; g.A = at<uint16_t>(m, L.dZ2); g.lda = nh; g.ta = 0;
+  g.B = at<uint16_t>(m, L.W2h); g.ldb = nh; g.tb = 0;
+  g.H = at<uint16_t>(m, L.dZ1); g.ldh = nh; g.Z = at<float>(m, L.Z1); g.ldz = nh;
+  if (e == hipSuccess) e = gemm<EPI_DSILU>(g, s);
+  // dW1 [nh][ni] = dZ1^T X
+  g = GemmP{};
+  g.M = nh; g.N = ni; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ1); g.lda = nh; g.ta = 1;
+  g.B = at<uint16_t>(m, L.X16); g.ldb = ni; g.tb = 0; g.C = G + L.oW1; g.ldc = ni;
+  if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
+  k_colsum<<<(nh + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.dZ1), n, nh, G + L.ob1);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pah_mlp_state_bytes(int32_t n_in, int32_t n_h, int32_t n_out, int32_t batch, uint64_t* bytes) {
+  if (n_in < 1 || n_h < 1 || n_out < 1 || batch < 1 || !bytes || n_in > 8192 || n_h > 8192 || n_out > 8192)
+    return MCRT_E_INVALID;
+  *bytes = mlp_layout(n_in, n_h, n_out, batch).total;
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_create(int32_t n_in, int32_t n_h, int32_t n_out, int32_t batch, void* state,
+                       uint64_t state_bytes, pah_mlp** out) {
+  if (!out) return MCRT_E_INVALID;
+  *out = nullptr;
+  uint64_t need = 0;
+  if (pah_mlp_state_bytes(n_in, n_h, n_out, batch, &need) != MCRT_OK || !state) return MCRT_E_INVALID;
+  if (state_bytes < need) return MCRT_E_CAPACITY;
+  pah_mlp* m = new (std::nothrow) pah_mlp();
+  if (!m) return MCRT_E_INVALID;
+  m->ni = n_in; m->nh = n_h; m->no = n_out; m->batch = batch;
+  m->L = mlp_layout(n_in, n_h, n_out, batch);
+  m->st = static_cast<unsigned char*>(state);
+  *out = m;
+  return MCRT_OK;
+}
+
+void pah_mlp_destroy(pah_mlp* m) { delete m; }
+
+const char* pah_mlp_last_error(const pah_mlp* m) { return m ? m->err.c_str() : "null network"; }
+
+int32_t pah_mlp_offsets(const pah_mlp* m, uint64_t* off, int32_t n_off) {
+  if (!m || !off || n_off < 32) return MCRT_E_INVALID;
+  const MlpLayout& L = m->L;
+  const uint64_t v[32] = {L.params, L.grads, L.adam_m, L.adam_v, L.n_params, L.oW1, L.ob1, L.oW2,
+                          L.ob2, L.oW3, L.ob3, L.W1h, L.W2h, L.W3h, L.x_mu, L.x_sd, L.x_lo, L.x_hi,
+                          L.y_mu, L.y_sd, L.X16, L.Z1, L.H1, L.Z2, L.H2, L.Y, L.dY16, L.dZ2, L.dZ1,
+                          L.loss, L.total, 0};
+  std::memcpy(off, v, sizeof v);
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_load(pah_mlp* m, const float* params, hipStream_t s) {
+  if (!m || !params) return MCRT_E_INVALID;
+  const MlpLayout& L = m->L;
+  hipError_t e = hipMemcpyAsync(m->st + L.params, params, 4 * L.n_params, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(m->st + L.adam_m, 0, 4 * L.n_params, s);
+  if (e == hipSuccess) e = hipMemsetAsync(m->st + L.adam_v, 0, 4 * L.n_params, s);
+  if (e == hipSuccess) e = refresh_all(m, s);
+  if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_set_norm(pah_mlp* m, const float* x_mu, const float* x_sd, const float* x_lo,
+                         const float* x_hi, const float* y_mu, const float* y_sd, hipStream_t s) {
+  if (!m || !x_mu || !x_sd || !x_lo || !x_hi || !y_mu || !y_sd) return MCRT_E_INVALID;
+  const MlpLayout& L = m->L;
+  const float* src[6] = {x_mu, x_sd, x_lo, x_hi, y_mu, y_sd};
+  const uint64_t dst[6] = {L.x_mu, L.x_sd, L.x_lo, L.x_hi, L.y_mu, L.y_sd};
+  for (int k = 0; k < 6; ++k) {
+    const uint64_t n = k < 4 ? (uint64_t)m->ni : (uint64_t)m->no;
+    const hipError_t e = hipMemcpyAsync(m->st + dst[k], src[k], 4 * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  }
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_forward(pah_mlp* m, const float* X, int32_t n, float* Y, hipStream_t s) {
+  if (!m || !X || !Y) return MCRT_E_INVALID;
+  if (n < 1 || n > m->batch) return mfail(m, MCRT_E_CAPACITY, "n outside 1..batch");
+  const int64_t nx = (int64_t)n * m->ni;
+  k_to_bf16<<<(unsigned)((nx + 255) / 256), 256, 0, s>>>(X, nx, at<uint16_t>(m, m->L.X16));
+  const hipError_t e = forward(m, n, at<uint16_t>(m, m->L.X16), Y, s);
+  if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_train_step(pah_mlp* m, const float* X, const float* T, int32_t n, float lr,
+                           int32_t step, hipStream_t s) {
+  if (!m || !X || !T) return MCRT_E_INVALID;
+  if (n < 1 || n > m->batch) return mfail(m, MCRT_E_CAPACITY, "n outside 1..batch");
+  if (step < 1) return mfail(m, MCRT_E_INVALID, "step counts from 1");
+  const MlpLayout& L = m->L;
+  const int64_t nx = (int64_t)n * m->ni;
+  k_to_bf16<<<(unsigned)((nx + 255) / 256), 256, 0, s>>>(X, nx, at<uint16_t>(m, L.X16));
+  hipError_t e = forward(m, n, at<uint16_t>(m, L.X16), at<float>(m, L.Y), s);
+  if (e == hipSuccess) e = hipMemsetAsync(m->st + L.loss, 0, 4, s);
+  if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  k_loss<<<256, 256, 0, s>>>(at<float>(m, L.Y), T, n, m->no, at<uint16_t>(m, L.dY16), at<float>(m, L.loss));
+  e = backward(m, n, s);
+  if (e == hipSuccess && lr != 0.0f) {
+    const double b1 = 0.9, b2 = 0.999;
+    const int64_t np = (int64_t)L.n_params;
+    k_adam<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(
+        at<float>(m, L.params), at<float>(m, L.grads), at<float>(m, L.adam_m), at<float>(m, L.adam_v),
+        np, lr, (float)b1, (float)b2, 1e-8f, (float)(1.0 - pow(b1, step)), (float)(1.0 - pow(b2, step)));
+    e = refresh_all(m, s);
+  }
+  if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int64_t n, double* out,
+                            uint8_t* ood, double* pabs, float in_margin, float balance_tol,
+                            hipStream_t s) {
+  if (!m || !ctx || !J || !out || !ood || !pabs) return MCRT_E_INVALID;
+  if (n < 0) return mfail(m, MCRT_E_INVALID, "n < 0");
+  const pah_desc& d = pah_ctx_desc(ctx);
+  if (d.n_lambda != m->ni || d.n_bands + d.n_lambda != m->no)
+    return mfail(m, MCRT_E_INVALID, "network shape does not match the PAH model");
+  const double* dnu = pah_ctx_dnu(ctx);
+  if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
+  const MlpLayout& L = m->L;
+  for (int64_t c0 = 0; c0 < n; c0 += m->batch) {
+    const int64_t nc = n - c0 < m->batch ? n - c0 : m->batch;
+    k_mlp_in<<<(unsigned)nc, 256, 0, s>>>(J + c0 * m->ni, nc, m->ni, d.cabs, dnu, at<float>(m, L.x_mu),
+                                           at<float>(m, L.x_sd), at<float>(m, L.x_lo), at<float>(m, L.x_hi),
+                                           in_margin, at<uint16_t>(m, L.X16), pabs + c0, ood + c0);
+    hipError_t e = forward(m, nc, at<uint16_t>(m, L.X16), at<float>(m, L.Y), s);
+    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+    k_mlp_out<<<(unsigned)nc, 256, 0, s>>>(at<float>(m, L.Y), nc, m->no, at<float>(m, L.y_mu),
+                                            at<float>(m, L.y_sd), pabs + c0, balance_tol, out + c0 * m->no,
+                                            ood + c0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  }
+  return MCRT_OK;
+}
+
+}  // extern "C"

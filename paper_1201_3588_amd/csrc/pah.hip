@@ -22,6 +22,7 @@
 
 #include "mcrt_internal.h"
 #include "pah.h"
+#include "pah_internal.h"
 
 using namespace mcrt;
 
@@ -168,6 +169,8 @@ struct SolveP {
   double* P_out;
   double* pabs;
   double* ws;
+  const int64_t* idx;     // cells to solve (null: 0..n-1)
+  const int64_t* n_dev;   // device count of idx (null: n)
 };
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -209,7 +212,9 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
     return P.wup[q] * sCJ[P.jb[q]];
   };
 
-  for (int64_t c = blockIdx.x; c < P.n; c += gridDim.x) {
+  const int64_t n_cells = P.n_dev ? *P.n_dev : P.n;
+  for (int64_t cl = blockIdx.x; cl < n_cells; cl += gridDim.x) {
+    const int64_t c = P.idx ? P.idx[cl] : cl;
     // ---- field times cross-section, absorbed power, top-bin rates
     for (int j = t; j < nl; j += kThreads) {
       const double Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[c * nl + j]
@@ -333,6 +338,18 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
   }
 }
 
+// indices of flagged cells, compacted on the device (order irrelevant: each
+// cell is solved independently); idx[n] holds the count
+__global__ void k_compact(const uint8_t* __restrict__ ood, int64_t n, int64_t* __restrict__ idx) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && ood[c]) {
+    const unsigned long long k = atomicAdd(reinterpret_cast<unsigned long long*>(idx + n), 1ull);
+    idx[k] = c;
+  }
+}
+
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
 size_t solve_lds(const pah_desc& d) {
   return sizeof(double) * (2 * (size_t)d.M + d.n_lambda + kBk * kBk + kBk + 8) + 16;
 }
@@ -348,6 +365,11 @@ struct pah_ctx {
   int blocks = 0;
   std::string err;
 };
+
+const pah_desc& pah_ctx_desc(const pah_ctx* c) { return c->d; }
+const double* pah_ctx_dnu(const pah_ctx* c) {
+  return c->built ? reinterpret_cast<const double*>(c->tables + c->lay.dnu) : nullptr;
+}
 
 namespace {
 int32_t pfail(pah_ctx* c, int32_t code, const std::string& m) {
@@ -459,6 +481,41 @@ int32_t pah_solve_exact(pah_ctx* c, const void* J, int32_t j_is_f32, int64_t n, 
   k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah solve launch: ") + hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_exact_fallback(pah_ctx* c, const float* J, int64_t n, const uint8_t* ood, double* out,
+                           int64_t* idx, void* ws, uint64_t ws_bytes, hipStream_t s) {
+  if (!c) return MCRT_E_INVALID;
+  if (!c->built) return pfail(c, MCRT_E_STATE, "fallback before pah_build_tables");
+  if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
+  if (n == 0) return MCRT_OK;
+  if (!J || !ood || !out || !idx || !ws) return pfail(c, MCRT_E_INVALID, "null argument");
+  uint64_t need = 0;
+  pah_workspace_bytes(c, &need);
+  if (ws_bytes < need) return pfail(c, MCRT_E_CAPACITY, "workspace too small");
+  k_zero_i64<<<1, 1, 0, s>>>(idx + n);
+  k_compact<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ood, n, idx);
+  const PahLayout& L = c->lay;
+  unsigned char* T = c->tables;
+  SolveP P{};
+  P.M = c->d.M; P.nl = c->d.n_lambda; P.nbd = c->d.n_bands; P.nblk = nblocks_of(c->d.M);
+  P.j_f32 = 1;
+  P.n = n; P.J = J; P.cabs = c->d.cabs;
+  P.dnu = reinterpret_cast<const double*>(T + L.dnu);
+  P.wup = reinterpret_cast<const double*>(T + L.wup);
+  P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
+  P.wtop = reinterpret_cast<const double*>(T + L.wtop);
+  P.adown = reinterpret_cast<const double*>(T + L.adown);
+  P.em = reinterpret_cast<const double*>(T + L.em);
+  P.out = out;
+  P.ws = static_cast<double*>(ws);
+  P.idx = idx;
+  P.n_dev = idx + n;
+  const int64_t blocks = n < c->blocks ? n : c->blocks;
+  k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("fallback launch: ") + hipGetErrorString(e));
   return MCRT_OK;
 }
 

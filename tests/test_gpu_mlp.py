@@ -1,0 +1,78 @@
+"""GPU parity of the surrogate network kernels (bfloat16 MFMA, FP32 accumulate)
+against the FP64 reference with bfloat16-rounded operands."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+pah = pytest.importorskip("paper_1201_3588_amd.pah")
+
+
+def rel_fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("shape,n", [((200, 256, 217), 2048), ((200, 256, 217), 77), ((37, 70, 29), 130)])
+def test_forward_backward_match_reference(shape, n):
+    ni, nh, no = shape
+    rng = np.random.default_rng(3)
+    p = omlp.init_params(ni, nh, no, seed=5)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, size=p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    X = rng.normal(size=(n, ni)).astype(np.float32)
+    T = rng.normal(size=(n, no)).astype(np.float32)
+    net = pah.PahMLP(ni, nh, no, batch=max(n, 64))
+    net.load(p)
+    Yg = net.forward(torch.as_tensor(X).cuda()).cpu().numpy()
+    Yr, cache = omlp.forward(p, X.astype(np.float64), bf16=True)
+    assert rel_fro(Yg, Yr) < 1e-4
+    net.train_step(torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda(), 0.0, 1)
+    torch.cuda.synchronize()
+    g = net.grads()
+    _, dY = omlp.mse(Yr, T.astype(np.float64))
+    gr = omlp.backward(cache, dY, bf16=True)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert rel_fro(g[k], gr[k]) < 2e-4, k
+    loss_ref = float(((Yr - T) ** 2).mean())
+    assert abs(net.loss() / loss_ref - 1) < 1e-4
+
+
+def test_adam_step_matches_reference():
+    rng = np.random.default_rng(7)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in omlp.init_params(200, 256, 217, seed=1).items()}
+    X = rng.normal(size=(512, 200)).astype(np.float32)
+    T = rng.normal(size=(512, 217)).astype(np.float32)
+    net = pah.PahMLP(batch=512)
+    net.load(p)
+    net.train_step(torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda(), 1e-3, 1)
+    torch.cuda.synchronize()
+    g = net.grads()
+    new = net.params()
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    ref = {k: val.copy() for k, val in p.items()}
+    omlp.adam_step(ref, g, m, v, 1, 1e-3)
+    for k in p:
+        assert np.max(np.abs(new[k] - ref[k])) <= 1e-6 * max(1.0, np.max(np.abs(ref[k]))), k
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(11)
+    ni, nh, no = 32, 64, 16
+    Wt = rng.normal(size=(no, ni)) / np.sqrt(ni)
+    X = rng.normal(size=(4096, ni)).astype(np.float32)
+    T = np.tanh(X @ Wt.T).astype(np.float32)
+    net = pah.PahMLP(ni, nh, no, batch=512)
+    net.load(omlp.init_params(ni, nh, no, seed=2))
+    Xt, Tt = torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda()
+    losses = []
+    step = 0
+    for ep in range(30):
+        for b in range(0, 4096, 512):
+            step += 1
+            net.train_step(Xt[b:b + 512], Tt[b:b + 512], 3e-3, step)
+        losses.append(net.loss())
+    assert losses[-1] < 0.1 * losses[0]
