@@ -110,6 +110,15 @@ int32_t pah_mlp_load(pah_mlp *m, const float *params, hipStream_t stream);
 int32_t pah_mlp_set_norm(pah_mlp *m, const float *x_mu, const float *x_sd, const float *x_lo,
                          const float *x_hi, const float *y_mu, const float *y_sd, hipStream_t stream);
 
+/* Training pairs from exactly solved cells: x = log10 max(J, 1e-40),
+ * y = log10 max(out / pabs, 1e-20) into X [n][n_in] and Y [n][n_out]
+ * (device FP32, caller-owned), then the per-column mean and sd (floored at
+ * 1e-3) of both are stored as the network's normalisation, X and Y are
+ * standardised in place and the standardised range of X is recorded.
+ * J: device float [n][n_in]; out, pabs: as returned by pah_solve_exact. */
+int32_t pah_mlp_prepare(pah_mlp *m, const float *J, const double *out, const double *pabs, int64_t n,
+                        float *X, float *Y, hipStream_t stream);
+
 /* Forward pass on standardised inputs X [n][n_in] (device FP32, rounded to
  * bfloat16), writing standardised outputs Y [n][n_out] (device FP32); n <= batch. */
 int32_t pah_mlp_forward(pah_mlp *m, const float *X, int32_t n, float *Y, hipStream_t stream);

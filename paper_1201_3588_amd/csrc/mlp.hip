@@ -286,6 +286,77 @@ __global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const 
   if (threadIdx.x == 0 && !(fabs(red[0] - pabs[c]) <= tol * pabs[c])) ood[c] |= 2;
 }
 
+// training pairs: x = log10 J, y = log10(F / P_abs) (floored), as floats
+__global__ void k_prep(const float* __restrict__ J, const double* __restrict__ out,
+                       const double* __restrict__ pabs, int64_t n, int ni, int no,
+                       float* __restrict__ X, float* __restrict__ Y) {
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  for (int j = threadIdx.x; j < ni; j += blockDim.x) X[c * ni + j] = log10f(fmaxf(J[c * ni + j], 1e-40f));
+  const double pa = pabs[c];
+  for (int q = threadIdx.x; q < no; q += blockDim.x)
+    Y[c * no + q] = (float)log10(fmax(out[c * no + q] / pa, 1e-20));
+}
+
+// per-column mean and standard deviation (floored) of a float [n][m] matrix
+__global__ void k_colstats(const float* __restrict__ A, int64_t n, int m, float* __restrict__ mu,
+                           float* __restrict__ sd) {
+  const int col = blockIdx.x;
+  __shared__ double r1[256], r2[256];
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) s += A[r * m + col];
+  r1[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) r1[threadIdx.x] += r1[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double mean = r1[0] / (double)n;
+  double v = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const double d = A[r * m + col] - mean;
+    v += d * d;
+  }
+  r2[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) r2[threadIdx.x] += r2[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mu[col] = (float)mean;
+    sd[col] = (float)fmax(sqrt(r2[0] / (double)n), 1e-3);
+  }
+}
+
+// standardise in place and record the standardised range per column
+__global__ void k_standardise(float* __restrict__ A, int64_t n, int m, const float* __restrict__ mu,
+                              const float* __restrict__ sd, float* __restrict__ lo, float* __restrict__ hi) {
+  const int col = blockIdx.x;
+  __shared__ float rlo[256], rhi[256];
+  float a = 3e38f, b = -3e38f;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const float x = (A[r * m + col] - mu[col]) / sd[col];
+    A[r * m + col] = x;
+    a = fminf(a, x);
+    b = fmaxf(b, x);
+  }
+  rlo[threadIdx.x] = a;
+  rhi[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      rlo[threadIdx.x] = fminf(rlo[threadIdx.x], rlo[threadIdx.x + k]);
+      rhi[threadIdx.x] = fmaxf(rhi[threadIdx.x], rhi[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && lo) {
+    lo[col] = rlo[0];
+    hi[col] = rhi[0];
+  }
+}
+
 }  // namespace
 
 struct pah_mlp {
@@ -473,6 +544,22 @@ int32_t pah_mlp_train_step(pah_mlp* m, const float* X, const float* T, int32_t n
         np, lr, (float)b1, (float)b2, 1e-8f, (float)(1.0 - pow(b1, step)), (float)(1.0 - pow(b2, step)));
     e = refresh_all(m, s);
   }
+  if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_mlp_prepare(pah_mlp* m, const float* J, const double* out, const double* pabs, int64_t n,
+                        float* X, float* Y, hipStream_t s) {
+  if (!m || !J || !out || !pabs || !X || !Y || n < 2) return MCRT_E_INVALID;
+  const MlpLayout& L = m->L;
+  k_prep<<<(unsigned)n, 256, 0, s>>>(J, out, pabs, n, m->ni, m->no, X, Y);
+  k_colstats<<<m->ni, 256, 0, s>>>(X, n, m->ni, at<float>(m, L.x_mu), at<float>(m, L.x_sd));
+  k_colstats<<<m->no, 256, 0, s>>>(Y, n, m->no, at<float>(m, L.y_mu), at<float>(m, L.y_sd));
+  k_standardise<<<m->ni, 256, 0, s>>>(X, n, m->ni, at<float>(m, L.x_mu), at<float>(m, L.x_sd),
+                                      at<float>(m, L.x_lo), at<float>(m, L.x_hi));
+  k_standardise<<<m->no, 256, 0, s>>>(Y, n, m->no, at<float>(m, L.y_mu), at<float>(m, L.y_sd),
+                                      nullptr, nullptr);
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
   return MCRT_OK;
 }
