@@ -75,6 +75,16 @@ int32_t pah_solve_exact(pah_ctx *ctx, const void *J, int32_t j_is_f32, int64_t n
                         double *P_out, double *pabs_out, void *ws, uint64_t ws_bytes,
                         hipStream_t stream);
 
+/* Re-emission CDF rows for PAH absorption in the transport (paper Sec. 2: an
+ * absorbed packet is re-emitted at a new frequency; for PAHs the frequency
+ * follows the molecule's emission spectrum).  Per cell c and bin j: the
+ * continuum power out[c][n_bands + j] plus each band power out[c][b] spread
+ * over the bins in proportion to cband_b(j) dnu_j; rows[c] is the running sum
+ * normalised to end at exactly 1.  out: device double [n][n_bands + n_lambda]
+ * (as from pah_solve_exact); rows: device double [n][n_lambda], the layout of
+ * one PAH species' slice of mcrt_run_opts.pah_rows. */
+int32_t pah_build_rows(pah_ctx *ctx, const double *out, int64_t n, double *rows, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate of the exact step: a perceptron n_in -> n_h -> n_h -> n_out
  * with SiLU activations, z = W x + b per layer (W stored [out][in]).

@@ -95,6 +95,7 @@ def lib():
         L.orc_pah_solve.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp,
                                     C.c_int64, _dp, _dp, _dp, C.c_int32]
         L.orc_pah_rates.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp]
+        L.orc_pah_rows.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, C.c_int64, _dp]
         _lib = L
     return _lib
 
@@ -278,3 +279,13 @@ def pah_solve(T, U, lam_um, cabs, cband, ccont, J, n_threads: int = 1, want_P: b
     lib().orc_pah_solve(len(T), _p(T), _p(U), nl, _p(lam), _p(ca), _p(cb), nbd, _p(cc), _p(J), n,
                         _p(out), _p(P), _p(pabs), n_threads)
     return out, P, pabs
+
+
+def pah_rows(lam_um, cband, out):
+    """Re-emission CDF rows [n, nl] from solver outputs [n, n_bands + nl]."""
+    lam = np.ascontiguousarray(lam_um, np.float64)
+    cb = np.ascontiguousarray(cband, np.float64)
+    o = np.ascontiguousarray(np.atleast_2d(out), np.float64)
+    rows = np.zeros((o.shape[0], lam.size))
+    lib().orc_pah_rows(lam.size, cb.shape[0], _p(lam), _p(cb), _p(o), o.shape[0], _p(rows))
+    return rows

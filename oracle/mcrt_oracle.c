@@ -593,3 +593,37 @@ void orc_pah_solve(int32_t M, const double *T, const double *U, int32_t nl,
   }
   free(nu); free(dnu); free(em);
 }
+
+/* ------------------------------------------------------------------------ */
+/* PAH re-emission rows: a packet absorbed by a PAH species leaves at a      */
+/* wavelength drawn from the cell's PAH emission spectrum.  Per bin j:      */
+/* continuum power cont_j plus every band's power F_b spread over the bins  */
+/* in proportion to Cband_b(j) dnu_j (the band profile; the Planck factor   */
+/* varies little across a band).  The row is the normalised running sum.    */
+/* ------------------------------------------------------------------------ */
+void orc_pah_rows(int32_t nl, int32_t n_bands, const double *lam_um, const double *cband,
+                  const double *out, int64_t n, double *rows) {
+  double *nu = (double *)malloc(sizeof(double) * nl), *dnu = (double *)malloc(sizeof(double) * nl);
+  orc_lambda_bins(nl, lam_um, nu, dnu);
+  double *w = (double *)malloc(sizeof(double) * (size_t)n_bands * nl);
+  for (int b = 0; b < n_bands; ++b) {
+    double tot = 0.0;
+    for (int j = 0; j < nl; ++j) tot += cband[(int64_t)b * nl + j] * dnu[j];
+    for (int j = 0; j < nl; ++j) w[(int64_t)b * nl + j] = tot > 0.0 ? cband[(int64_t)b * nl + j] * dnu[j] / tot : 0.0;
+  }
+  const int n_out = n_bands + nl;
+  for (int64_t c = 0; c < n; ++c) {
+    const double *o = out + c * n_out;
+    double *r = rows + c * nl;
+    double cum = 0.0;
+    for (int j = 0; j < nl; ++j) {
+      double e = o[n_bands + j];
+      for (int b = 0; b < n_bands; ++b) e += o[b] * w[(int64_t)b * nl + j];
+      cum += e;
+      r[j] = cum;
+    }
+    for (int j = 0; j < nl; ++j) r[j] = cum > 0.0 ? r[j] / cum : 1.0;
+    r[nl - 1] = 1.0;
+  }
+  free(nu); free(dnu); free(w);
+}

@@ -32,7 +32,7 @@ constexpr int kBk = 32;
 constexpr int kThreads = 256;
 
 struct PahLayout {
-  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, adown, em, total;
+  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, adown, em, bandw, total;
 };
 
 PahLayout pah_layout(const pah_desc& d) {
@@ -55,6 +55,7 @@ PahLayout pah_layout(const pah_desc& d) {
   L.wtop = take(8 * M * nl);
   L.adown = take(8 * M);
   L.em = take(8 * M * no);
+  L.bandw = take(8 * (uint64_t)(d.n_bands > 0 ? d.n_bands : 1) * nl);
   L.total = off;
   return L;
 }
@@ -152,6 +153,54 @@ __global__ void k_pah_em(int M, int nl, int nbd, const double* __restrict__ T,
     for (int j = 0; j < nl; ++j) s += cband[(int64_t)b * nl + j] * planck_nu(nu[j], T[i]) * dnu[j];
     em[(int64_t)i * no + b] = 4.0 * kPi * s;
   }
+}
+
+// band profile on the grid: Cband_b(j) dnu_j normalised over j
+__global__ void k_pah_bandw(int nl, const double* __restrict__ cband, const double* __restrict__ dnu,
+                            double* __restrict__ w) {
+  const int b = blockIdx.x;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) s += cband[(int64_t)b * nl + j] * dnu[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  for (int j = threadIdx.x; j < nl; j += blockDim.x)
+    w[(int64_t)b * nl + j] = tot > 0.0 ? cband[(int64_t)b * nl + j] * dnu[j] / tot : 0.0;
+}
+
+// re-emission CDF row per cell: continuum power per bin plus band powers
+// spread by their profiles, running sum normalised to end at exactly 1
+__global__ void __launch_bounds__(256) k_pah_rows(int nl, int nbd, int64_t n, const double* __restrict__ out,
+                                                  const double* __restrict__ w, double* __restrict__ rows) {
+  extern __shared__ double sc[];                 // [nl] scan buffer
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  const int no = nbd + nl;
+  const double* o = out + c * no;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
+    double e = o[nbd + j];
+    for (int b = 0; b < nbd; ++b) e += o[b] * w[(int64_t)b * nl + j];
+    sc[j] = e;
+  }
+  __syncthreads();
+  // inclusive scan (Hillis-Steele) over nl entries
+  for (int off = 1; off < nl; off <<= 1) {
+    double v[16];
+    int cnt = 0;
+    for (int j = threadIdx.x; j < nl; j += blockDim.x) v[cnt++] = j >= off ? sc[j - off] : 0.0;
+    __syncthreads();
+    cnt = 0;
+    for (int j = threadIdx.x; j < nl; j += blockDim.x) sc[j] += v[cnt++];
+    __syncthreads();
+  }
+  const double tot = sc[nl - 1];
+  for (int j = threadIdx.x; j < nl; j += blockDim.x)
+    rows[c * nl + j] = (j == nl - 1 || !(tot > 0.0)) ? 1.0 : sc[j] / tot;
 }
 
 struct SolveP {
@@ -441,6 +490,7 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
                                                          D(L.wtop));
   k_pah_em<<<M, 256, 0, s>>>(M, nl, d.n_bands, d.T, d.U, D(L.nu), D(L.dnu), d.cabs, d.cband, d.ccont,
                              D(L.adown), D(L.em));
+  if (d.n_bands > 0) k_pah_bandw<<<d.n_bands, 256, 0, s>>>(nl, d.cband, D(L.dnu), D(L.bandw));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah table launch: ") + hipGetErrorString(e));
   c->built = true;
@@ -481,6 +531,20 @@ int32_t pah_solve_exact(pah_ctx* c, const void* J, int32_t j_is_f32, int64_t n, 
   k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah solve launch: ") + hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, hipStream_t s) {
+  if (!c) return MCRT_E_INVALID;
+  if (!c->built) return pfail(c, MCRT_E_STATE, "rows before pah_build_tables");
+  if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
+  if (n == 0) return MCRT_OK;
+  if (!out || !rows) return pfail(c, MCRT_E_INVALID, "null out or rows");
+  if (c->d.n_lambda > 16 * 256) return pfail(c, MCRT_E_UNSUPPORTED, "n_lambda > 4096");
+  k_pah_rows<<<(unsigned)n, 256, sizeof(double) * c->d.n_lambda, s>>>(
+      c->d.n_lambda, c->d.n_bands, n, out, reinterpret_cast<const double*>(c->tables + c->lay.bandw), rows);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("rows launch: ") + hipGetErrorString(e));
   return MCRT_OK;
 }
 

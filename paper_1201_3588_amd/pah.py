@@ -29,7 +29,8 @@ def lib():
         L.pah_build_tables.argtypes = [P, P, C.c_uint64, P]
         L.pah_workspace_bytes.argtypes = [P, C.POINTER(C.c_uint64)]
         L.pah_solve_exact.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P, P, C.c_uint64, P]
-        for n in ("pah_tables_bytes", "pah_ctx_create", "pah_build_tables", "pah_workspace_bytes",
+        L.pah_build_rows.argtypes = [P, P, C.c_int64, P, P]
+        for n in ("pah_build_rows", "pah_tables_bytes", "pah_ctx_create", "pah_build_tables", "pah_workspace_bytes",
                   "pah_solve_exact"):
             getattr(L, n).restype = C.c_int32
         L._pah_ready = True
@@ -84,6 +85,13 @@ class PahSolver:
     def _check(self, rc, what):
         if rc != 0:
             raise MCRTError(rc, f"{what}: {lib().pah_last_error(self.ctx).decode()}")
+
+    def rows(self, out, rows=None):
+        """Re-emission CDF rows [n, n_lambda] (float64) from solver outputs."""
+        n = int(out.shape[0])
+        r = rows if rows is not None else torch.empty((n, self.n_lambda), dtype=torch.float64, device=self.device)
+        self._check(lib().pah_build_rows(self.ctx, _ptr(out.contiguous()), n, _ptr(r), _stream()), "pah_build_rows")
+        return r
 
     def solve(self, J: torch.Tensor, want_P=False, out=None):
         """J: [n, n_lambda] float32 or float64 device tensor -> (out [n, n_out],

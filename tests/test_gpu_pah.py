@@ -56,3 +56,14 @@ def test_float_input_and_many_cells():
     allout = s.solve(torch.as_tensor(J).cuda())[0].sum(1).cpu().numpy()
     ratio = allout / g_pabs.cpu().numpy()
     assert np.all(np.abs(ratio - 1) < 0.05)
+
+
+def test_reemission_rows_match_oracle():
+    pm = synth.pah_model(200, LAM)
+    s = pah.PahSolver.from_model(pm)
+    J = fields(40, seed=5)
+    out, _, _ = s.solve(torch.as_tensor(J).cuda())
+    rows = s.rows(out).cpu().numpy()
+    ref = oracle.pah_rows(LAM, pm.cband, out.cpu().numpy())
+    assert np.all(rows[:, -1] == 1.0)
+    assert np.max(np.abs(rows - ref)) < 1e-12

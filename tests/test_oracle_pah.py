@@ -108,3 +108,26 @@ def test_small_molecule_fluctuates_and_top_bin_empty():
     assert T[np.argmax(P[0])] < 30.0
     assert P[0][T > 500].sum() > 1e-6
     assert P[0][-1] < 1e-10 and P[1][-1] < 1e-10
+
+
+def test_reemission_rows():
+    # the row's increments add up the continuum bin powers and the band powers
+    pm = synth.pah_model(30, LAM)
+    J = synth.blackbody_field(LAM, [1e3, 1e5], [20000.0, 6000.0])
+    out, _, _ = solve(pm, J)
+    rows = oracle.pah_rows(LAM, pm.cband, out)
+    assert np.all(np.diff(rows, axis=1) >= 0) and np.all(rows[:, -1] == 1.0)
+    tot = out.sum(1)
+    pdf = np.diff(np.concatenate([np.zeros((2, 1)), rows], axis=1), axis=1)
+    nu, dnu = oracle.lambda_bins(LAM)
+    # a bin far from every band carries only its continuum power
+    far = np.argmin(np.abs(LAM - 1.0))
+    assert np.allclose(pdf[:, far] * tot, out[:, 17 + far], rtol=1e-6)
+    # bins around 11.3 um carry the 11.3 um band: integrated excess = band power share
+    b = 10
+    w = pm.cband[b] * dnu / (pm.cband[b] * dnu).sum()
+    near = w > 1e-3
+    excess = (pdf[:, near] * tot[:, None] - out[:, 17:][:, near]).sum(1)
+    others = sum(out[:, k] * (pm.cband[k] * dnu / (pm.cband[k] * dnu).sum())[near].sum()
+                 for k in range(17) if k != b)
+    assert np.allclose(excess, out[:, b] * w[near].sum() + others, rtol=1e-9)
