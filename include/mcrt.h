@@ -145,7 +145,7 @@ typedef struct {
 /* Byte offsets of the tables inside the tables buffer (for inspection). */
 typedef struct {
   uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt, Wt, xk;
-  uint64_t kext32, g32, rho_h32, level, binfo, pah_slot, scratch, total;
+  uint64_t kext32, g32, rho_h32, level, leaf_lo, binfo, pah_slot, scratch, total;
 } mcrt_table_layout;
 
 int32_t mcrt_version(void);
@@ -193,6 +193,13 @@ int32_t mcrt_temperatures(mcrt_ctx *ctx, const uint64_t *nabs, uint64_t n_total,
  * J_out: device [n_cells * n_lambda] float. */
 int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
                             float *J_out, hipStream_t stream);
+
+/* Optically thin field of the source at every leaf centre, the starting
+ * field of the PAH iteration (no dust in the way):
+ * J_nu[c][j] = L w_j / (16 pi^2 r_c^2 dnu_j), w_j the source's share of bin j,
+ * r_c the distance from the source to the leaf centre, at least half the leaf
+ * side.  J_out: device float [n_cells * n_lambda]. */
+int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
 
 /* Random-access microbenchmark defining the achievable ceiling of the
  * transport kernel's memory traffic.  mode 0: ceil(n_ops / threads) * threads

@@ -95,6 +95,7 @@ def lib():
         L.orc_pah_solve.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp,
                                     C.c_int64, _dp, _dp, _dp, C.c_int32]
         L.orc_pah_rates.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp]
+        L.orc_thin_field.argtypes = [C.POINTER(Problem), C.POINTER(Tables), _dp]
         L.orc_pah_rows.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, C.c_int64, _dp]
         _lib = L
     return _lib
@@ -245,6 +246,12 @@ class Session:
         jq = np.ascontiguousarray(jq, np.uint64).reshape(-1)
         J = np.zeros(p.n_cells * p.nl)
         lib().orc_mean_intensity(C.byref(p), C.byref(self._T), _p(jq, _u64p), _p(J))
+        return J.reshape(p.n_cells, p.nl)
+
+    def thin_field(self):
+        p = self.p
+        J = np.zeros(p.n_cells * p.nl)
+        lib().orc_thin_field(C.byref(p), C.byref(self._T), _p(J))
         return J.reshape(p.n_cells, p.nl)
 
     def locate(self, F):

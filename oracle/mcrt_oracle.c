@@ -627,3 +627,45 @@ void orc_pah_rows(int32_t nl, int32_t n_bands, const double *lam_um, const doubl
   }
   free(nu); free(dnu); free(w);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Optically thin stellar field at every leaf centre, the starting field of */
+/* the PAH iteration: J_nu,j = L w_j / (16 pi^2 r^2 dnu_j), w_j the source's */
+/* share of bin j, r the distance star - centre, at least half the side.    */
+/* ------------------------------------------------------------------------ */
+static void leaf_centres_rec(const orc_problem *p, int32_t e, int lev, int64_t lo0, int64_t lo1,
+                             int64_t lo2, double *cen, double *half) {
+  const int64_t span = (int64_t)1 << (p->L - lev);
+  if (e >= 0) {
+    const double fine = p->base_size * ldexp(1.0, -p->L);
+    cen[3 * e + 0] = p->box_min[0] + ((double)lo0 + 0.5 * (double)span) * fine;
+    cen[3 * e + 1] = p->box_min[1] + ((double)lo1 + 0.5 * (double)span) * fine;
+    cen[3 * e + 2] = p->box_min[2] + ((double)lo2 + 0.5 * (double)span) * fine;
+    half[e] = 0.5 * (double)span * fine;
+    return;
+  }
+  const int64_t h = span >> 1;
+  for (int o = 0; o < 8; ++o)
+    leaf_centres_rec(p, p->nodes[(int64_t)(-e - 1) * 8 + o], lev + 1, lo0 + (o & 1) * h,
+                     lo1 + ((o >> 1) & 1) * h, lo2 + ((o >> 2) & 1) * h, cen, half);
+}
+
+void orc_thin_field(const orc_problem *p, const orc_tables *t, double *J_out) {
+  double *cen = (double *)malloc(sizeof(double) * 3 * (size_t)p->n_cells);
+  double *half = (double *)malloc(sizeof(double) * (size_t)p->n_cells);
+  const int64_t nf = (int64_t)1 << p->L;
+  for (int64_t b = 0; b < (int64_t)p->nb * p->nb * p->nb; ++b) {
+    int64_t bx = b % p->nb, by = (b / p->nb) % p->nb, bz = b / ((int64_t)p->nb * p->nb);
+    leaf_centres_rec(p, p->base_map[b], 0, bx * nf, by * nf, bz * nf, cen, half);
+  }
+  for (int64_t c = 0; c < p->n_cells; ++c) {
+    double dx = cen[3 * c] - p->src_pos[0], dy = cen[3 * c + 1] - p->src_pos[1], dz = cen[3 * c + 2] - p->src_pos[2];
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r < half[c]) r = half[c];
+    for (int j = 0; j < p->nl; ++j) {
+      double w = t->src_cdf[j] - (j > 0 ? t->src_cdf[j - 1] : 0.0);
+      J_out[c * p->nl + j] = p->lum * w / (16.0 * PI * PI * r * r * t->dnu[j]);
+    }
+  }
+  free(cen); free(half);
+}

@@ -109,6 +109,7 @@ void orc_pah_solve(int32_t M, const double *T, const double *U, int32_t nl,
 void orc_pah_rates(int32_t M, const double *T, const double *U, int32_t nl,
                    const double *lam_um, const double *cabs, const double *J,
                    double *A_up, double *A_down);
+void orc_thin_field(const orc_problem *p, const orc_tables *t, double *J_out);
 void orc_pah_rows(int32_t nl, int32_t n_bands, const double *lam_um, const double *cband,
                   const double *out, int64_t n, double *rows);
 #ifdef __cplusplus

@@ -86,7 +86,7 @@ int32_t mcrt_table_layout_get(const mcrt_ctx* ctx, mcrt_table_layout* out) {
   if (!ctx || !out) return MCRT_E_INVALID;
   const Layout& L = ctx->lay;
   *out = mcrt_table_layout{L.nu, L.dnu, L.src_cdf, L.kext, L.albedo, L.gpar, L.sp_cdf, L.Tk, L.E,
-                           L.R, L.Bt, L.Wt, L.xk, L.kext32, L.g32, L.rho_h32, L.level, L.binfo, L.pah_slot, L.scratch,
+                           L.R, L.Bt, L.Wt, L.xk, L.kext32, L.g32, L.rho_h32, L.level, L.leaf_lo, L.binfo, L.pah_slot, L.scratch,
                            L.total};
   return MCRT_OK;
 }
@@ -165,6 +165,15 @@ int32_t mcrt_temperatures(mcrt_ctx* ctx, const uint64_t* nabs, uint64_t n_total,
   if (!nabs || !T_out || n_total == 0) return fail(ctx, MCRT_E_INVALID, "null array or n_total == 0");
   const hipError_t e = launch_temperatures(ctx, nabs, n_total, T_out, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "temperature launch");
+  return MCRT_OK;
+}
+
+int32_t mcrt_thin_field(mcrt_ctx* ctx, float* J_out, hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!ctx->tables_built) return fail(ctx, MCRT_E_STATE, "thin field before mcrt_build_tables");
+  if (!J_out) return fail(ctx, MCRT_E_INVALID, "null J_out");
+  const hipError_t e = launch_thin_field(ctx, J_out, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "thin field launch");
   return MCRT_OK;
 }
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ int cdf_search(const double* __restrict__ cdf, int n,
 
 struct Layout {
   uint64_t nu, dnu, src_cdf, kext, albedo, gpar, sp_cdf, Tk, E, R, Bt, Wt, xk;
-  uint64_t kext32, g32, rho_h32, level, binfo, pah_slot, scratch, total;
+  uint64_t kext32, g32, rho_h32, level, leaf_lo, binfo, pah_slot, scratch, total;
 };
 
 // run scratch inside the tables buffer (zeroed by a fill kernel per run)
@@ -82,6 +82,7 @@ hipError_t launch_transport(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mc
                             const mcrt_tallies& t, hipStream_t s);
 hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
                                hipStream_t s);
+hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s);
 hipError_t launch_mean_intensity(mcrt_ctx* c, const uint64_t* jq, uint64_t n_total, float* J,
                                  hipStream_t s);
 }  // namespace mcrt

@@ -101,7 +101,41 @@ __global__ void k_mean_intensity(int64_t n_cells, int nl, double h, int L, doubl
   }
 }
 
+__global__ void k_thin_field(int64_t n_cells, int nl, double h, int L, double bx, double by, double bz,
+                             double sx, double sy, double sz, double lum,
+                             const double* __restrict__ src_cdf, const double* __restrict__ dnu,
+                             const int4* __restrict__ leaf_lo, float* __restrict__ J) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cells * nl) return;
+  const int64_t c = i / nl;
+  const int j = (int)(i % nl);
+  const int4 lo = leaf_lo[c];
+  const double fine = h * ldexp(1.0, -L);
+  const double span = ldexp(1.0, L - lo.w);
+  const double dx = bx + ((double)lo.x + 0.5 * span) * fine - sx;
+  const double dy = by + ((double)lo.y + 0.5 * span) * fine - sy;
+  const double dz = bz + ((double)lo.z + 0.5 * span) * fine - sz;
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double half = 0.5 * span * fine;
+  if (r < half) r = half;
+  const double w = src_cdf[j] - (j > 0 ? src_cdf[j - 1] : 0.0);
+  J[i] = (float)(lum * w / (16.0 * kPi * kPi * r * r * dnu[j]));
+}
+
 }  // namespace
+
+hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s) {
+  const mcrt_desc& d = c->d;
+  const Layout& L = c->lay;
+  unsigned char* B = c->tables;
+  const int64_t n = d.n_cells * d.n_lambda;
+  k_thin_field<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+      d.n_cells, d.n_lambda, d.base_size, d.max_level, d.box_min[0], d.box_min[1], d.box_min[2],
+      c->src.pos[0], c->src.pos[1], c->src.pos[2], c->src.lum,
+      reinterpret_cast<const double*>(B + L.src_cdf), reinterpret_cast<const double*>(B + L.dnu),
+      reinterpret_cast<const int4*>(B + L.leaf_lo), J);
+  return hipGetLastError();
+}
 
 hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
                                hipStream_t s) {

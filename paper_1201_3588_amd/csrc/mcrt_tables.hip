@@ -105,24 +105,44 @@ __global__ void k_rows(int nl, int S, int K, const double* __restrict__ kabs,
   row[nl - 1] = 1.0;
 }
 
-// depth of every leaf (walk each base cube's subtree with an explicit stack)
+// depth and lower corner (finest units) of every leaf: walk each base cube's
+// subtree with an explicit stack
 __global__ void k_levels(int nb, int L, const int32_t* __restrict__ base_map,
-                         const int32_t* __restrict__ nodes, int8_t* __restrict__ level) {
+                         const int32_t* __restrict__ nodes, int8_t* __restrict__ level,
+                         int4* __restrict__ leaf_lo) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= (int64_t)nb * nb * nb) return;
+  const int bx = (int)(b % nb), by = (int)((b / nb) % nb), bz = (int)(b / ((int64_t)nb * nb));
   const int32_t e = base_map[b];
-  if (e >= 0) { level[e] = 0; return; }
+  if (e >= 0) {
+    level[e] = 0;
+    leaf_lo[e] = make_int4(bx << L, by << L, bz << L, 0);
+    return;
+  }
   int32_t stk_node[16];
   int8_t stk_oct[16];
+  int stk_lo[16][3];
   int sp = 0;
   stk_node[0] = -e - 1;
   stk_oct[0] = 0;
+  stk_lo[0][0] = bx << L; stk_lo[0][1] = by << L; stk_lo[0][2] = bz << L;
   while (sp >= 0) {
     if (stk_oct[sp] == 8) { --sp; continue; }
-    const int32_t c = nodes[(int64_t)stk_node[sp] * 8 + stk_oct[sp]];
+    const int o = stk_oct[sp];
+    const int32_t c = nodes[(int64_t)stk_node[sp] * 8 + o];
     stk_oct[sp] += 1;
-    if (c >= 0) level[c] = (int8_t)(sp + 1);
-    else if (sp + 1 < L && sp + 1 < 16) { ++sp; stk_node[sp] = -c - 1; stk_oct[sp] = 0; }
+    const int h = 1 << (L - sp - 1);
+    const int l0 = stk_lo[sp][0] + (o & 1) * h, l1 = stk_lo[sp][1] + ((o >> 1) & 1) * h,
+              l2 = stk_lo[sp][2] + ((o >> 2) & 1) * h;
+    if (c >= 0) {
+      level[c] = (int8_t)(sp + 1);
+      leaf_lo[c] = make_int4(l0, l1, l2, sp + 1);
+    } else if (sp + 1 < L && sp + 1 < 16) {
+      ++sp;
+      stk_node[sp] = -c - 1;
+      stk_oct[sp] = 0;
+      stk_lo[sp][0] = l0; stk_lo[sp][1] = l1; stk_lo[sp][2] = l2;
+    }
   }
 }
 
@@ -230,6 +250,7 @@ Layout make_layout(const mcrt_desc& d) {
   L.g32 = take(4 * nl);
   L.rho_h32 = take(4 * (uint64_t)d.n_cells);
   L.level = take((uint64_t)d.n_cells);
+  L.leaf_lo = take(16 * (uint64_t)d.n_cells);
   L.binfo = take(8 * (uint64_t)d.nb * d.nb * d.nb);
   L.pah_slot = take(4 * S);
   L.scratch = take(sizeof(RunScratch));
@@ -269,7 +290,8 @@ hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s) {
   k_newton_weights<<<(nl * S + 255) / 256, 256, 0, s>>>(nl, S, d.kabs, D(L.nu), D(L.dnu), D(L.Wt), D(L.xk));
   const int64_t nbase = (int64_t)d.nb * d.nb * d.nb;
   k_levels<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(d.nb, d.max_level, d.base_map, d.nodes,
-                                                            reinterpret_cast<int8_t*>(T + L.level));
+                                                            reinterpret_cast<int8_t*>(T + L.level),
+                                                            reinterpret_cast<int4*>(T + L.leaf_lo));
   k_cells<<<(unsigned)((d.n_cells + 255) / 256), 256, 0, s>>>(d.n_cells, d.base_size, d.rho,
                                                               F(L.rho_h32));
   k_binfo<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(nbase, d.base_size, d.base_map, d.rho,

@@ -55,7 +55,7 @@ class RunOpts(C.Structure):
 
 class TableLayout(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("nu", "dnu", "src_cdf", "kext", "albedo", "gpar", "sp_cdf",
-                                          "Tk", "E", "R", "Bt", "Wt", "xk", "kext32", "g32", "rho_h32", "level",
+                                          "Tk", "E", "R", "Bt", "Wt", "xk", "kext32", "g32", "rho_h32", "level", "leaf_lo",
                                           "binfo", "pah_slot", "scratch", "total")]
 
 
@@ -86,6 +86,8 @@ def lib():
         L.mcrt_run.argtypes = [P, C.c_uint64, C.c_uint64, C.POINTER(RunOpts), C.POINTER(Tallies), P]
         L.mcrt_temperatures.argtypes = [P, P, C.c_uint64, P, P]
         L.mcrt_mean_intensity.argtypes = [P, P, C.c_uint64, P, P]
+        L.mcrt_thin_field.argtypes = [P, P, P]
+        L.mcrt_thin_field.restype = C.c_int32
         for name in ("mcrt_tables_bytes", "mcrt_ctx_create", "mcrt_table_layout_get", "mcrt_build_tables",
                      "mcrt_run", "mcrt_temperatures", "mcrt_mean_intensity"):
             getattr(L, name).restype = C.c_int32
@@ -243,6 +245,11 @@ class Engine:
         J = torch.empty(self.n_cells * self.n_lambda, dtype=torch.float32, device=self.device)
         self._check(lib().mcrt_mean_intensity(self.ctx, _ptr(jq), int(n_total), _ptr(J), _stream()),
                     "mcrt_mean_intensity")
+        return J.view(self.n_cells, self.n_lambda)
+
+    def thin_field(self):
+        J = torch.empty(self.n_cells * self.n_lambda, dtype=torch.float32, device=self.device)
+        self._check(lib().mcrt_thin_field(self.ctx, _ptr(J), _stream()), "mcrt_thin_field")
         return J.view(self.n_cells, self.n_lambda)
 
     def layout(self):

@@ -463,10 +463,12 @@ def c3_gap_spiral(n_packets: int = 100_000_000, seed: int = 3, nl: int = 200,
 
 
 def small_disk(n_packets: int = 20_000, seed: int = 2, nl: int = 40, nb: int = 16,
-               n_sizes: int = 2, max_level: int = 3) -> Workload:
-    """Reduced disk with the C2 structure (nested grid, several species, HG)
-    sized for the oracle to finish in seconds."""
-    return _disk_workload(f"small_disk{nb}", nb, n_packets, seed, nl, False, False,
+               n_sizes: int = 2, max_level: int = 3, with_pah: bool = False,
+               gap_spiral: bool = False) -> Workload:
+    """Reduced disk with the C2 structure (nested grid, several species, HG;
+    optionally the C3 gap, spiral and PAH species) sized for the oracle to
+    finish in seconds."""
+    return _disk_workload(f"small_disk{nb}", nb, n_packets, seed, nl, gap_spiral, with_pah,
                           n_sizes=n_sizes, max_level=max_level)
 
 

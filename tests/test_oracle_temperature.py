@@ -69,3 +69,27 @@ def test_mean_intensity_thin_point_source():
     spec = (J[inner] * dnu).sum(0)
     main = B / B.sum() > 0.02
     assert np.allclose(spec[main] / spec.sum(), (B / B.sum())[main], rtol=0.05)
+
+
+def test_thin_field_is_the_mean_intensity_of_a_thin_medium():
+    # far from the star the analytic thin field equals the path-length estimate
+    nb = 6
+    Rb = 3.0 * AU
+    w = synth.uniform_cube(nb, 1.0, albedo=0.0, nl=50, n_packets=1000000, seed=23)
+    w.grid.box_min = np.full(3, -Rb)
+    w.grid.base_size = 2 * Rb / nb
+    w.source.pos = np.zeros(3)
+    w.source.lum = synth.L_SUN
+    w.species.kabs = np.full((1, 50), 1e-6 / w.grid.base_size)
+    w.species.ksca = np.zeros((1, 50))
+    s = oracle.Session(w, n_threads=8)
+    J = s.mean_intensity(s.transport()["jq"])
+    Jt = s.thin_field()
+    nu, dnu = oracle.lambda_bins(w.species.lam_um)
+    lo, side = w.grid.leaf_boxes_cm()
+    r = np.linalg.norm(lo + 0.5 * side[:, None], axis=1)
+    far = r > 2.5 * side[0]
+    tot, tott = (J * dnu).sum(1), (Jt * dnu).sum(1)
+    # <r^-2> over a cell differs from r_c^-2 by O((side/r)^2 / 12): a few percent here
+    assert np.all(np.abs(tot[far] / tott[far] - 1) < 0.06)
+    assert far.sum() > 50
