@@ -6,9 +6,14 @@ workload (64^3 base cubes refined 2x2x2 to depth 3 inside 1 AU = 262,480
 leaves, 3 materials x 8 grain sizes, 200 wavelengths, Henyey-Greenstein
 scattering, 1e7 packets from a 5800 K, 1 L_sun star, FP32 geometry, FP64
 tables and temperatures, path-length J tally on):
-  table build -> transport of all packets -> temperatures -> mean intensity.
-Inputs are resident in device memory before the timed region.  Prints one
-JSON line.  The CPU oracle is timed on a bounded sample for reference.
+  table build -> transport of all packets -> temperatures -> mean intensity
+  -> PAH (30 C) emission of every dusty cell from its field: surrogate network
+     with exact fallback on flagged cells -> PAH re-emission rows.
+The exact PAH solver is timed on the same cells beside the step.  The
+surrogate is trained before the timed region on exactly solved cells (the
+disk's fields plus synthetic fields).  Inputs are resident in device memory
+before the timed region.  Prints one JSON line.  The CPU oracle is timed on a
+bounded sample for reference.
 """
 from __future__ import annotations
 
@@ -34,6 +39,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=400_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--no-pah", action="store_true")
+    ap.add_argument("--train-synthetic", type=int, default=400_000)
+    ap.add_argument("--epochs", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
@@ -53,6 +61,33 @@ def main():
     tal = eng.new_tallies(tally_j=True)
     stream = torch.cuda.current_stream()
     ev = []
+    dusty = torch.as_tensor(np.nonzero(w.grid.rho > 0)[0]).cuda()
+    sur = None
+    info = {}
+    if not args.no_pah:
+        from paper_1201_3588_amd import pah
+        from paper_1201_3588_amd.surrogate import Surrogate, band_error
+        pm = synth.pah_model(30, w.species.lam_um)
+        solver = pah.PahSolver.from_model(pm)
+        sur = Surrogate(solver, batch=2048, seed=4)
+        # training cells: the disk's own fields (one pass) plus synthetic fields
+        eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
+        t_prep = time.perf_counter()
+        eng.run(tal, 0, N, N, w.seed + 101)
+        Jd = eng.mean_intensity(tal["jq"], N).index_select(0, dusty)
+        Js = torch.as_tensor(synth.pah_fields(args.train_synthetic, w.species.lam_um, seed=4)[0]
+                             .astype(np.float32)).cuda()
+        Jtr = torch.cat([Jd, Js])
+        keep = Jtr.sum(1) > 0
+        Jtr = Jtr[keep].contiguous()
+        out_tr, pabs_tr = sur.exact(Jtr)
+        hist = sur.fit(Jtr, out_tr, pabs_tr, epochs=args.epochs, lr=2e-3)
+        torch.cuda.synchronize()
+        info["surrogate_training"] = {"cells": int(Jtr.shape[0]), "epochs": args.epochs,
+                                      "loss_first": hist[0], "loss_last": hist[-1],
+                                      "setup_s": time.perf_counter() - t_prep}
+        rows = torch.empty((dusty.numel(), w.species.n_lambda), dtype=torch.float64, device="cuda")
+    pah_t = []
 
     def step():
         for v in tal.values():
@@ -66,6 +101,15 @@ def main():
         ev.append((e0, e1))
         T = eng.temperatures(tal["nabs"], N)
         J = eng.mean_intensity(tal["jq"], N)
+        if sur is not None:
+            Jc = J.index_select(0, dusty)
+            p0 = torch.cuda.Event(enable_timing=True)
+            p1 = torch.cuda.Event(enable_timing=True)
+            p0.record(stream)
+            out, ood, pabs, idx = sur.solve(Jc)
+            sur.solver.rows(out, rows=rows)
+            p1.record(stream)
+            pah_t.append((p0, p1, ood))
         return T, J
 
     for _ in range(args.warmup):
@@ -80,6 +124,29 @@ def main():
     wall = t1 - t0
     k_ms = [a.elapsed_time(b) for a, b in ev]
     k_avg = sum(k_ms) / len(k_ms) / 1e3
+    if sur is not None:
+        n_c = int(dusty.numel())
+        s_ms = [a.elapsed_time(b) for a, b, _ in pah_t]
+        s_avg = sum(s_ms) / len(s_ms) / 1e3
+        frac_ood = float((pah_t[-1][2] != 0).float().mean().item())
+        # exact solver on the same cells, and the surrogate's band error against it
+        Jc = eng.mean_intensity(tal["jq"], N).index_select(0, dusty)
+        torch.cuda.synchronize()
+        x0 = torch.cuda.Event(enable_timing=True)
+        x1 = torch.cuda.Event(enable_timing=True)
+        x0.record(stream)
+        ex, _ = sur.exact(Jc)
+        x1.record(stream)
+        pred, ood, _ = sur.predict(Jc)
+        torch.cuda.synchronize()
+        t_ex = x0.elapsed_time(x1) / 1e3
+        err = band_error(pred, ex)
+        okm = (ood == 0) & (ex[:, :17].sum(1) > 0)
+        info["pah"] = {"cells": n_c, "exact_cells_per_s": n_c / t_ex,
+                       "surrogate_in_loop_cells_per_s": n_c / s_avg,
+                       "speedup": t_ex / s_avg, "ood_fraction": frac_ood,
+                       "band_error_p95": float(torch.quantile(err[okm], 0.95).item()),
+                       "band_error_median": float(err[okm].median().item())}
     c = mcrt.u64_view(tal["counters"])
     cnt = {k: int(c[v]) for k, v in mcrt.CNT.items()}
     assert cnt["launched"] == N and cnt["launched"] == cnt["escaped"] + cnt["killed"] + cnt["terminated"]
@@ -111,6 +178,7 @@ def main():
         "transport_packets_per_s": N / k_avg,
         "transport_crossings_per_s": cnt["crossings"] / k_avg,
         "per_step_counts": cnt,
+        **info,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_transport<float>", "alg_bytes_per_launch": alg_bytes},
