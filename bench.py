@@ -80,8 +80,12 @@ def main():
         Jtr = torch.cat([Jd, Js])
         keep = Jtr.sum(1) > 0
         Jtr = Jtr[keep].contiguous()
+        print(f"bench: exact solve of {Jtr.shape[0]} training cells", file=sys.stderr, flush=True)
         out_tr, pabs_tr = sur.exact(Jtr)
-        hist = sur.fit(Jtr, out_tr, pabs_tr, epochs=args.epochs, lr=2e-3)
+        torch.cuda.synchronize()
+        print(f"bench: solved in {time.perf_counter() - t_prep:.1f} s; training", file=sys.stderr, flush=True)
+        hist = sur.fit(Jtr, out_tr, pabs_tr, epochs=args.epochs, lr=2e-3,
+                       log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         info["surrogate_training"] = {"cells": int(Jtr.shape[0]), "epochs": args.epochs,
                                       "loss_first": hist[0], "loss_last": hist[-1],
@@ -116,6 +120,8 @@ def main():
         step()
     torch.cuda.synchronize()
     ev.clear()
+    pah_t.clear()
+    print("bench: timed steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
