@@ -191,6 +191,10 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   uint64_t pid = 0, kidx = 0;
   uint32_t events = 0;
   R u0 = 0, u1 = 0, u2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0, dens = 0;
+  R r0 = 0, r1 = 0, r2 = 1;                 // 1/d (FP32 path)
+  auto set_recip = [&]() {
+    if (sizeof(R) == 4) { r0 = R(1) / d0; r1 = R(1) / d1; r2 = R(1) / d2; }
+  };
   int j = 0, cell = 0, lev = 0, lo0 = 0, lo1 = 0, lo2 = 0;
   // frequent counters in registers, rare ones in LDS
   uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
@@ -232,6 +236,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
               d0 = st * cp; d1 = st * sp; d2 = mu;
             }
             tau = -rlog((R)u24(w[3]));
+            set_recip();
             const double nf = (double)(1 << L);
             cell = locate(P, (int)floor(P.x0 * nf), (int)floor(P.y0 * nf), (int)floor(P.z0 * nf),
                           lev, lo0, lo1, lo2, dens);
@@ -265,19 +270,22 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
     R tex = (R)INFINITY;
     int ax = -1;
     {
+      // FP32: multiply by the direction's reciprocals (one rounding more than
+      // a division, well inside FP32 geometry tolerance); FP64: divide, as the
+      // definition does
       R t;
       if (d0 != R(0)) {
-        t = (d0 > R(0) ? side - u0 : -u0) / d0;
+        t = sizeof(R) == 4 ? (d0 > R(0) ? side - u0 : -u0) * r0 : (d0 > R(0) ? side - u0 : -u0) / d0;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 0; }
       }
       if (d1 != R(0)) {
-        t = (d1 > R(0) ? side - u1 : -u1) / d1;
+        t = sizeof(R) == 4 ? (d1 > R(0) ? side - u1 : -u1) * r1 : (d1 > R(0) ? side - u1 : -u1) / d1;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 1; }
       }
       if (d2 != R(0)) {
-        t = (d2 > R(0) ? side - u2 : -u2) / d2;
+        t = sizeof(R) == 4 ? (d2 > R(0) ? side - u2 : -u2) * r2 : (d2 > R(0) ? side - u2 : -u2) / d2;
         t = t < R(0) ? R(0) : t;
         if (t < tex) { tex = t; ax = 2; }
       }
@@ -319,6 +327,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
           d0 = n0; d1 = n1; d2 = n2;
         }
         bump(4);
+        set_recip();
         tau = -rlog((R)u24(w[3]));
         if (TRACE) record(P, kidx, 2, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
       } else {
@@ -363,6 +372,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
         const R mu = (R)(2.0 * u24(v[1]) - 1.0);
         const R st = rsqrt0(R(1) - mu * mu);
         d0 = st * cp; d1 = st * sp; d2 = mu;
+        set_recip();
         tau = -rlog((R)u24(w[3]));
         if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
       }

@@ -69,7 +69,7 @@ class Surrogate:
         g = torch.Generator(device=J.device)
         g.manual_seed(self.seed)
         step = 0
-        hist = []
+        hist = []                      # loss of the first batch, then at each epoch end
         for ep in range(epochs):
             perm = torch.randperm(n, generator=g, device=J.device)
             for k in range(steps_per_epoch):
@@ -77,6 +77,8 @@ class Surrogate:
                 step += 1
                 lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / total))
                 self.net.train_step(X.index_select(0, idx), Y.index_select(0, idx), lr_t, step)
+                if step == 1:
+                    hist.append(self.net.loss())
             hist.append(self.net.loss())
             if log:
                 log(f"epoch {ep} loss {hist[-1]:.5f}")
