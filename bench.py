@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--no-pah", action="store_true")
     ap.add_argument("--train-synthetic", type=int, default=400_000)
     ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
+                         "the reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
@@ -55,6 +58,12 @@ def main():
     from paper_1201_3588_amd import mcrt
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     w = synth.c2_disk(n_packets=args.packets)
     N = w.n_packets
     eng = mcrt.Engine.from_workload(w)
