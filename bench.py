@@ -42,6 +42,8 @@ def main():
     ap.add_argument("--no-pah", action="store_true")
     ap.add_argument("--train-synthetic", type=int, default=400_000)
     ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--train-passes", type=int, default=3,
+                    help="transport passes (other seeds) whose disk fields join the training set")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
                          "the reference for scaling hardware byte counters")
@@ -82,11 +84,15 @@ def main():
         # training cells: the disk's own fields (one pass) plus synthetic fields
         eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
         t_prep = time.perf_counter()
-        eng.run(tal, 0, N, N, w.seed + 101)
-        Jd = eng.mean_intensity(tal["jq"], N).index_select(0, dusty)
+        Jd = []
+        for k in range(args.train_passes):
+            for v in tal.values():
+                v.zero_()
+            eng.run(tal, 0, N, N, w.seed + 101 * (k + 1))
+            Jd.append(eng.mean_intensity(tal["jq"], N).index_select(0, dusty))
         Js = torch.as_tensor(synth.pah_fields(args.train_synthetic, w.species.lam_um, seed=4)[0]
                              .astype(np.float32)).cuda()
-        Jtr = torch.cat([Jd, Js])
+        Jtr = torch.cat(Jd + [Js])
         keep = Jtr.sum(1) > 0
         Jtr = Jtr[keep].contiguous()
         print(f"bench: exact solve of {Jtr.shape[0]} training cells", file=sys.stderr, flush=True)

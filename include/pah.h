@@ -88,7 +88,8 @@ int32_t pah_build_rows(pah_ctx *ctx, const double *out, int64_t n, double *rows,
 /* ------------------------------------------------------------------------
  * Learned surrogate of the exact step: a perceptron n_in -> n_h -> n_h -> n_out
  * with SiLU activations, z = W x + b per layer (W stored [out][in]).
- * Inputs are standardised log10 J_nu per wavelength bin; outputs standardised
+ * Inputs are standardised log10 max(J_nu, 1e-10 max_j J_nu) per wavelength bin
+ * (a Monte Carlo field has empty bins); outputs standardised
  * log10(F_q / P_abs) per output q (P_abs = absorbed power).  Products run on
  * the matrix cores with bfloat16 operands (round to nearest even) and FP32
  * accumulation; weights keep FP32 masters, updated by Adam (beta1 0.9,
@@ -120,7 +121,7 @@ int32_t pah_mlp_load(pah_mlp *m, const float *params, hipStream_t stream);
 int32_t pah_mlp_set_norm(pah_mlp *m, const float *x_mu, const float *x_sd, const float *x_lo,
                          const float *x_hi, const float *y_mu, const float *y_sd, hipStream_t stream);
 
-/* Training pairs from exactly solved cells: x = log10 max(J, 1e-40),
+/* Training pairs from exactly solved cells: x = log10 max(J, 1e-10 max_j J),
  * y = log10 max(out / pabs, 1e-20) into X [n][n_in] and Y [n][n_out]
  * (device FP32, caller-owned), then the per-column mean and sd (floored at
  * 1e-3) of both are stored as the network's normalisation, X and Y are

@@ -232,6 +232,23 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// floor of a cell's field for the log transform: 1e-10 of its largest bin (a
+// Monte Carlo field has empty bins; their exact value barely matters)
+__device__ __forceinline__ float field_floor(const float* __restrict__ Jc, int ni) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int j = threadIdx.x; j < ni; j += blockDim.x) m = fmaxf(m, Jc[j]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  const float f = fmaxf(red[0] * 1e-10f, 1e-38f);
+  __syncthreads();
+  return f;
+}
+
 // inference input: standardised log10 J in bf16, absorbed power, input range flag
 __global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const double* __restrict__ cabs,
                          const double* __restrict__ dnu, const float* __restrict__ mu,
@@ -245,10 +262,11 @@ __global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const d
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double pa = 0.0;
+  const float fl = field_floor(J + c * nl, nl);
   for (int j = threadIdx.x; j < nl; j += blockDim.x) {
     const float Jj = J[c * nl + j];
     pa += cabs[j] * (double)Jj * dnu[j];
-    const float x = (log10f(fmaxf(Jj, 1e-40f)) - mu[j]) / sd[j];
+    const float x = (log10f(fmaxf(Jj, fl)) - mu[j]) / sd[j];
     if (x < lo[j] - margin || x > hi[j] + margin) bad = 1;
     X[c * nl + j] = f2bf(x);
   }
@@ -286,13 +304,14 @@ __global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const 
   if (threadIdx.x == 0 && !(fabs(red[0] - pabs[c]) <= tol * pabs[c])) ood[c] |= 2;
 }
 
-// training pairs: x = log10 J, y = log10(F / P_abs) (floored), as floats
+// training pairs: x = log10 J (floored), y = log10(F / P_abs) (floored), as floats
 __global__ void k_prep(const float* __restrict__ J, const double* __restrict__ out,
                        const double* __restrict__ pabs, int64_t n, int ni, int no,
                        float* __restrict__ X, float* __restrict__ Y) {
   const int64_t c = blockIdx.x;
   if (c >= n) return;
-  for (int j = threadIdx.x; j < ni; j += blockDim.x) X[c * ni + j] = log10f(fmaxf(J[c * ni + j], 1e-40f));
+  const float fl = field_floor(J + c * ni, ni);
+  for (int j = threadIdx.x; j < ni; j += blockDim.x) X[c * ni + j] = log10f(fmaxf(J[c * ni + j], fl));
   const double pa = pabs[c];
   for (int q = threadIdx.x; q < no; q += blockDim.x)
     Y[c * no + q] = (float)log10(fmax(out[c * no + q] / pa, 1e-20));
