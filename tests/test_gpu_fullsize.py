@@ -1,0 +1,103 @@
+"""Parity at the benchmark's full size: the flared disk (262,480 leaves, 24
+species, 200 wavelengths) with 1e7 packets in the launch configuration that
+bench.py times.  The oracle cannot redo the whole pass, so it checks sampled
+outputs one by one and properties that hold at any size:
+  * exact integer bookkeeping of the full pass;
+  * with the pass's own absorption field frozen, sampled packet ids anywhere in
+    [0, 1e7) retrace the oracle's histories;
+  * temperatures of sampled cells and the mean intensity of every cell,
+    recomputed by the oracle from the GPU's tallies;
+  * the exact PAH solver on sampled cells' fields;
+  * 3 sigma agreement of SED and shell absorptions at 2e6 packets (frozen field).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+mcrt = pytest.importorskip("paper_1201_3588_amd.mcrt")
+
+from test_gpu_transport import _compare_traces, conservation, host, statistical_check  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def full_pass():
+    w = synth.c2_disk()
+    e = mcrt.Engine.from_workload(w)
+    e.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    tal = e.new_tallies(tally_j=True)
+    e.run(tal, 0, w.n_packets, w.n_packets, w.seed)
+    T = e.temperatures(tal["nabs"], w.n_packets)
+    J = e.mean_intensity(tal["jq"], w.n_packets)
+    torch.cuda.synchronize()
+    return w, e, host(tal), T.cpu().numpy(), J.cpu().numpy()
+
+
+def test_full_pass_bookkeeping(full_pass):
+    w, e, r, T, J = full_pass
+    conservation(r, w.n_packets)
+    c = r["counters"]
+    assert c[2] == 0                                   # nothing hit the event cap
+    assert c[6] > 5e8 and c[11] > 4e8                  # crossings, path-tally segments
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(J))
+
+
+def test_sampled_packets_retrace_oracle(full_pass):
+    w, e, r, T, J = full_pass
+    frozen = r["nabs"].reshape(w.grid.n_cells, w.species.n_species)
+    s = oracle.Session(w, frozen_nabs=frozen)
+    ids = np.linspace(0, w.n_packets - 1, 160).astype(np.int64)
+    same = 0
+    for pid in ids:
+        tal = e.new_tallies(tally_j=True)
+        gt = e.run(tal, int(pid), 1, w.n_packets, w.seed, frozen_nabs=frozen, trace_cap=400,
+                   flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+        ot = s.transport(int(pid), 1, trace_cap=400)["trace"]
+        same += _compare_traces(gt, ot, 1e-5, float(w.grid.nb))
+    assert same >= 0.97 * len(ids)
+
+
+def test_sampled_temperatures_and_all_intensities(full_pass):
+    w, e, r, T, J = full_pass
+    S = w.species.n_species
+    nabs = r["nabs"].reshape(w.grid.n_cells, S)
+    rng = np.random.default_rng(1)
+    hot = np.nonzero(nabs.sum(1) > 0)[0]
+    pick = rng.choice(hot, 300, replace=False)
+    sub = np.zeros_like(nabs)
+    sub[pick] = nabs[pick]
+    s = oracle.Session(w, n_threads=8)
+    To = s.temperatures(sub)
+    assert np.allclose(T[pick], To[pick], rtol=1e-11, atol=0)
+    Jo = s.mean_intensity(r["jq"])
+    assert np.allclose(J, Jo, rtol=2e-7, atol=1e-30 * Jo.max())
+
+
+def test_pah_exact_on_sampled_disk_fields(full_pass):
+    from paper_1201_3588_amd import pah
+    w, e, r, T, J = full_pass
+    dusty = np.nonzero((w.grid.rho > 0) & (J.sum(1) > 0))[0]
+    pick = np.random.default_rng(2).choice(dusty, 40, replace=False)
+    pm = synth.pah_model(30, w.species.lam_um)
+    s = pah.PahSolver.from_model(pm)
+    g_out, _, _ = s.solve(torch.as_tensor(J[pick]).cuda())
+    g_out = g_out.cpu().numpy()
+    Tg = 2.7 * (5000.0 / 2.7) ** (np.arange(500) / 499)
+    o_out, _, _ = oracle.pah_solve(Tg, pm.enthalpy(Tg), w.species.lam_um, pm.cabs, pm.cband, pm.ccont,
+                                   J[pick].astype(np.float64), n_threads=8)
+    for c in range(len(pick)):
+        m = o_out[c] > 1e-12 * o_out[c].max()
+        assert np.max(np.abs(g_out[c][m] / o_out[c][m] - 1)) < 1e-10
+
+
+def test_full_grid_statistics_frozen(full_pass):
+    w, e, r, T, J = full_pass
+    frozen = r["nabs"].reshape(w.grid.n_cells, w.species.n_species)
+    w2 = synth.c2_disk(n_packets=2_000_000)
+    res = statistical_check(w2, frozen=frozen)
+    for k in ("sed", "shells"):
+        frac, zmax, chi2, n = res[k]
+        assert n >= 5 and frac <= 0.02 and zmax < 6.0, (k, res[k])
