@@ -13,8 +13,9 @@
 //     C0    = sum_{i<f_b} P_i D^b_i
 //     Bin[f][i] = sum_{k=f}^{e_b-1} A_{k,i}  (f_b <= i < f < e_b)
 //     P_f = (C0 + Sin_f + sum_{i=f_b}^{f-1} P_i (D^b_i + Bin[f][i])) / A_{f-1,f}.
-// One 256-thread workgroup per cell (persistent grid); the in-block recurrence
-// runs on one wave with shuffle reductions.
+// Four cells per 256-thread workgroup (persistent grid): each cell-independent
+// table entry is loaded once for the four cells, and the in-block recurrence
+// of cell w runs on wave w with shuffle reductions.
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -30,9 +31,10 @@ namespace {
 
 constexpr int kBk = 32;
 constexpr int kThreads = 256;
+constexpr int kNC = 4;             // cells per workgroup
 
 struct PahLayout {
-  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, adown, em, bandw, total;
+  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, jlim, adown, em, bandw, total;
 };
 
 PahLayout pah_layout(const pah_desc& d) {
@@ -53,6 +55,7 @@ PahLayout pah_layout(const pah_desc& d) {
   L.wup = take(8 * M * M);
   L.jb = take(2 * M * M);
   L.wtop = take(8 * M * nl);
+  L.jlim = take(4 * M);
   L.adown = take(8 * M);
   L.em = take(8 * M * no);
   L.bandw = take(8 * (uint64_t)(d.n_bands > 0 ? d.n_bands : 1) * nl);
@@ -108,6 +111,17 @@ __global__ void k_pah_up(int M, int nl, const double* __restrict__ U, const doub
   }
   wup[q] = w;
   jb[q] = (uint16_t)bin;
+}
+
+// number of leading wavelength bins that reach the top bin from state i
+// (photon energy falls with the bin index, so the overlapping bins lead)
+__global__ void k_pah_jlim(int M, int nl, const double* __restrict__ wtop, int* __restrict__ jlim) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int last = 0;
+  for (int j = 0; j < nl; ++j)
+    if (wtop[(int64_t)i * nl + j] != 0.0) last = j + 1;
+  jlim[i] = last;
 }
 
 // top bin: integral over every jump at or above its lower edge
@@ -212,6 +226,7 @@ struct SolveP {
   const double* wup;
   const uint16_t* jb;
   const double* wtop;
+  const int* jlim;
   const double* adown;
   const double* em;
   double* out;
@@ -228,78 +243,115 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// sum over the workgroup (all threads get the result); red: >= 4 doubles
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum_d(v);
+// sums of kNC per-thread values over the workgroup; every thread gets all
+// kNC results in out[]
+__device__ __forceinline__ void block_sum_nc(const double* v, double* red, double* out) {
   const int w = threadIdx.x >> 6;
+  double x[kNC];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) x[c] = wave_sum_d(v[c]);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) red[w * kNC + c] = x[c];
   __syncthreads();
-  double s = 0.0;
-  for (int k = 0; k < kThreads / 64; ++k) s += red[k];
-  return s;
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < kThreads / 64; ++k) s += red[k * kNC + c];
+    out[c] = s;
+  }
 }
 
+// kNC cells per workgroup: every cell-independent table entry is loaded once
+// and applied to kNC cells; the in-block recurrence of cell w runs on wave w.
 __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
   extern __shared__ double sm[];
   const int M = P.M, nl = P.nl, nbd = P.nbd, nblk = P.nblk;
   const int no = nbd + nl;
-  double* sP = sm;                       // [M]
-  double* sTop = sP + M;                 // [M]
-  double* sCJ = sTop + M;                // [nl]
-  double* sBin = sCJ + nl;               // [kBk * kBk]
-  double* sIn = sBin + kBk * kBk;        // [kBk] -> suffix sums
-  double* red = sIn + kBk;               // [8]
-  int* sScale = reinterpret_cast<int*>(red + 8);
-  double* D = P.ws + (int64_t)blockIdx.x * nblk * M;
+  double* sP = sm;                              // [kNC][M]
+  double* sTop = sP + kNC * M;                  // [kNC][M]
+  double* sCJ = sTop + kNC * M;                 // [kNC][nl]
+  double* sBin = sCJ + kNC * nl;                // [kNC][kBk * kBk]
+  double* sIn = sBin + kNC * kBk * kBk;         // [kNC][kBk]
+  double* red = sIn + kNC * kBk;                // [4 * kNC]
+  int* sScale = reinterpret_cast<int*>(red + 4 * kNC);   // [kNC]
+  double* D = P.ws + (int64_t)blockIdx.x * kNC * nblk * M;    // [kNC][nblk][M]
   const int t = threadIdx.x;
-  const int lane = t & 63;
-
-  auto A = [&](int k, int i) -> double {
-    if (k == M - 1) return sTop[i];
-    const int64_t q = (int64_t)k * M + i;
-    return P.wup[q] * sCJ[P.jb[q]];
-  };
+  const int lane = t & 63, wave = t >> 6;
+  const double fourpi_h = 4.0 * kPi / kH;
+  (void)fourpi_h;
 
   const int64_t n_cells = P.n_dev ? *P.n_dev : P.n;
-  for (int64_t cl = blockIdx.x; cl < n_cells; cl += gridDim.x) {
-    const int64_t c = P.idx ? P.idx[cl] : cl;
-    // ---- field times cross-section, absorbed power, top-bin rates
-    for (int j = t; j < nl; j += kThreads) {
-      const double Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[c * nl + j]
-                                : reinterpret_cast<const double*>(P.J)[c * nl + j];
-      sCJ[j] = P.cabs[j] * Jj;
+  const int64_t n_groups = (n_cells + kNC - 1) / kNC;
+  for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    int64_t cell[kNC];
+    bool valid[kNC];
+#pragma unroll
+    for (int w = 0; w < kNC; ++w) {
+      const int64_t cl = grp * kNC + w;
+      valid[w] = cl < n_cells;
+      cell[w] = valid[w] ? (P.idx ? P.idx[cl] : cl) : -1;
+    }
+    // ---- field times cross-section; absorbed power (wave w: cell w)
+    for (int q = t; q < kNC * nl; q += kThreads) {
+      const int w = q / nl, j = q % nl;
+      double Jj = 0.0;
+      if (valid[w])
+        Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[cell[w] * nl + j]
+                     : reinterpret_cast<const double*>(P.J)[cell[w] * nl + j];
+      sCJ[w * nl + j] = P.cabs[j] * Jj;
     }
     __syncthreads();
-    for (int i = t; i < M; i += kThreads) {
-      double acc = 0.0;
-      const double* w = P.wtop + (int64_t)i * nl;
-      for (int j = 0; j < nl; ++j) acc += w[j] * sCJ[j];
-      sTop[i] = acc;
-    }
     {
       double pa = 0.0;
-      for (int j = t; j < nl; j += kThreads) pa += sCJ[j] * P.dnu[j];
-      pa = block_sum(pa, red);
-      if (t == 0 && P.pabs) P.pabs[c] = 4.0 * kPi * pa;
+      for (int j = lane; j < nl; j += 64) pa += sCJ[wave * nl + j] * P.dnu[j];
+      pa = wave_sum_d(pa);
+      if (wave < kNC && lane == 0 && P.pabs && valid[wave]) P.pabs[cell[wave]] = 4.0 * kPi * pa;
+    }
+    // ---- top-bin rates (only the leading bins overlap)
+    for (int i = t; i < M; i += kThreads) {
+      double acc[kNC] = {};
+      const double* wt = P.wtop + (int64_t)i * nl;
+      const int jl = P.jlim[i];
+      for (int j = 0; j < jl; ++j) {
+        const double a = wt[j];
+#pragma unroll
+        for (int w = 0; w < kNC; ++w) acc[w] += a * sCJ[w * nl + j];
+      }
+#pragma unroll
+      for (int w = 0; w < kNC; ++w) sTop[w * M + i] = acc[w];
     }
     __syncthreads();
 
-    // ---- pass 1: D^b_i, columns paired (i, M-1-i) to balance the work
+    // ---- pass 1: D^b_i for every cell, columns paired (i, M-1-i)
     for (int h = t; h < (M + 1) / 2; h += kThreads) {
       for (int side = 0; side < 2; ++side) {
         const int i = side == 0 ? h : M - 1 - h;
         if (side == 1 && i == h) break;
-        double S = 0.0;
-        D[(int64_t)(nblk - 1) * M + i] = 0.0;    // last block ends at M
+        double S[kNC] = {};
+#pragma unroll
+        for (int w = 0; w < kNC; ++w) D[((int64_t)w * nblk + nblk - 1) * M + i] = 0.0;
         for (int k = M - 1; k > i; --k) {
-          S += A(k, i);
-          // k is the first index past block b = (k-1)/kBk - 1
-          if (k > kBk && ((k - 1) % kBk) == 0) D[(int64_t)((k - 1) / kBk - 1) * M + i] = S;
+          if (k == M - 1) {
+#pragma unroll
+            for (int w = 0; w < kNC; ++w) S[w] += sTop[w * M + i];
+          } else {
+            const int64_t q = (int64_t)k * M + i;
+            const double a = P.wup[q];
+            const int jj = P.jb[q];
+#pragma unroll
+            for (int w = 0; w < kNC; ++w) S[w] += a * sCJ[w * nl + jj];
+          }
+          if (k > kBk && ((k - 1) % kBk) == 0) {
+            const int b = (k - 1) / kBk - 1;
+#pragma unroll
+            for (int w = 0; w < kNC; ++w) D[((int64_t)w * nblk + b) * M + i] = S[w];
+          }
         }
       }
     }
-    if (t == 0) { sP[0] = 1.0; *sScale = 0; }
+    if (t < kNC) { sP[t * M] = 1.0; sScale[t] = 0; }
     __syncthreads();
 
     // ---- pass 2: blocks of f upward
@@ -307,81 +359,123 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       const int fb = 1 + kBk * b;
       const int eb = fb + kBk < M ? fb + kBk : M;
       const int bk = eb - fb;
-      const double* Db = D + (int64_t)b * M;
-      // in_k for k in the block: 32 k-slots x 8 i-groups
+      // in_k for k in the block: 32 k-slots x 8 i-groups, all cells per load
       {
         const int kk = t >> 3, g = t & 7;
-        double acc = 0.0;
+        double acc[kNC] = {};
         if (kk < bk) {
           const int k = fb + kk;
-          for (int i = g; i < fb; i += 8) acc += sP[i] * A(k, i);
+          if (k == M - 1) {
+            for (int i = g; i < fb; i += 8)
+#pragma unroll
+              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * sTop[w * M + i];
+          } else {
+            for (int i = g; i < fb; i += 8) {
+              const int64_t q = (int64_t)k * M + i;
+              const double a = P.wup[q];
+              const int jj = P.jb[q];
+#pragma unroll
+              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * (a * sCJ[w * nl + jj]);
+            }
+          }
         }
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
-        acc += __shfl_xor(acc, 4);
-        if (g == 0 && kk < kBk) sIn[kk] = kk < bk ? acc : 0.0;
+#pragma unroll
+        for (int w = 0; w < kNC; ++w) {
+          acc[w] += __shfl_xor(acc[w], 1);
+          acc[w] += __shfl_xor(acc[w], 2);
+          acc[w] += __shfl_xor(acc[w], 4);
+          if (g == 0 && kk < kBk) sIn[w * kBk + kk] = kk < bk ? acc[w] : 0.0;
+        }
       }
-      // C0 = sum_{i<fb} P_i D^b_i
-      double C0 = 0.0;
-      for (int i = t; i < fb; i += kThreads) C0 += sP[i] * Db[i];
-      C0 = block_sum(C0, red);
-      // Bin[f][i] = sum_{k=f}^{eb-1} A_{k,i}: one thread per column i of the block
-      if (t < bk) {
-        const int i = fb + t;
-        double acc = 0.0;
-        for (int k = eb - 1; k > i; --k) {
-          acc += A(k, i);
-          sBin[(k - fb) * kBk + t] = acc;
+      // C0 = sum_{i<fb} P_i D^b_i, per cell
+      double C0[kNC];
+      {
+        double v[kNC] = {};
+        for (int i = t; i < fb; i += kThreads)
+#pragma unroll
+          for (int w = 0; w < kNC; ++w) v[w] += sP[w * M + i] * D[((int64_t)w * nblk + b) * M + i];
+        block_sum_nc(v, red, C0);
+      }
+      // Bin[f][i] = sum_{k=f}^{eb-1} A_{k,i}: thread (w, column)
+      if (t < kNC * kBk) {
+        const int w = t / kBk, col = t % kBk;
+        if (col < bk) {
+          const int i = fb + col;
+          double acc = 0.0;
+          for (int k = eb - 1; k > i; --k) {
+            if (k == M - 1) acc += sTop[w * M + i];
+            else {
+              const int64_t q = (int64_t)k * M + i;
+              acc += P.wup[q] * sCJ[w * nl + P.jb[q]];
+            }
+            sBin[w * kBk * kBk + (k - fb) * kBk + col] = acc;
+          }
         }
       }
       __syncthreads();
-      if (t == 0) {                      // suffix sums of in_k
+      if (t < kNC) {                       // suffix sums of in_k
         double acc = 0.0;
-        for (int kk = bk - 1; kk >= 0; --kk) { acc += sIn[kk]; sIn[kk] = acc; }
+        for (int kk = bk - 1; kk >= 0; --kk) { acc += sIn[t * kBk + kk]; sIn[t * kBk + kk] = acc; }
       }
       __syncthreads();
-      // sequential recurrence on wave 0; lane l holds P_{fb+l}
-      if (t < 64) {
+      // sequential recurrence: wave w for cell w; lane l holds P_{fb+l}
+      if (wave < kNC) {
+        const int w = wave;
+        const double* Db = D + ((int64_t)w * nblk + b) * M;
         const double Dl = lane < bk ? Db[fb + lane] : 0.0;
+        const double* bin = sBin + w * kBk * kBk;
+        const double* sin_ = sIn + w * kBk;
         double myP = 0.0;
-        int nsc = 0;                     // rescales by 2^-664 inside this block
-        double c0 = C0;
+        int nsc = 0;                       // rescales by 2^-664 inside this block
+        double c0 = C0[w];
         for (int fl = 0; fl < bk; ++fl) {
           const int f = fb + fl;
-          const double term = lane < fl ? myP * (Dl + sBin[fl * kBk + lane]) : 0.0;
+          const double term = lane < fl ? myP * (Dl + bin[fl * kBk + lane]) : 0.0;
           const double s = wave_sum_d(term);
-          const double sin_f = nsc ? ldexp(sIn[fl], -664 * nsc) : sIn[fl];
-          double Pf = (c0 + sin_f + s) / P.adown[f];
+          const double sin_f = nsc ? ldexp(sin_[fl], -664 * nsc) : sin_[fl];
+          const double Pf = (c0 + sin_f + s) / P.adown[f];
           if (lane == fl) myP = Pf;
-          if (Pf > 1e200) {               // keep the unnormalised P finite
+          if (Pf > 1e200) {                 // keep the unnormalised P finite
             ++nsc;
             if (lane <= fl) myP = ldexp(myP, -664);
             c0 = ldexp(c0, -664);
           }
         }
-        if (lane < bk) sP[fb + lane] = myP;
-        if (lane == 0) *sScale = nsc;
+        if (lane < bk) sP[w * M + fb + lane] = myP;
+        if (lane == 0) sScale[w] = nsc;
       }
       __syncthreads();
-      const int nsc = *sScale;
-      if (nsc) {
-        for (int i = t; i < fb; i += kThreads) sP[i] = ldexp(sP[i], -664 * nsc);
+      for (int q = t; q < kNC * fb; q += kThreads) {
+        const int w = q / fb, i = q % fb;
+        const int nsc = sScale[w];
+        if (nsc) sP[w * M + i] = ldexp(sP[w * M + i], -664 * nsc);
       }
       __syncthreads();
     }
 
-    // ---- normalise and emit
-    double tot = 0.0;
-    for (int i = t; i < M; i += kThreads) tot += sP[i];
-    tot = block_sum(tot, red);
-    for (int i = t; i < M; i += kThreads) sP[i] /= tot;
+    // ---- normalise (wave w: cell w) and emit
+    if (wave < kNC) {
+      double tot = 0.0;
+      for (int i = lane; i < M; i += 64) tot += sP[wave * M + i];
+      tot = wave_sum_d(tot);
+      for (int i = lane; i < M; i += 64) sP[wave * M + i] /= tot;
+    }
     __syncthreads();
     if (P.P_out)
-      for (int i = t; i < M; i += kThreads) P.P_out[c * M + i] = sP[i];
+      for (int q = t; q < kNC * M; q += kThreads) {
+        const int w = q / M, i = q % M;
+        if (valid[w]) P.P_out[cell[w] * M + i] = sP[w * M + i];
+      }
     for (int q = t; q < no; q += kThreads) {
-      double acc = 0.0;
-      for (int i = 1; i < M; ++i) acc += sP[i] * P.em[(int64_t)i * no + q];
-      P.out[c * no + q] = acc;
+      double acc[kNC] = {};
+      for (int i = 1; i < M; ++i) {
+        const double e = P.em[(int64_t)i * no + q];
+#pragma unroll
+        for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * e;
+      }
+#pragma unroll
+      for (int w = 0; w < kNC; ++w)
+        if (valid[w]) P.out[cell[w] * no + q] = acc[w];
     }
     __syncthreads();
   }
@@ -400,7 +494,8 @@ __global__ void k_compact(const uint8_t* __restrict__ ood, int64_t n, int64_t* _
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 size_t solve_lds(const pah_desc& d) {
-  return sizeof(double) * (2 * (size_t)d.M + d.n_lambda + kBk * kBk + kBk + 8) + 16;
+  return sizeof(double) * (kNC * (2 * (size_t)d.M + d.n_lambda + kBk * kBk + kBk) + 4 * kNC) +
+         sizeof(int) * kNC + 16;
 }
 
 }  // namespace
@@ -488,6 +583,7 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
   const int64_t ml = (int64_t)M * nl;
   k_pah_top<<<(unsigned)((ml + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.Ue), D(L.Elo), D(L.Ehi),
                                                          D(L.wtop));
+  k_pah_jlim<<<(M + 255) / 256, 256, 0, s>>>(M, nl, D(L.wtop), reinterpret_cast<int*>(T + L.jlim));
   k_pah_em<<<M, 256, 0, s>>>(M, nl, d.n_bands, d.T, d.U, D(L.nu), D(L.dnu), d.cabs, d.cband, d.ccont,
                              D(L.adown), D(L.em));
   if (d.n_bands > 0) k_pah_bandw<<<d.n_bands, 256, 0, s>>>(nl, d.cband, D(L.dnu), D(L.bandw));
@@ -499,7 +595,7 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
 
 int32_t pah_workspace_bytes(const pah_ctx* c, uint64_t* bytes) {
   if (!c || !bytes) return MCRT_E_INVALID;
-  *bytes = (uint64_t)c->blocks * nblocks_of(c->d.M) * c->d.M * sizeof(double);
+  *bytes = (uint64_t)c->blocks * kNC * nblocks_of(c->d.M) * c->d.M * sizeof(double);
   return MCRT_OK;
 }
 
@@ -523,11 +619,13 @@ int32_t pah_solve_exact(pah_ctx* c, const void* J, int32_t j_is_f32, int64_t n, 
   P.wup = reinterpret_cast<const double*>(T + L.wup);
   P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
   P.wtop = reinterpret_cast<const double*>(T + L.wtop);
+  P.jlim = reinterpret_cast<const int*>(T + L.jlim);
   P.adown = reinterpret_cast<const double*>(T + L.adown);
   P.em = reinterpret_cast<const double*>(T + L.em);
   P.out = out; P.P_out = P_out; P.pabs = pabs_out;
   P.ws = static_cast<double*>(ws);
-  const int64_t blocks = n < c->blocks ? n : c->blocks;
+  const int64_t groups = (n + kNC - 1) / kNC;
+  const int64_t blocks = groups < c->blocks ? groups : c->blocks;
   k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("pah solve launch: ") + hipGetErrorString(e));
@@ -570,13 +668,15 @@ int32_t pah_exact_fallback(pah_ctx* c, const float* J, int64_t n, const uint8_t*
   P.wup = reinterpret_cast<const double*>(T + L.wup);
   P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
   P.wtop = reinterpret_cast<const double*>(T + L.wtop);
+  P.jlim = reinterpret_cast<const int*>(T + L.jlim);
   P.adown = reinterpret_cast<const double*>(T + L.adown);
   P.em = reinterpret_cast<const double*>(T + L.em);
   P.out = out;
   P.ws = static_cast<double*>(ws);
   P.idx = idx;
   P.n_dev = idx + n;
-  const int64_t blocks = n < c->blocks ? n : c->blocks;
+  const int64_t groups = (n + kNC - 1) / kNC;
+  const int64_t blocks = groups < c->blocks ? groups : c->blocks;
   k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("fallback launch: ") + hipGetErrorString(e));
