@@ -163,7 +163,19 @@ def main():
         t_ex = x0.elapsed_time(x1) / 1e3
         err = band_error(pred, ex)
         okm = (ood == 0) & (ex[:, :17].sum(1) > 0)
-        info["pah"] = {"cells": n_c, "exact_cells_per_s": n_c / t_ex,
+        cpu_pah = None
+        if not args.no_cpu:
+            import oracle
+            threads = min(16, len(os.sched_getaffinity(0)))
+            sample = Jc[:: max(1, n_c // 4000)][:4000].double().cpu().numpy()
+            Tg = 2.7 * (5000.0 / 2.7) ** (np.arange(500) / 499)
+            tc0 = time.perf_counter()
+            oracle.pah_solve(Tg, pm.enthalpy(Tg), w.species.lam_um, pm.cabs, pm.cband, pm.ccont, sample,
+                             n_threads=threads)
+            cpu_pah = {"value": sample.shape[0] / (time.perf_counter() - tc0), "unit": "cells/s",
+                       "cores": threads, "kind": "oracle",
+                       "sample": f"{sample.shape[0]} of the disk's dusty cells, exact P(T) solver"}
+        info["pah"] = {"cells": n_c, "exact_cells_per_s": n_c / t_ex, "cpu_baseline_exact": cpu_pah,
                        "surrogate_in_loop_cells_per_s": n_c / s_avg,
                        "speedup": t_ex / s_avg, "ood_fraction": frac_ood,
                        "band_error_p95": float(torch.quantile(err[okm], 0.95).item()),
