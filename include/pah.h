@@ -88,9 +88,11 @@ int32_t pah_build_rows(pah_ctx *ctx, const double *out, int64_t n, double *rows,
 /* ------------------------------------------------------------------------
  * Learned surrogate of the exact step: a perceptron n_in -> n_h -> n_h -> n_out
  * with SiLU activations, z = W x + b per layer (W stored [out][in]).
- * Inputs are standardised log10 max(J_nu, 1e-10 max_j J_nu) per wavelength bin
- * (a Monte Carlo field has empty bins); outputs standardised
- * log10(F_q / P_abs) per output q (P_abs = absorbed power).  Products run on
+ * Inputs (n_in = n_lambda + 1), standardised: the share of the absorbed power
+ * in each wavelength bin, f_j = C_j J_j dnu_j / sum C J dnu (the emission per
+ * absorbed power is linear in these in the single-photon regime), and
+ * log10 P_abs (P_abs = 4 pi sum C J dnu, the field strength); outputs
+ * standardised log10(F_q / P_abs) per output q.  Products run on
  * the matrix cores with bfloat16 operands (round to nearest even) and FP32
  * accumulation; weights keep FP32 masters, updated by Adam (beta1 0.9,
  * beta2 0.999, eps 1e-8, bias-corrected), and bfloat16 working copies.
@@ -121,14 +123,15 @@ int32_t pah_mlp_load(pah_mlp *m, const float *params, hipStream_t stream);
 int32_t pah_mlp_set_norm(pah_mlp *m, const float *x_mu, const float *x_sd, const float *x_lo,
                          const float *x_hi, const float *y_mu, const float *y_sd, hipStream_t stream);
 
-/* Training pairs from exactly solved cells: x = log10 max(J, 1e-10 max_j J),
- * y = log10 max(out / pabs, 1e-20) into X [n][n_in] and Y [n][n_out]
- * (device FP32, caller-owned), then the per-column mean and sd (floored at
+/* Training pairs from exactly solved cells: x = the input features above,
+ * y = log10 max(out / pabs, 1e-20), into X [n][n_in] and Y [n][n_out]
+ * (device FP32, caller-owned); then the per-column mean and sd (floored at
  * 1e-3) of both are stored as the network's normalisation, X and Y are
  * standardised in place and the standardised range of X is recorded.
- * J: device float [n][n_in]; out, pabs: as returned by pah_solve_exact. */
-int32_t pah_mlp_prepare(pah_mlp *m, const float *J, const double *out, const double *pabs, int64_t n,
-                        float *X, float *Y, hipStream_t stream);
+ * J: device float [n][n_lambda]; out, pabs: as returned by pah_solve_exact;
+ * ctx: the PAH model (its tables built) the network is for. */
+int32_t pah_mlp_prepare(pah_mlp *m, const pah_ctx *ctx, const float *J, const double *out,
+                        const double *pabs, int64_t n, float *X, float *Y, hipStream_t stream);
 
 /* Forward pass on standardised inputs X [n][n_in] (device FP32, rounded to
  * bfloat16), writing standardised outputs Y [n][n_out] (device FP32); n <= batch. */

@@ -232,24 +232,33 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// floor of a cell's field for the log transform: 1e-10 of its largest bin (a
-// Monte Carlo field has empty bins; their exact value barely matters)
-__device__ __forceinline__ float field_floor(const float* __restrict__ Jc, int ni) {
-  __shared__ float red[256];
-  float m = 0.0f;
-  for (int j = threadIdx.x; j < ni; j += blockDim.x) m = fmaxf(m, Jc[j]);
-  red[threadIdx.x] = m;
+// network inputs of one cell: the share of the absorbed power in each
+// wavelength bin, f_j = C_j J_j dnu_j / sum_j' C J dnu (the emission per
+// absorbed power is linear in these while single photons heat the molecule),
+// then log10 of the absorbed power 4 pi sum C J dnu (the field strength, which
+// governs multi-photon heating).  Returns the absorbed power.
+__device__ __forceinline__ double cell_features(const float* __restrict__ Jc, int nl,
+                                                const double* __restrict__ cabs,
+                                                const double* __restrict__ dnu, float* x) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) s += cabs[j] * (double)Jc[j] * dnu[j];
+  red[threadIdx.x] = s;
   __syncthreads();
   for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  const float f = fmaxf(red[0] * 1e-10f, 1e-38f);
+  const double tot = red[0];
   __syncthreads();
-  return f;
+  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) x[j] = (float)(cabs[j] * (double)Jc[j] * dnu[j] * inv);
+  const double pabs = 4.0 * kPi * tot;
+  if (threadIdx.x == 0) x[nl] = (float)log10(fmax(pabs, 1e-300));
+  return pabs;
 }
 
-// inference input: standardised log10 J in bf16, absorbed power, input range flag
+// inference input: standardised features in bf16, absorbed power, range flag
 __global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const double* __restrict__ cabs,
                          const double* __restrict__ dnu, const float* __restrict__ mu,
                          const float* __restrict__ sd, const float* __restrict__ lo,
@@ -257,27 +266,20 @@ __global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const d
                          double* __restrict__ pabs, uint8_t* __restrict__ ood) {
   const int64_t c = blockIdx.x;
   if (c >= n) return;
-  __shared__ double red[256];
+  extern __shared__ float xs[];                 // [nl + 1]
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
+  const double pa = cell_features(J + c * nl, nl, cabs, dnu, xs);
   __syncthreads();
-  double pa = 0.0;
-  const float fl = field_floor(J + c * nl, nl);
-  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
-    const float Jj = J[c * nl + j];
-    pa += cabs[j] * (double)Jj * dnu[j];
-    const float x = (log10f(fmaxf(Jj, fl)) - mu[j]) / sd[j];
+  const int ni = nl + 1;
+  for (int j = threadIdx.x; j < ni; j += blockDim.x) {
+    const float x = (xs[j] - mu[j]) / sd[j];
     if (x < lo[j] - margin || x > hi[j] + margin) bad = 1;
-    X[c * nl + j] = f2bf(x);
+    X[c * ni + j] = f2bf(x);
   }
-  red[threadIdx.x] = pa;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    pabs[c] = 4.0 * kPi * red[0];
+    pabs[c] = pa;
     ood[c] = bad ? 1 : 0;
   }
 }
@@ -304,14 +306,14 @@ __global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const 
   if (threadIdx.x == 0 && !(fabs(red[0] - pabs[c]) <= tol * pabs[c])) ood[c] |= 2;
 }
 
-// training pairs: x = log10 J (floored), y = log10(F / P_abs) (floored), as floats
+// training pairs: x = cell features, y = log10(F / P_abs) (floored), as floats
 __global__ void k_prep(const float* __restrict__ J, const double* __restrict__ out,
-                       const double* __restrict__ pabs, int64_t n, int ni, int no,
+                       const double* __restrict__ pabs, int64_t n, int nl, int no,
+                       const double* __restrict__ cabs, const double* __restrict__ dnu,
                        float* __restrict__ X, float* __restrict__ Y) {
   const int64_t c = blockIdx.x;
   if (c >= n) return;
-  const float fl = field_floor(J + c * ni, ni);
-  for (int j = threadIdx.x; j < ni; j += blockDim.x) X[c * ni + j] = log10f(fmaxf(J[c * ni + j], fl));
+  cell_features(J + c * nl, nl, cabs, dnu, X + c * (nl + 1));
   const double pa = pabs[c];
   for (int q = threadIdx.x; q < no; q += blockDim.x)
     Y[c * no + q] = (float)log10(fmax(out[c * no + q] / pa, 1e-20));
@@ -567,11 +569,16 @@ int32_t pah_mlp_train_step(pah_mlp* m, const float* X, const float* T, int32_t n
   return MCRT_OK;
 }
 
-int32_t pah_mlp_prepare(pah_mlp* m, const float* J, const double* out, const double* pabs, int64_t n,
-                        float* X, float* Y, hipStream_t s) {
-  if (!m || !J || !out || !pabs || !X || !Y || n < 2) return MCRT_E_INVALID;
+int32_t pah_mlp_prepare(pah_mlp* m, const pah_ctx* ctx, const float* J, const double* out,
+                        const double* pabs, int64_t n, float* X, float* Y, hipStream_t s) {
+  if (!m || !ctx || !J || !out || !pabs || !X || !Y || n < 2) return MCRT_E_INVALID;
+  const pah_desc& d = pah_ctx_desc(ctx);
+  if (d.n_lambda + 1 != m->ni || d.n_bands + d.n_lambda != m->no)
+    return mfail(m, MCRT_E_INVALID, "network shape does not match the PAH model");
+  const double* dnu = pah_ctx_dnu(ctx);
+  if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
   const MlpLayout& L = m->L;
-  k_prep<<<(unsigned)n, 256, 0, s>>>(J, out, pabs, n, m->ni, m->no, X, Y);
+  k_prep<<<(unsigned)n, 256, 0, s>>>(J, out, pabs, n, d.n_lambda, m->no, d.cabs, dnu, X, Y);
   k_colstats<<<m->ni, 256, 0, s>>>(X, n, m->ni, at<float>(m, L.x_mu), at<float>(m, L.x_sd));
   k_colstats<<<m->no, 256, 0, s>>>(Y, n, m->no, at<float>(m, L.y_mu), at<float>(m, L.y_sd));
   k_standardise<<<m->ni, 256, 0, s>>>(X, n, m->ni, at<float>(m, L.x_mu), at<float>(m, L.x_sd),
@@ -589,14 +596,14 @@ int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int6
   if (!m || !ctx || !J || !out || !ood || !pabs) return MCRT_E_INVALID;
   if (n < 0) return mfail(m, MCRT_E_INVALID, "n < 0");
   const pah_desc& d = pah_ctx_desc(ctx);
-  if (d.n_lambda != m->ni || d.n_bands + d.n_lambda != m->no)
+  if (d.n_lambda + 1 != m->ni || d.n_bands + d.n_lambda != m->no)
     return mfail(m, MCRT_E_INVALID, "network shape does not match the PAH model");
   const double* dnu = pah_ctx_dnu(ctx);
   if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
   const MlpLayout& L = m->L;
   for (int64_t c0 = 0; c0 < n; c0 += m->batch) {
     const int64_t nc = n - c0 < m->batch ? n - c0 : m->batch;
-    k_mlp_in<<<(unsigned)nc, 256, 0, s>>>(J + c0 * m->ni, nc, m->ni, d.cabs, dnu, at<float>(m, L.x_mu),
+    k_mlp_in<<<(unsigned)nc, 256, sizeof(float) * m->ni, s>>>(J + c0 * d.n_lambda, nc, d.n_lambda, d.cabs, dnu, at<float>(m, L.x_mu),
                                            at<float>(m, L.x_sd), at<float>(m, L.x_lo), at<float>(m, L.x_hi),
                                            in_margin, at<uint16_t>(m, L.X16), pabs + c0, ood + c0);
     hipError_t e = forward(m, nc, at<uint16_t>(m, L.X16), at<float>(m, L.Y), s);

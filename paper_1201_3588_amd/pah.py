@@ -129,7 +129,7 @@ def _mlp_lib():
         L.pah_mlp_train_step.argtypes = [P, P, P, C.c_int32, C.c_float, C.c_int32, P]
         L.pah_surrogate_infer.argtypes = [P, P, P, C.c_int64, P, P, P, C.c_float, C.c_float, P]
         L.pah_exact_fallback.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_uint64, P]
-        L.pah_mlp_prepare.argtypes = [P, P, P, P, C.c_int64, P, P, P]
+        L.pah_mlp_prepare.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
         for n in ("pah_mlp_prepare", "pah_mlp_state_bytes", "pah_mlp_create", "pah_mlp_offsets", "pah_mlp_load",
                   "pah_mlp_set_norm", "pah_mlp_forward", "pah_mlp_train_step", "pah_surrogate_infer",
                   "pah_exact_fallback"):
@@ -205,13 +205,13 @@ class PahMLP:
         self._check(_mlp_lib().pah_mlp_set_norm(self.h, *[_ptr(t) for t in ts], _stream()), "set_norm")
         torch.cuda.current_stream().synchronize()
 
-    def prepare(self, J, out, pabs):
+    def prepare(self, solver, J, out, pabs):
         """Standardised training pairs (X, Y) from solved cells; sets the normalisation."""
         n = int(J.shape[0])
         X = torch.empty((n, self.n_in), dtype=torch.float32, device=self.device)
         Y = torch.empty((n, self.n_out), dtype=torch.float32, device=self.device)
-        self._check(_mlp_lib().pah_mlp_prepare(self.h, _ptr(J.contiguous().float()), _ptr(out), _ptr(pabs), n,
-                                               _ptr(X), _ptr(Y), _stream()), "pah_mlp_prepare")
+        self._check(_mlp_lib().pah_mlp_prepare(self.h, solver.ctx, _ptr(J.contiguous().float()), _ptr(out),
+                                               _ptr(pabs), n, _ptr(X), _ptr(Y), _stream()), "pah_mlp_prepare")
         return X, Y
 
     def forward(self, X):

@@ -43,8 +43,8 @@ class Surrogate:
     def __init__(self, solver: PahSolver, n_h=256, batch=2048, seed=4):
         self.solver = solver
         self.batch = batch
-        self.net = PahMLP(solver.n_lambda, n_h, solver.n_out, batch=batch, device=solver.device)
-        self.net.load(init_params(solver.n_lambda, n_h, solver.n_out, seed))
+        self.net = PahMLP(solver.n_lambda + 1, n_h, solver.n_out, batch=batch, device=solver.device)
+        self.net.load(init_params(solver.n_lambda + 1, n_h, solver.n_out, seed))
         self.seed = seed
 
     def exact(self, J, chunk=1 << 18):
@@ -61,7 +61,7 @@ class Surrogate:
 
     def fit(self, J, out, pabs, epochs=30, lr=2e-3, log=None):
         """Train on solved cells (J float32 [n, nl] device).  Cosine learning rate."""
-        X, Y = self.net.prepare(J, out, pabs)
+        X, Y = self.net.prepare(self.solver, J, out, pabs)
         n = int(X.shape[0])
         B = self.batch
         steps_per_epoch = n // B
