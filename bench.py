@@ -189,6 +189,19 @@ def main():
     # (16 B); per absorption and per escape one 8 B atomic (16 B)
     alg_bytes = 8 * cnt["crossings"] + 16 * cnt["jseg"] + 16 * cnt["absorptions"] + 16 * cnt["escaped"]
     achieved = alg_bytes / k_avg / 1e9
+    # HBM bytes of one launch from the committed counter summary, if it was taken
+    # on the current transport kernel source
+    traffic = None
+    try:
+        import hashlib
+        src = os.path.join(ROOT, "paper_1201_3588_amd", "csrc", "mcrt_transport.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        kv = dict(l.split(": ", 1) for l in open(os.path.join(ROOT, "profiles", "transport_flared_disk_pmc.md"))
+                  if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+        if kv.get("source_sha256", "").strip() == sha and N == 10_000_000:
+            traffic = int(kv["traffic_bytes_per_launch"])
+    except OSError:
+        pass
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,
@@ -213,7 +226,7 @@ def main():
         "per_step_counts": cnt,
         **info,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_transport<float>", "alg_bytes_per_launch": alg_bytes},
     }
 
@@ -240,8 +253,8 @@ def main():
         out["random_access_ceiling"] = {
             "atomics_per_s": atom_rate, "table_bytes": n_slots * 8,
             "gbs_at_16B_per_op": atom_rate * 16 / 1e9,
-            "transport_jseg_per_s": cnt["jseg"] / k_avg,
-            "frac_of_ceiling": (alg_bytes / k_avg) / (atom_rate * 16)}
+            "transport_atomics_per_s": (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg,
+            "frac_of_ceiling": (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg / atom_rate}
         del table
 
     if not args.no_cpu:
