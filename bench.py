@@ -156,7 +156,7 @@ def main():
         x0 = torch.cuda.Event(enable_timing=True)
         x1 = torch.cuda.Event(enable_timing=True)
         x0.record(stream)
-        ex, _ = sur.exact(Jc)
+        ex, _pabs_ex = sur.exact(Jc)
         x1.record(stream)
         pred, ood, _ = sur.predict(Jc)
         torch.cuda.synchronize()
@@ -178,6 +178,10 @@ def main():
         info["pah"] = {"cells": n_c, "exact_cells_per_s": n_c / t_ex, "cpu_baseline_exact": cpu_pah,
                        "surrogate_in_loop_cells_per_s": n_c / s_avg,
                        "speedup": t_ex / s_avg, "ood_fraction": frac_ood,
+                       "ood_input_fraction": float(((ood & 1) != 0).float().mean().item()),
+                       "ood_balance_fraction": float(((ood & 2) != 0).float().mean().item()),
+                       "exact_balance_dev_p99": float(torch.quantile(
+                           (ex.sum(1) / _pabs_ex - 1).abs()[ex.sum(1) > 0], 0.99).item()),
                        "band_error_p95": float(torch.quantile(err[okm], 0.95).item()),
                        "band_error_median": float(err[okm].median().item())}
     c = mcrt.u64_view(tal["counters"])
