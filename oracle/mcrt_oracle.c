@@ -458,14 +458,19 @@ void orc_mean_intensity(const orc_problem *p, const orc_tables *t, const uint64_
 /* PAH: steady-state temperature distribution of transiently heated          */
 /* molecules (Sec. 1, Sec. 4 and Fig. 3 of the paper).                       */
 /*                                                                          */
-/* States: M enthalpy bins with centres U_i = U(T_i); bin edges halfway      */
-/* between centres (bin 0 starts at U_0, the top bin ends half a step above  */
-/* U_{M-1}).  Upward rates (photon absorption, cross-section and field        */
-/* constant in each wavelength bin):                                        */
-/*   A_{f,i} = dU_f * 4 pi C(E) J_nu(E) / (h E),  E = U_f - U_i,  f > i,      */
-/* zero when E is outside the wavelength grid; the top bin takes every jump   */
-/* at or above its lower edge (the integral of the same rate density).       */
-/* Downward rates: continuous cooling to the next lower bin,                 */
+/* States: M enthalpy bins with centres U_i = U(T_i).                        */
+/* Heating (photon absorption; cross-section and field constant in each      */
+/* wavelength bin, every photon of bin j carrying E_j = h nu_j):             */
+/*   N_j = 4 pi C_j J_j dnu_j / (h nu_j) photons per second.                 */
+/* A molecule in state i that absorbs one of them has enthalpy x = U_i + E_j;*/
+/* the transition is shared between the two bin centres around x,            */
+/* U_k <= x < U_{k+1}, with weights (U_{k+1} - x)/(U_{k+1} - U_k) on k and    */
+/* (x - U_k)/(U_{k+1} - U_k) on k+1, so the mean enthalpy gain is exactly     */
+/* E_j (the part left on k = i is no transition).  Jumps to or beyond the    */
+/* top centre go to the top bin.  Hence sum_k A_{k,i} (U_k - U_i) equals the  */
+/* absorbed power 4 pi sum_j C_j J_j dnu_j for every state whose jumps stay   */
+/* below the top, and the steady state emits what it absorbs.                */
+/* Cooling: continuous, to the next lower bin,                               */
 /*   A_{i-1,i} = 4 pi sum_j C_j B_j(T_i) dnu_j / (U_i - U_{i-1}).             */
 /* Steady state: the upward flux across the boundary below bin f equals the   */
 /* downward flux P_f A_{f-1,f}, so with B_{f,i} = sum_{k>=f} A_{k,i}:        */
@@ -474,56 +479,23 @@ void orc_mean_intensity(const orc_problem *p, const orc_tables *t, const uint64_
 /* and the continuum power per wavelength bin, per molecule (the ground bin   */
 /* emits nothing, matching its lack of a downward transition).              */
 /* ------------------------------------------------------------------------ */
-/* wavelength edges in micron, ascending: bin j spans [ed[j], ed[j+1]) */
-static void lambda_edges_um(int32_t nl, const double *lam_um, double *ed) {
-  ed[0] = lam_um[0] * lam_um[0] / sqrt(lam_um[0] * lam_um[1]);
-  for (int j = 1; j < nl; ++j) ed[j] = sqrt(lam_um[j - 1] * lam_um[j]);
-  ed[nl] = lam_um[nl - 1] * lam_um[nl - 1] / sqrt(lam_um[nl - 2] * lam_um[nl - 1]);
-}
-
-/* wavelength bin holding lambda = h c / E, or -1 outside the grid */
-static int lam_bin_of_energy(int32_t nl, const double *ed, double E) {
-  double lam = H_PLANCK * C_LIGHT / E * 1e4;   /* micron */
-  if (!(lam >= ed[0]) || lam >= ed[nl]) return -1;
-  int lo = 0, hi = nl - 1;                      /* largest j with ed[j] <= lam */
-  while (lo < hi) {
-    int mid = (lo + hi + 1) / 2;
-    if (ed[mid] <= lam) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 void orc_pah_rates(int32_t M, const double *T, const double *U, int32_t nl,
                    const double *lam_um, const double *cabs, const double *J,
                    double *A_up, double *A_down) {
   double *nu = (double *)malloc(sizeof(double) * nl), *dnu = (double *)malloc(sizeof(double) * nl);
   orc_lambda_bins(nl, lam_um, nu, dnu);
-  double *Ue = (double *)malloc(sizeof(double) * (M + 1));
-  Ue[0] = U[0];
-  for (int i = 1; i < M; ++i) Ue[i] = 0.5 * (U[i - 1] + U[i]);
-  Ue[M] = U[M - 1] + 0.5 * (U[M - 1] - U[M - 2]);
-  /* photon-energy edges of each wavelength bin */
-  double *ed = (double *)malloc(sizeof(double) * (nl + 1));
-  lambda_edges_um(nl, lam_um, ed);
-  double *Elo = (double *)malloc(sizeof(double) * nl), *Ehi = (double *)malloc(sizeof(double) * nl);
-  for (int j = 0; j < nl; ++j) {
-    Ehi[j] = H_PLANCK * C_LIGHT / (ed[j] * 1e-4);
-    Elo[j] = H_PLANCK * C_LIGHT / (ed[j + 1] * 1e-4);
-  }
   for (int64_t q = 0; q < (int64_t)M * M; ++q) A_up[q] = 0.0;
-  for (int i = 0; i < M; ++i) {
-    for (int f = i + 1; f < M - 1; ++f) {
-      double E = U[f] - U[i];
-      int j = lam_bin_of_energy(nl, ed, E);
-      if (j >= 0) A_up[(int64_t)f * M + i] = (Ue[f + 1] - Ue[f]) * 4.0 * PI * cabs[j] * J[j] / (H_PLANCK * E);
-    }
-    if (i < M - 1) {
-      double Emin = Ue[M - 1] - U[i], acc = 0.0;
-      for (int j = 0; j < nl; ++j) {
-        double a = Elo[j] > Emin ? Elo[j] : Emin;
-        if (Ehi[j] > a) acc += 4.0 * PI * cabs[j] * J[j] / H_PLANCK * log(Ehi[j] / a);
-      }
-      A_up[(int64_t)(M - 1) * M + i] = acc;
+  for (int i = 0; i < M - 1; ++i) {
+    for (int j = 0; j < nl; ++j) {
+      const double E = H_PLANCK * nu[j];
+      const double N = 4.0 * PI * cabs[j] * J[j] * dnu[j] / E;
+      const double x = U[i] + E;
+      if (x >= U[M - 1]) { A_up[(int64_t)(M - 1) * M + i] += N; continue; }
+      int k = i;                                  /* U_k <= x < U_{k+1} */
+      while (U[k + 1] <= x) ++k;
+      const double span = U[k + 1] - U[k];
+      if (k > i) A_up[(int64_t)k * M + i] += N * ((U[k + 1] - x) / span);
+      A_up[(int64_t)(k + 1) * M + i] += N * ((x - U[k]) / span);
     }
   }
   A_down[0] = 0.0;
@@ -532,7 +504,7 @@ void orc_pah_rates(int32_t M, const double *T, const double *U, int32_t nl,
     for (int j = 0; j < nl; ++j) pe += cabs[j] * orc_planck_nu(nu[j], T[i]) * dnu[j];
     A_down[i] = 4.0 * PI * pe / (U[i] - U[i - 1]);
   }
-  free(nu); free(dnu); free(Ue); free(Elo); free(Ehi); free(ed);
+  free(nu); free(dnu);
 }
 
 void orc_pah_solve(int32_t M, const double *T, const double *U, int32_t nl,
