@@ -7,12 +7,14 @@
  * the steady state of the molecule's enthalpy states, not from one temperature.
  *
  * The exact solver (pah_solve_exact), per cell and in FP64:
- *   states: M enthalpy bins, centres U_i = U(T_i), edges halfway between
- *     centres (bin 0 starts at U_0; the top bin ends half a step above U_{M-1});
- *   heating (photon absorption, cross-section and field constant per
- *     wavelength bin): A_{f,i} = dU_f 4 pi C(E) J_nu(E) / (h E), E = U_f - U_i,
- *     zero outside the wavelength grid; the top bin takes every jump at or above
- *     its lower edge (integral of the same rate density);
+ *   states: M enthalpy bins with centres U_i = U(T_i);
+ *   heating (photon absorption; cross-section and field constant per
+ *     wavelength bin, photons of bin j carrying E_j = h nu_j): the
+ *     N_j = 4 pi C_j J_j dnu_j / E_j photons per second of bin j take state i
+ *     to x = U_i + E_j, shared between the bin centres U_k <= x < U_{k+1} with
+ *     weights (U_{k+1} - x)/(U_{k+1} - U_k) on k and (x - U_k)/(U_{k+1} - U_k)
+ *     on k+1 (mean gain exactly E_j; the share left on k = i is no
+ *     transition); jumps to or past the top centre land in the top bin;
  *   cooling: continuous, to the next lower bin, A_{i-1,i} =
  *     4 pi sum_j C_j B_j(T_i) dnu_j / (U_i - U_{i-1});
  *   steady state: P_f A_{f-1,f} = sum_{i<f} P_i sum_{k>=f} A_{k,i}, P_0 = 1,
@@ -21,6 +23,9 @@
  *     sum_{i>=1} P_i 4 pi sum_j Cband_b(j) B_j(T_i) dnu_j, then n_lambda
  *     continuum powers 4 pi Ccont(j) B_j(T_i) dnu_j summed the same way
  *     (the ground bin emits nothing: it has no lower state).
+ *   With Cband summed over bands plus Ccont equal to C, the outputs add up to
+ *   the absorbed power 4 pi sum_j C_j J_j dnu_j whenever no jump passes the
+ *   top bin (the deficit is the energy of such jumps above U_{M-1}).
  * Conventions (device arrays caller-owned, async on the stream, error codes)
  * are those of mcrt.h.
  */
@@ -37,8 +42,8 @@ extern "C" {
 typedef struct pah_ctx pah_ctx;
 
 typedef struct {
-  int32_t M;                  /* enthalpy bins, 3..4096 */
-  int32_t n_lambda;           /* wavelength bins, 2..4096 */
+  int32_t M;                  /* enthalpy bins, >= 3 */
+  int32_t n_lambda;           /* wavelength bins, >= 2; M + 3 n_lambda <= 4061 */
   int32_t n_bands;            /* emission bands, 0..64 */
   int32_t pad;
   const double *T;            /* device [M] bin temperatures (K), increasing */
@@ -55,25 +60,21 @@ int32_t pah_ctx_create(const pah_desc *desc, pah_ctx **out);
 void pah_ctx_destroy(pah_ctx *ctx);
 const char *pah_last_error(const pah_ctx *ctx);
 
-/* Builds the cell-independent tables in FP64 on the device: bin frequencies
- * and widths, heating weights dU_f 4 pi / (h E) with the wavelength bin of
- * each jump E, the top-bin integrals, cooling rates and the emission of every
- * output at every state temperature.  tables: device, >= pah_tables_bytes. */
+/* Builds the cell-independent tables in FP64 on the device: bin frequencies,
+ * widths and photon energies, 1 / (U_f - U_{f-1}), the count m(f,i) of
+ * wavelength bins whose photons lift state i to U_f or beyond, cooling rates
+ * and the emission of every output at every state temperature.
+ * tables: device, >= pah_tables_bytes. */
 int32_t pah_build_tables(pah_ctx *ctx, void *tables, uint64_t tables_bytes, hipStream_t stream);
-
-/* Workspace (device, caller-owned) needed by pah_solve_exact. */
-int32_t pah_workspace_bytes(const pah_ctx *ctx, uint64_t *bytes);
 
 /* Exact steady-state P(T) and emission for n cells.
  * J: device [n][n_lambda] mean intensity J_nu (erg s^-1 cm^-2 Hz^-1 sr^-1),
  *    float when j_is_f32 != 0, else double.
  * out: device [n][n_bands + n_lambda] double (see the header comment).
  * P_out: device [n][M] double or NULL.  pabs_out: device [n] double or NULL,
- *    the absorbed power 4 pi sum_j cabs_j J_j dnu_j.
- * ws: device workspace of >= pah_workspace_bytes. */
+ *    the absorbed power 4 pi sum_j cabs_j J_j dnu_j.  Needs no scratch memory. */
 int32_t pah_solve_exact(pah_ctx *ctx, const void *J, int32_t j_is_f32, int64_t n, double *out,
-                        double *P_out, double *pabs_out, void *ws, uint64_t ws_bytes,
-                        hipStream_t stream);
+                        double *P_out, double *pabs_out, hipStream_t stream);
 
 /* Re-emission CDF rows for PAH absorption in the transport (paper Sec. 2: an
  * absorbed packet is re-emitted at a new frequency; for PAHs the frequency
@@ -157,11 +158,9 @@ int32_t pah_surrogate_infer(pah_mlp *m, const pah_ctx *ctx, const float *J, int6
 /* Exact solution for the flagged cells only: every cell c with ood[c] != 0
  * is solved by the exact solver and its row of out overwritten.  The flagged
  * cells are gathered on the device into idx (device int64 [n + 1]; idx[n]
- * receives their count), so no host round trip is needed.  ws as for
- * pah_solve_exact. */
+ * receives their count), so no host round trip is needed. */
 int32_t pah_exact_fallback(pah_ctx *ctx, const float *J, int64_t n, const uint8_t *ood,
-                           double *out, int64_t *idx, void *ws, uint64_t ws_bytes,
-                           hipStream_t stream);
+                           double *out, int64_t *idx, hipStream_t stream);
 
 #ifdef __cplusplus
 }

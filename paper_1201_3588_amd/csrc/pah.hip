@@ -2,20 +2,23 @@
 // and their band/continuum emission, per cell, in FP64 (paper Sec. 1, Sec. 4,
 // Fig. 3: P(T) depends on the strength and the hardness of the field).
 //
-// P_f A_{f-1,f} = sum_{i<f} P_i B_{f,i},  B_{f,i} = sum_{k>=f} A_{k,i}.
-// Forming B_{f,i} by running subtraction loses the hot tail to cancellation
-// and storing it costs M^2/2 doubles per cell, so the f range is cut into
-// blocks of kBk and every sum is kept positive:
-//   pass 1 (top-down): D^b_i = sum_{k >= end of block b} A_{k,i}, per block,
-//                      into a per-workgroup global scratch;
-//   pass 2 (bottom-up, block b = [f_b, e_b)):
-//     in_k  = sum_{i<f_b} P_i A_{k,i}  (k in the block),  Sin_f = sum_{k>=f} in_k
-//     C0    = sum_{i<f_b} P_i D^b_i
-//     Bin[f][i] = sum_{k=f}^{e_b-1} A_{k,i}  (f_b <= i < f < e_b)
-//     P_f = (C0 + Sin_f + sum_{i=f_b}^{f-1} P_i (D^b_i + Bin[f][i])) / A_{f-1,f}.
-// Four cells per 256-thread workgroup (persistent grid): each cell-independent
-// table entry is loaded once for the four cells, and the in-block recurrence
-// of cell w runs on wave w with shuffle reductions.
+// Heating: the N_j = 4 pi C_j J_j dnu_j / (h nu_j) photons per second of
+// wavelength bin j move a molecule from U_i to x = U_i + E_j (E_j = h nu_j),
+// shared between the two bin centres around x so that the mean gain is E_j.
+// The steady state needs only the cumulative upward rates
+//   B_{f,i} = sum_{k>=f} A_{k,i}
+//           = C[m(f,i)] + sum_{m(f,i) <= j < m(f-1,i)} N_j (U_i + E_j - U_{f-1}) / dU_f,
+// with m(f,i) = #{j : U_f <= U_i + E_j} (photon energy falls with j, so these
+// j lead) and C[m] = sum_{j<m} N_j; for i = f-1 the second sum runs over all
+// j >= m(f,i) and equals H[m] / dU_f, H[m] = sum_{j>=m} N_j E_j.  Every B is
+// thus a sum of positive terms read from two per-cell prefix arrays and a
+// cell-independent index table: no running subtraction, no per-cell matrix.
+//
+// Recurrence P_f dU_f^-1 P_em(T_f) = sum_{i<f} P_i B_{f,i}, P_0 = 1, in blocks
+// of kBk values of f: the contribution of earlier blocks (X_f) is a
+// matrix-vector product over all threads, the in-block part runs on one wave
+// per cell with the block's B entries staged in LDS.  Four cells per
+// 256-thread workgroup share every table load.
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -34,7 +37,7 @@ constexpr int kThreads = 256;
 constexpr int kNC = 4;             // cells per workgroup
 
 struct PahLayout {
-  uint64_t nu, dnu, ed, Elo, Ehi, Ue, wup, jb, wtop, jlim, adown, em, bandw, total;
+  uint64_t nu, dnu, ed, E, fac, invdu, mtab, adown, em, bandw, total;
 };
 
 PahLayout pah_layout(const pah_desc& d) {
@@ -49,13 +52,10 @@ PahLayout pah_layout(const pah_desc& d) {
   L.nu = take(8 * nl);
   L.dnu = take(8 * nl);
   L.ed = take(8 * (nl + 1));
-  L.Elo = take(8 * nl);
-  L.Ehi = take(8 * nl);
-  L.Ue = take(8 * (M + 1));
-  L.wup = take(8 * M * M);
-  L.jb = take(2 * M * M);
-  L.wtop = take(8 * M * nl);
-  L.jlim = take(4 * M);
+  L.E = take(8 * nl);
+  L.fac = take(8 * nl);
+  L.invdu = take(8 * M);
+  L.mtab = take(2 * M * M);
   L.adown = take(8 * M);
   L.em = take(8 * M * no);
   L.bandw = take(8 * (uint64_t)(d.n_bands > 0 ? d.n_bands : 1) * nl);
@@ -63,9 +63,10 @@ PahLayout pah_layout(const pah_desc& d) {
   return L;
 }
 
-// wavelength bins: centres, widths, ascending edges (micron), photon-energy edges
+// wavelength bins: centres, widths, edges (micron), photon energies and the
+// factor 4 pi dnu / (h nu) turning C J into photons per second; 1 / dU_f
 __global__ void k_pah_bins(int nl, int M, const double* __restrict__ lam, const double* __restrict__ U,
-                           double* nu, double* dnu, double* ed, double* Elo, double* Ehi, double* Ue) {
+                           double* nu, double* dnu, double* ed, double* E, double* fac, double* invdu) {
   for (int j = threadIdx.x; j <= nl; j += blockDim.x) {
     double e;
     if (j == 0) e = lam[0] * lam[0] / sqrt(lam[0] * lam[1]);
@@ -73,71 +74,33 @@ __global__ void k_pah_bins(int nl, int M, const double* __restrict__ lam, const 
     else e = sqrt(lam[j - 1] * lam[j]);
     ed[j] = e;
   }
-  for (int i = threadIdx.x; i <= M; i += blockDim.x) {
-    if (i == 0) Ue[0] = U[0];
-    else if (i == M) Ue[M] = U[M - 1] + 0.5 * (U[M - 1] - U[M - 2]);
-    else Ue[i] = 0.5 * (U[i - 1] + U[i]);
-  }
+  for (int f = threadIdx.x; f < M; f += blockDim.x) invdu[f] = f > 0 ? 1.0 / (U[f] - U[f - 1]) : 0.0;
   __syncthreads();
   for (int j = threadIdx.x; j < nl; j += blockDim.x) {
     nu[j] = kC / (lam[j] * 1e-4);
     dnu[j] = kC / (ed[j] * 1e-4) - kC / (ed[j + 1] * 1e-4);
-    Ehi[j] = kH * kC / (ed[j] * 1e-4);
-    Elo[j] = kH * kC / (ed[j + 1] * 1e-4);
+    E[j] = kH * nu[j];
+    fac[j] = 4.0 * kPi * dnu[j] / E[j];
   }
 }
 
-// heating weight and wavelength bin of every jump i -> k (k < M-1)
-__global__ void k_pah_up(int M, int nl, const double* __restrict__ U, const double* __restrict__ Ue,
-                         const double* __restrict__ ed, double* __restrict__ wup,
-                         uint16_t* __restrict__ jb) {
+// m(f,i) = number of wavelength bins whose photons lift state i to U_f or
+// beyond (a leading run of j: the photon energy falls with j); f > i only
+__global__ void k_pah_m(int M, int nl, const double* __restrict__ U, const double* __restrict__ E,
+                        uint16_t* __restrict__ mtab) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)M * M) return;
-  const int k = (int)(q / M), i = (int)(q % M);
-  double w = 0.0;
-  int bin = 0;
-  if (i < k && k < M - 1) {
-    const double E = U[k] - U[i];
-    const double lam = kH * kC / E * 1e4;   // micron
-    if (lam >= ed[0] && lam < ed[nl]) {
-      int lo = 0, hi = nl - 1;              // largest j with ed[j] <= lam
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ed[mid] <= lam) lo = mid; else hi = mid - 1;
-      }
-      bin = lo;
-      w = (Ue[k + 1] - Ue[k]) * 4.0 * kPi / (kH * E);
+  const int f = (int)(q / M), i = (int)(q % M);
+  int lo = 0;
+  if (i < f) {
+    const double Uf = U[f], Ui = U[i];
+    int hi = nl;                         // first j with U_i + E_j < U_f
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Uf <= Ui + E[mid]) lo = mid + 1; else hi = mid;
     }
   }
-  wup[q] = w;
-  jb[q] = (uint16_t)bin;
-}
-
-// number of leading wavelength bins that reach the top bin from state i
-// (photon energy falls with the bin index, so the overlapping bins lead)
-__global__ void k_pah_jlim(int M, int nl, const double* __restrict__ wtop, int* __restrict__ jlim) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  int last = 0;
-  for (int j = 0; j < nl; ++j)
-    if (wtop[(int64_t)i * nl + j] != 0.0) last = j + 1;
-  jlim[i] = last;
-}
-
-// top bin: integral over every jump at or above its lower edge
-__global__ void k_pah_top(int M, int nl, const double* __restrict__ U, const double* __restrict__ Ue,
-                          const double* __restrict__ Elo, const double* __restrict__ Ehi,
-                          double* __restrict__ wtop) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)M * nl) return;
-  const int i = (int)(q / nl), j = (int)(q % nl);
-  double w = 0.0;
-  if (i < M - 1) {
-    const double Emin = Ue[M - 1] - U[i];
-    const double a = Elo[j] > Emin ? Elo[j] : Emin;
-    if (Ehi[j] > a) w = 4.0 * kPi / kH * log(Ehi[j] / a);
-  }
-  wtop[q] = w;
+  mtab[q] = (uint16_t)lo;
 }
 
 // cooling rates and emission table
@@ -222,17 +185,16 @@ struct SolveP {
   int64_t n;
   const void* J;
   const double* cabs;
-  const double* dnu;
-  const double* wup;
-  const uint16_t* jb;
-  const double* wtop;
-  const int* jlim;
+  const double* U;
+  const double* E;
+  const double* fac;
+  const double* invdu;
+  const uint16_t* mtab;
   const double* adown;
   const double* em;
   double* out;
   double* P_out;
   double* pabs;
-  double* ws;
   const int64_t* idx;     // cells to solve (null: 0..n-1)
   const int64_t* n_dev;   // device count of idx (null: n)
 };
@@ -243,23 +205,37 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// sums of kNC per-thread values over the workgroup; every thread gets all
-// kNC results in out[]
-__device__ __forceinline__ void block_sum_nc(const double* v, double* red, double* out) {
-  const int w = threadIdx.x >> 6;
-  double x[kNC];
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ double wave_scan_d(double v, int lane) {
 #pragma unroll
-  for (int c = 0; c < kNC; ++c) x[c] = wave_sum_d(v[c]);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0)
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(v, off);
+    if (lane >= off) v += y;
+  }
+  return v;
+}
+
+// B_{f,i} (f > i) for the kNC cells of the workgroup
+__device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, const double* sC,
+                                          const double* sH, int f, int i, double* Bv) {
+  const int M = P.M, nl = P.nl;
+  const int m = P.mtab[(int64_t)f * M + i];
 #pragma unroll
-    for (int c = 0; c < kNC; ++c) red[w * kNC + c] = x[c];
-  __syncthreads();
+  for (int w = 0; w < kNC; ++w) Bv[w] = sC[w * (nl + 1) + m];
+  const double inv = P.invdu[f];
+  if (i == f - 1) {
 #pragma unroll
-  for (int c = 0; c < kNC; ++c) {
-    double s = 0.0;
-    for (int k = 0; k < kThreads / 64; ++k) s += red[k * kNC + c];
-    out[c] = s;
+    for (int w = 0; w < kNC; ++w) Bv[w] += inv * sH[w * (nl + 1) + m];
+  } else {
+    const int m1 = P.mtab[(int64_t)(f - 1) * M + i];
+    if (m1 > m) {
+      const double Ui = P.U[i], Uf1 = P.U[f - 1];
+      for (int j = m; j < m1; ++j) {
+        const double wt = ((Ui + P.E[j]) - Uf1) * inv;
+#pragma unroll
+        for (int w = 0; w < kNC; ++w) Bv[w] += wt * sN[w * nl + j];
+      }
+    }
   }
 }
 
@@ -270,17 +246,14 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
   const int M = P.M, nl = P.nl, nbd = P.nbd, nblk = P.nblk;
   const int no = nbd + nl;
   double* sP = sm;                              // [kNC][M]
-  double* sTop = sP + kNC * M;                  // [kNC][M]
-  double* sCJ = sTop + kNC * M;                 // [kNC][nl]
-  double* sBin = sCJ + kNC * nl;                // [kNC][kBk * kBk]
-  double* sIn = sBin + kNC * kBk * kBk;         // [kNC][kBk]
-  double* red = sIn + kNC * kBk;                // [4 * kNC]
-  int* sScale = reinterpret_cast<int*>(red + 4 * kNC);   // [kNC]
-  double* D = P.ws + (int64_t)blockIdx.x * kNC * nblk * M;    // [kNC][nblk][M]
+  double* sN = sP + kNC * M;                    // [kNC][nl]     photons per second
+  double* sC = sN + kNC * nl;                   // [kNC][nl + 1] sum_{j<m} N_j
+  double* sH = sC + kNC * (nl + 1);             // [kNC][nl + 1] sum_{j>=m} N_j E_j
+  double* sBin = sH + kNC * (nl + 1);           // [kNC][kBk * kBk]
+  double* sX = sBin + kNC * kBk * kBk;          // [kNC][kBk]
+  int* sScale = reinterpret_cast<int*>(sX + kNC * kBk);   // [kNC]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const double fourpi_h = 4.0 * kPi / kH;
-  (void)fourpi_h;
 
   const int64_t n_cells = P.n_dev ? *P.n_dev : P.n;
   const int64_t n_groups = (n_cells + kNC - 1) / kNC;
@@ -293,90 +266,57 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       valid[w] = cl < n_cells;
       cell[w] = valid[w] ? (P.idx ? P.idx[cl] : cl) : -1;
     }
-    // ---- field times cross-section; absorbed power (wave w: cell w)
+    // ---- photon rates of every wavelength bin
     for (int q = t; q < kNC * nl; q += kThreads) {
       const int w = q / nl, j = q % nl;
       double Jj = 0.0;
       if (valid[w])
         Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[cell[w] * nl + j]
                      : reinterpret_cast<const double*>(P.J)[cell[w] * nl + j];
-      sCJ[w * nl + j] = P.cabs[j] * Jj;
+      sN[w * nl + j] = P.cabs[j] * Jj * P.fac[j];
     }
     __syncthreads();
-    {
-      double pa = 0.0;
-      for (int j = lane; j < nl; j += 64) pa += sCJ[wave * nl + j] * P.dnu[j];
-      pa = wave_sum_d(pa);
-      if (wave < kNC && lane == 0 && P.pabs && valid[wave]) P.pabs[cell[wave]] = 4.0 * kPi * pa;
-    }
-    // ---- top-bin rates (only the leading bins overlap)
-    for (int i = t; i < M; i += kThreads) {
-      double acc[kNC] = {};
-      const double* wt = P.wtop + (int64_t)i * nl;
-      const int jl = P.jlim[i];
-      for (int j = 0; j < jl; ++j) {
-        const double a = wt[j];
-#pragma unroll
-        for (int w = 0; w < kNC; ++w) acc[w] += a * sCJ[w * nl + j];
+    // ---- prefix sums C (from the most energetic bin) and H (from the least):
+    // wave w scans cell w; H[0] is the absorbed power
+    if (wave < kNC) {
+      const int w = wave;
+      double carry = 0.0;
+      if (lane == 0) sC[w * (nl + 1)] = 0.0;
+      for (int base = 0; base < nl; base += 64) {
+        const int j = base + lane;
+        const double v = wave_scan_d(j < nl ? sN[w * nl + j] : 0.0, lane) + carry;
+        if (j < nl) sC[w * (nl + 1) + j + 1] = v;
+        carry = __shfl(v, 63);
       }
-#pragma unroll
-      for (int w = 0; w < kNC; ++w) sTop[w * M + i] = acc[w];
+      carry = 0.0;
+      if (lane == 0) sH[w * (nl + 1) + nl] = 0.0;
+      for (int base = 0; base < nl; base += 64) {
+        const int j = nl - 1 - (base + lane);
+        const double v = wave_scan_d(j >= 0 ? sN[w * nl + j] * P.E[j] : 0.0, lane) + carry;
+        if (j >= 0) sH[w * (nl + 1) + j] = v;
+        carry = __shfl(v, 63);
+      }
+      if (lane == 0 && P.pabs && valid[w]) P.pabs[cell[w]] = sH[w * (nl + 1)];
+      if (lane == 0) { sP[w * M] = 1.0; sScale[w] = 0; }
     }
     __syncthreads();
 
-    // ---- pass 1: D^b_i for every cell, columns paired (i, M-1-i)
-    for (int h = t; h < (M + 1) / 2; h += kThreads) {
-      for (int side = 0; side < 2; ++side) {
-        const int i = side == 0 ? h : M - 1 - h;
-        if (side == 1 && i == h) break;
-        double S[kNC] = {};
-#pragma unroll
-        for (int w = 0; w < kNC; ++w) D[((int64_t)w * nblk + nblk - 1) * M + i] = 0.0;
-        for (int k = M - 1; k > i; --k) {
-          if (k == M - 1) {
-#pragma unroll
-            for (int w = 0; w < kNC; ++w) S[w] += sTop[w * M + i];
-          } else {
-            const int64_t q = (int64_t)k * M + i;
-            const double a = P.wup[q];
-            const int jj = P.jb[q];
-#pragma unroll
-            for (int w = 0; w < kNC; ++w) S[w] += a * sCJ[w * nl + jj];
-          }
-          if (k > kBk && ((k - 1) % kBk) == 0) {
-            const int b = (k - 1) / kBk - 1;
-#pragma unroll
-            for (int w = 0; w < kNC; ++w) D[((int64_t)w * nblk + b) * M + i] = S[w];
-          }
-        }
-      }
-    }
-    if (t < kNC) { sP[t * M] = 1.0; sScale[t] = 0; }
-    __syncthreads();
-
-    // ---- pass 2: blocks of f upward
+    // ---- blocks of f upward
     for (int b = 0; b < nblk; ++b) {
       const int fb = 1 + kBk * b;
       const int eb = fb + kBk < M ? fb + kBk : M;
       const int bk = eb - fb;
-      // in_k for k in the block: 32 k-slots x 8 i-groups, all cells per load
+      // X_f = sum_{i<fb} P_i B_{f,i}: 32 f-slots x 8 i-groups, all cells per load
       {
         const int kk = t >> 3, g = t & 7;
         double acc[kNC] = {};
         if (kk < bk) {
-          const int k = fb + kk;
-          if (k == M - 1) {
-            for (int i = g; i < fb; i += 8)
+          const int f = fb + kk;
+          for (int i = g; i < fb; i += 8) {
+            double Bv[kNC];
+            cum_rates(P, sN, sC, sH, f, i, Bv);
 #pragma unroll
-              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * sTop[w * M + i];
-          } else {
-            for (int i = g; i < fb; i += 8) {
-              const int64_t q = (int64_t)k * M + i;
-              const double a = P.wup[q];
-              const int jj = P.jb[q];
-#pragma unroll
-              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * (a * sCJ[w * nl + jj]);
-            }
+            for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * Bv[w];
           }
         }
 #pragma unroll
@@ -384,61 +324,36 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
           acc[w] += __shfl_xor(acc[w], 1);
           acc[w] += __shfl_xor(acc[w], 2);
           acc[w] += __shfl_xor(acc[w], 4);
-          if (g == 0 && kk < kBk) sIn[w * kBk + kk] = kk < bk ? acc[w] : 0.0;
+          if (g == 0 && kk < kBk) sX[w * kBk + kk] = kk < bk ? acc[w] : 0.0;
         }
       }
-      // C0 = sum_{i<fb} P_i D^b_i, per cell
-      double C0[kNC];
-      {
-        double v[kNC] = {};
-        for (int i = t; i < fb; i += kThreads)
+      // in-block entries B_{f,i}, fb <= i < f < eb
+      for (int q = t; q < kBk * kBk; q += kThreads) {
+        const int fl = q / kBk, col = q % kBk;
+        if (col < fl && fl < bk) {
+          double Bv[kNC];
+          cum_rates(P, sN, sC, sH, fb + fl, fb + col, Bv);
 #pragma unroll
-          for (int w = 0; w < kNC; ++w) v[w] += sP[w * M + i] * D[((int64_t)w * nblk + b) * M + i];
-        block_sum_nc(v, red, C0);
-      }
-      // Bin[f][i] = sum_{k=f}^{eb-1} A_{k,i}: thread (w, column)
-      if (t < kNC * kBk) {
-        const int w = t / kBk, col = t % kBk;
-        if (col < bk) {
-          const int i = fb + col;
-          double acc = 0.0;
-          for (int k = eb - 1; k > i; --k) {
-            if (k == M - 1) acc += sTop[w * M + i];
-            else {
-              const int64_t q = (int64_t)k * M + i;
-              acc += P.wup[q] * sCJ[w * nl + P.jb[q]];
-            }
-            sBin[w * kBk * kBk + (k - fb) * kBk + col] = acc;
-          }
+          for (int w = 0; w < kNC; ++w) sBin[w * kBk * kBk + q] = Bv[w];
         }
-      }
-      __syncthreads();
-      if (t < kNC) {                       // suffix sums of in_k
-        double acc = 0.0;
-        for (int kk = bk - 1; kk >= 0; --kk) { acc += sIn[t * kBk + kk]; sIn[t * kBk + kk] = acc; }
       }
       __syncthreads();
       // sequential recurrence: wave w for cell w; lane l holds P_{fb+l}
       if (wave < kNC) {
         const int w = wave;
-        const double* Db = D + ((int64_t)w * nblk + b) * M;
-        const double Dl = lane < bk ? Db[fb + lane] : 0.0;
         const double* bin = sBin + w * kBk * kBk;
-        const double* sin_ = sIn + w * kBk;
+        const double* xs = sX + w * kBk;
         double myP = 0.0;
         int nsc = 0;                       // rescales by 2^-664 inside this block
-        double c0 = C0[w];
         for (int fl = 0; fl < bk; ++fl) {
-          const int f = fb + fl;
-          const double term = lane < fl ? myP * (Dl + bin[fl * kBk + lane]) : 0.0;
+          const double term = lane < fl ? myP * bin[fl * kBk + lane] : 0.0;
           const double s = wave_sum_d(term);
-          const double sin_f = nsc ? ldexp(sin_[fl], -664 * nsc) : sin_[fl];
-          const double Pf = (c0 + sin_f + s) / P.adown[f];
+          const double xf = nsc ? ldexp(xs[fl], -664 * nsc) : xs[fl];
+          const double Pf = (xf + s) / P.adown[fb + fl];
           if (lane == fl) myP = Pf;
           if (Pf > 1e200) {                 // keep the unnormalised P finite
             ++nsc;
             if (lane <= fl) myP = ldexp(myP, -664);
-            c0 = ldexp(c0, -664);
           }
         }
         if (lane < bk) sP[w * M + fb + lane] = myP;
@@ -494,9 +409,11 @@ __global__ void k_compact(const uint8_t* __restrict__ ood, int64_t n, int64_t* _
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 size_t solve_lds(const pah_desc& d) {
-  return sizeof(double) * (kNC * (2 * (size_t)d.M + d.n_lambda + kBk * kBk + kBk) + 4 * kNC) +
-         sizeof(int) * kNC + 16;
+  return sizeof(double) * kNC * ((size_t)d.M + 3 * (size_t)d.n_lambda + 2 + kBk * kBk + kBk) +
+         sizeof(int) * kNC;
 }
+
+constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace
 
@@ -527,9 +444,27 @@ const char* pcheck(const pah_desc* d) {
   if (d->n_bands < 0 || d->n_bands > 64) return "n_bands must be in 0..64";
   if (!d->T || !d->U || !d->lambda_um || !d->cabs || !d->ccont || (d->n_bands > 0 && !d->cband))
     return "null device array";
+  if (solve_lds(*d) > kMaxLds) return "M + 3 n_lambda exceeds the solver's LDS (at most 4061)";
   return nullptr;
 }
 int nblocks_of(int M) { return (M - 1 + kBk - 1) / kBk; }
+
+// launch parameters shared by the exact solve and the fallback
+SolveP solve_params(const pah_ctx* c) {
+  const PahLayout& L = c->lay;
+  const unsigned char* T = c->tables;
+  SolveP P{};
+  P.M = c->d.M; P.nl = c->d.n_lambda; P.nbd = c->d.n_bands; P.nblk = nblocks_of(c->d.M);
+  P.cabs = c->d.cabs;
+  P.U = c->d.U;
+  P.E = reinterpret_cast<const double*>(T + L.E);
+  P.fac = reinterpret_cast<const double*>(T + L.fac);
+  P.invdu = reinterpret_cast<const double*>(T + L.invdu);
+  P.mtab = reinterpret_cast<const uint16_t*>(T + L.mtab);
+  P.adown = reinterpret_cast<const double*>(T + L.adown);
+  P.em = reinterpret_cast<const double*>(T + L.em);
+  return P;
+}
 }  // namespace
 
 extern "C" {
@@ -575,15 +510,11 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
   unsigned char* T = c->tables;
   auto D = [&](uint64_t o) { return reinterpret_cast<double*>(T + o); };
   const int M = d.M, nl = d.n_lambda;
-  k_pah_bins<<<1, 256, 0, s>>>(nl, M, d.lambda_um, d.U, D(L.nu), D(L.dnu), D(L.ed), D(L.Elo),
-                               D(L.Ehi), D(L.Ue));
+  k_pah_bins<<<1, 256, 0, s>>>(nl, M, d.lambda_um, d.U, D(L.nu), D(L.dnu), D(L.ed), D(L.E),
+                               D(L.fac), D(L.invdu));
   const int64_t mm = (int64_t)M * M;
-  k_pah_up<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.Ue), D(L.ed), D(L.wup),
-                                                        reinterpret_cast<uint16_t*>(T + L.jb));
-  const int64_t ml = (int64_t)M * nl;
-  k_pah_top<<<(unsigned)((ml + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.Ue), D(L.Elo), D(L.Ehi),
-                                                         D(L.wtop));
-  k_pah_jlim<<<(M + 255) / 256, 256, 0, s>>>(M, nl, D(L.wtop), reinterpret_cast<int*>(T + L.jlim));
+  k_pah_m<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.E),
+                                                       reinterpret_cast<uint16_t*>(T + L.mtab));
   k_pah_em<<<M, 256, 0, s>>>(M, nl, d.n_bands, d.T, d.U, D(L.nu), D(L.dnu), d.cabs, d.cband, d.ccont,
                              D(L.adown), D(L.em));
   if (d.n_bands > 0) k_pah_bandw<<<d.n_bands, 256, 0, s>>>(nl, d.cband, D(L.dnu), D(L.bandw));
@@ -593,37 +524,17 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
   return MCRT_OK;
 }
 
-int32_t pah_workspace_bytes(const pah_ctx* c, uint64_t* bytes) {
-  if (!c || !bytes) return MCRT_E_INVALID;
-  *bytes = (uint64_t)c->blocks * kNC * nblocks_of(c->d.M) * c->d.M * sizeof(double);
-  return MCRT_OK;
-}
-
 int32_t pah_solve_exact(pah_ctx* c, const void* J, int32_t j_is_f32, int64_t n, double* out,
-                        double* P_out, double* pabs_out, void* ws, uint64_t ws_bytes, hipStream_t s) {
+                        double* P_out, double* pabs_out, hipStream_t s) {
   if (!c) return MCRT_E_INVALID;
   if (!c->built) return pfail(c, MCRT_E_STATE, "pah_solve_exact before pah_build_tables");
   if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
   if (n == 0) return MCRT_OK;
-  if (!J || !out || !ws) return pfail(c, MCRT_E_INVALID, "null J, out or workspace");
-  uint64_t need = 0;
-  pah_workspace_bytes(c, &need);
-  if (ws_bytes < need) return pfail(c, MCRT_E_CAPACITY, "workspace too small");
-  const PahLayout& L = c->lay;
-  unsigned char* T = c->tables;
-  SolveP P{};
-  P.M = c->d.M; P.nl = c->d.n_lambda; P.nbd = c->d.n_bands; P.nblk = nblocks_of(c->d.M);
+  if (!J || !out) return pfail(c, MCRT_E_INVALID, "null J or out");
+  SolveP P = solve_params(c);
   P.j_f32 = j_is_f32 ? 1 : 0;
-  P.n = n; P.J = J; P.cabs = c->d.cabs;
-  P.dnu = reinterpret_cast<const double*>(T + L.dnu);
-  P.wup = reinterpret_cast<const double*>(T + L.wup);
-  P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
-  P.wtop = reinterpret_cast<const double*>(T + L.wtop);
-  P.jlim = reinterpret_cast<const int*>(T + L.jlim);
-  P.adown = reinterpret_cast<const double*>(T + L.adown);
-  P.em = reinterpret_cast<const double*>(T + L.em);
+  P.n = n; P.J = J;
   P.out = out; P.P_out = P_out; P.pabs = pabs_out;
-  P.ws = static_cast<double*>(ws);
   const int64_t groups = (n + kNC - 1) / kNC;
   const int64_t blocks = groups < c->blocks ? groups : c->blocks;
   k_pah_solve<<<(unsigned)blocks, kThreads, solve_lds(c->d), s>>>(P);
@@ -647,32 +558,18 @@ int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, h
 }
 
 int32_t pah_exact_fallback(pah_ctx* c, const float* J, int64_t n, const uint8_t* ood, double* out,
-                           int64_t* idx, void* ws, uint64_t ws_bytes, hipStream_t s) {
+                           int64_t* idx, hipStream_t s) {
   if (!c) return MCRT_E_INVALID;
   if (!c->built) return pfail(c, MCRT_E_STATE, "fallback before pah_build_tables");
   if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
   if (n == 0) return MCRT_OK;
-  if (!J || !ood || !out || !idx || !ws) return pfail(c, MCRT_E_INVALID, "null argument");
-  uint64_t need = 0;
-  pah_workspace_bytes(c, &need);
-  if (ws_bytes < need) return pfail(c, MCRT_E_CAPACITY, "workspace too small");
+  if (!J || !ood || !out || !idx) return pfail(c, MCRT_E_INVALID, "null argument");
   k_zero_i64<<<1, 1, 0, s>>>(idx + n);
   k_compact<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ood, n, idx);
-  const PahLayout& L = c->lay;
-  unsigned char* T = c->tables;
-  SolveP P{};
-  P.M = c->d.M; P.nl = c->d.n_lambda; P.nbd = c->d.n_bands; P.nblk = nblocks_of(c->d.M);
+  SolveP P = solve_params(c);
   P.j_f32 = 1;
-  P.n = n; P.J = J; P.cabs = c->d.cabs;
-  P.dnu = reinterpret_cast<const double*>(T + L.dnu);
-  P.wup = reinterpret_cast<const double*>(T + L.wup);
-  P.jb = reinterpret_cast<const uint16_t*>(T + L.jb);
-  P.wtop = reinterpret_cast<const double*>(T + L.wtop);
-  P.jlim = reinterpret_cast<const int*>(T + L.jlim);
-  P.adown = reinterpret_cast<const double*>(T + L.adown);
-  P.em = reinterpret_cast<const double*>(T + L.em);
+  P.n = n; P.J = J;
   P.out = out;
-  P.ws = static_cast<double*>(ws);
   P.idx = idx;
   P.n_dev = idx + n;
   const int64_t groups = (n + kNC - 1) / kNC;

@@ -27,10 +27,9 @@ def lib():
         L.pah_last_error.argtypes = [P]
         L.pah_last_error.restype = C.c_char_p
         L.pah_build_tables.argtypes = [P, P, C.c_uint64, P]
-        L.pah_workspace_bytes.argtypes = [P, C.POINTER(C.c_uint64)]
-        L.pah_solve_exact.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P, P, C.c_uint64, P]
+        L.pah_solve_exact.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P, P]
         L.pah_build_rows.argtypes = [P, P, C.c_int64, P, P]
-        for n in ("pah_build_rows", "pah_tables_bytes", "pah_ctx_create", "pah_build_tables", "pah_workspace_bytes",
+        for n in ("pah_build_rows", "pah_tables_bytes", "pah_ctx_create", "pah_build_tables",
                   "pah_solve_exact"):
             getattr(L, n).restype = C.c_int32
         L._pah_ready = True
@@ -65,9 +64,6 @@ class PahSolver:
         self.tables = torch.zeros(int(nb.value), dtype=torch.uint8, device=dev)
         self._check(L.pah_build_tables(ctx, _ptr(self.tables), self.tables.numel(), _stream()),
                     "pah_build_tables")
-        wb = C.c_uint64()
-        self._check(L.pah_workspace_bytes(ctx, C.byref(wb)), "workspace")
-        self.ws = torch.empty(int(wb.value), dtype=torch.uint8, device=dev)
 
     @classmethod
     def from_model(cls, pm, M=500, T_lo=2.7, T_hi=5000.0, device="cuda"):
@@ -102,8 +98,7 @@ class PahSolver:
         P = torch.empty((n, self.M), dtype=torch.float64, device=self.device) if want_P else None
         pabs = torch.empty(n, dtype=torch.float64, device=self.device)
         self._check(lib().pah_solve_exact(self.ctx, _ptr(J), 1 if J.dtype == torch.float32 else 0, n,
-                                          _ptr(o), _ptr(P), _ptr(pabs), _ptr(self.ws), self.ws.numel(),
-                                          _stream()), "pah_solve_exact")
+                                          _ptr(o), _ptr(P), _ptr(pabs), _stream()), "pah_solve_exact")
         return o, P, pabs
 
 
@@ -128,7 +123,7 @@ def _mlp_lib():
         L.pah_mlp_forward.argtypes = [P, P, C.c_int32, P, P]
         L.pah_mlp_train_step.argtypes = [P, P, P, C.c_int32, C.c_float, C.c_int32, P]
         L.pah_surrogate_infer.argtypes = [P, P, P, C.c_int64, P, P, P, C.c_float, C.c_float, P]
-        L.pah_exact_fallback.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_uint64, P]
+        L.pah_exact_fallback.argtypes = [P, P, C.c_int64, P, P, P, P]
         L.pah_mlp_prepare.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
         for n in ("pah_mlp_prepare", "pah_mlp_state_bytes", "pah_mlp_create", "pah_mlp_offsets", "pah_mlp_load",
                   "pah_mlp_set_norm", "pah_mlp_forward", "pah_mlp_train_step", "pah_surrogate_infer",
@@ -246,6 +241,6 @@ def exact_fallback(solver, J, ood, out, idx=None):
     if idx is None:
         idx = torch.empty(n + 1, dtype=torch.int64, device=J.device)
     rc = _mlp_lib().pah_exact_fallback(solver.ctx, _ptr(J.contiguous().float()), n, _ptr(ood), _ptr(out),
-                                       _ptr(idx), _ptr(solver.ws), solver.ws.numel(), _stream())
+                                       _ptr(idx), _stream())
     solver._check(rc, "pah_exact_fallback")
     return idx

@@ -86,3 +86,26 @@ def test_call_order_and_capacity_codes():
     finally:
         L.mcrt_ctx_destroy(ctx)
     assert L.mcrt_ctx_create(C.byref(good_desc()), None) == -1
+
+
+def test_pah_descriptor_limits():
+    from paper_1201_3588_amd import pah
+    L = pah.lib()
+    fake = C.c_void_p(0x1000)
+    nb = C.c_uint64()
+
+    def desc(M, nl, nbands=17):
+        d = pah.PahDesc()
+        d.M, d.n_lambda, d.n_bands = M, nl, nbands
+        d.T = d.U = d.lambda_um = d.cabs = d.cband = d.ccont = fake
+        return d
+
+    assert L.pah_tables_bytes(C.byref(desc(500, 200)), C.byref(nb)) == 0 and nb.value > 500 * 500 * 2
+    assert L.pah_tables_bytes(C.byref(desc(4061 - 3 * 200, 200)), C.byref(nb)) == 0
+    for M, nl in [(2, 200), (500, 1), (4062 - 3 * 200, 200), (500, 1500)]:
+        assert L.pah_tables_bytes(C.byref(desc(M, nl)), C.byref(nb)) == -1, (M, nl)
+        ctx = C.c_void_p()
+        assert L.pah_ctx_create(C.byref(desc(M, nl)), C.byref(ctx)) == -1 and not ctx.value
+    d = desc(500, 200)
+    d.U = None
+    assert L.pah_tables_bytes(C.byref(d), C.byref(nb)) == -1
