@@ -209,13 +209,33 @@ __global__ void k_loss(const float* __restrict__ Y, const float* __restrict__ T,
   if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)N);
 }
 
-// column sums of a bf16 [n][N] matrix
-__global__ void k_colsum(const uint16_t* __restrict__ G, int64_t n, int N, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  float acc = 0.0f;
-  for (int64_t r = 0; r < n; ++r) acc += bf2f(G[r * N + c]);
-  out[c] = acc;
+// column sums of a bf16 [n][N] matrix: a strip of 64 columns per workgroup,
+// 16 row groups with 4 independent accumulators each, combined in LDS in a
+// fixed order (deterministic)
+constexpr int kColRows = 16;
+__global__ void __launch_bounds__(64 * kColRows) k_colsum(const uint16_t* __restrict__ G, int64_t n, int N,
+                                                          float* __restrict__ out) {
+  __shared__ float part[kColRows][64];
+  const int lc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lc;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (c < N) {
+    int64_t r = rg;
+    for (; r + 3 * kColRows < n; r += 4 * kColRows) {
+      a0 += bf2f(G[r * N + c]);
+      a1 += bf2f(G[(r + kColRows) * N + c]);
+      a2 += bf2f(G[(r + 2 * kColRows) * N + c]);
+      a3 += bf2f(G[(r + 3 * kColRows) * N + c]);
+    }
+    for (; r < n; r += kColRows) a0 += bf2f(G[r * N + c]);
+  }
+  part[rg][lc] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (rg == 0 && c < N) {
+    float s = 0.0f;
+    for (int k = 0; k < kColRows; ++k) s += part[k][lc];
+    out[c] = s;
+  }
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 masters, bias-corrected with step t
@@ -438,7 +458,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   g.M = no; g.N = nh; g.K = (int)n; g.A = dY; g.lda = no; g.ta = 1;
   g.B = at<uint16_t>(m, L.H2); g.ldb = nh; g.tb = 0; g.C = G + L.oW3; g.ldc = nh;
   hipError_t e = gemm<EPI_F32>(g, s);
-  k_colsum<<<(no + 255) / 256, 256, 0, s>>>(dY, n, no, G + L.ob3);
+  k_colsum<<<(no + 63) / 64, 64 * kColRows, 0, s>>>(dY, n, no, G + L.ob3);
   // dZ2 = (dY W3) * silu'(Z2); W3 [no][nh] read as (k=o, n=j) -> W3h with tb = 0
   g = GemmP{};
   g.M = (int)n; g.N = nh; g.K = no; g.A = dY; g.lda = no; g.ta = 0;
@@ -450,7 +470,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   g.M = nh; g.N = nh; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ2); g.lda = nh; g.ta = 1;
   g.B = at<uint16_t>(m, L.H1); g.ldb = nh; g.tb = 0; g.C = G + L.oW2; g.ldc = nh;
   if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
-  k_colsum<<<(nh + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.dZ2), n, nh, G + L.ob2);
+  k_colsum<<<(nh + 63) / 64, 64 * kColRows, 0, s>>>(at<uint16_t>(m, L.dZ2), n, nh, G + L.ob2);
   // dZ1 = (dZ2 W2) * silu'(Z1)
   g = GemmP{};
   g.M = (int)n; g.N = nh; g.K = nh; g.A = at<uint16_t>(m, L.dZ2); g.lda = nh; g.ta = 0;
@@ -462,7 +482,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   g.M = nh; g.N = ni; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ1); g.lda = nh; g.ta = 1;
   g.B = at<uint16_t>(m, L.X16); g.ldb = ni; g.tb = 0; g.C = G + L.oW1; g.ldc = ni;
   if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
-  k_colsum<<<(nh + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.dZ1), n, nh, G + L.ob1);
+  k_colsum<<<(nh + 63) / 64, 64 * kColRows, 0, s>>>(at<uint16_t>(m, L.dZ1), n, nh, G + L.ob1);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
