@@ -112,7 +112,8 @@ const char *pah_mlp_last_error(const pah_mlp *m);
  * params, grads, adam_m, adam_v, n_params (a count), then element offsets of
  * W1 b1 W2 b2 W3 b3 inside a parameter block, then byte offsets of the bf16
  * weights W1 W2 W3, x_mu x_sd x_lo x_hi y_mu y_sd, activations X Z1 H1 Z2 H2
- * Y dY dZ2 dZ1, loss, total.  off: host array of >= 32 entries. */
+ * Y dY dZ2 dZ1, loss, packed inference weights, total.  off: host array of
+ * >= 32 entries. */
 int32_t pah_mlp_offsets(const pah_mlp *m, uint64_t *off, int32_t n_off);
 
 /* Copies FP32 parameters (device, flat [W1 b1 W2 b2 W3 b3]) into the masters,

@@ -131,7 +131,7 @@ struct MlpLayout {
   uint64_t oW1, ob1, oW2, ob2, oW3, ob3;     // element offsets inside a block
   uint64_t W1h, W2h, W3h;                    // bf16 copies
   uint64_t x_mu, x_sd, x_lo, x_hi, y_mu, y_sd;
-  uint64_t X16, Z1, H1, Z2, H2, Y, dY16, dZ2, dZ1, loss, total;
+  uint64_t X16, Z1, H1, Z2, H2, Y, dY16, dZ2, dZ1, loss, Wpk, total;
 };
 
 MlpLayout mlp_layout(int ni, int nh, int no, int batch) {
@@ -173,6 +173,7 @@ MlpLayout mlp_layout(int ni, int nh, int no, int batch) {
   L.dZ2 = take(2 * B * nh);
   L.dZ1 = take(2 * B * nh);
   L.loss = take(256);
+  L.Wpk = take(2ull * 3 * 256 * 256);
   L.total = off;
   return L;
 }
@@ -398,6 +399,189 @@ __global__ void k_standardise(float* __restrict__ A, int64_t n, int m, const flo
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference for networks no wider than 256: 64 cells per workgroup.
+// The cells' features, both hidden activations and the outputs never leave
+// the chip: two LDS buffers of [64][264] bfloat16 take turns as layer input
+// and output; weight fragments come from a zero-padded [256][256] copy of each
+// matrix (L2 resident); the last layer writes F and the balance flag straight
+// from its accumulators.  Same MFMA instruction and k order as k_gemm, so the
+// products equal the layer-by-layer path.
+constexpr int kFT = 64;          // cells per workgroup
+constexpr int kFW = 256;         // packed width
+constexpr int kFP = kFW + 8;     // LDS row stride (16-byte rows, banks spread)
+
+size_t fused_lds() { return 2 * sizeof(uint16_t) * kFT * kFP + sizeof(double) * 3 * kFT + sizeof(int) * kFT; }
+
+// zero-padded [256][256] bf16 copies of W1, W2, W3 (row = output unit)
+__global__ void k_pack(const uint16_t* __restrict__ W1, const uint16_t* __restrict__ W2,
+                       const uint16_t* __restrict__ W3, int ni, int nh, int no, uint16_t* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 3 * kFW * kFW) return;
+  const int which = q / (kFW * kFW), n = (q / kFW) % kFW, k = q % kFW;
+  const uint16_t* W = which == 0 ? W1 : (which == 1 ? W2 : W3);
+  const int R = which == 2 ? no : nh, K = which == 0 ? ni : nh;
+  out[q] = (n < R && k < K) ? W[n * K + k] : (uint16_t)0;
+}
+
+struct InferP {
+  const float* J;
+  int64_t n;
+  int nl, ni, nh, no;
+  const double* cabs;
+  const double* dnu;
+  const float *x_mu, *x_sd, *x_lo, *x_hi, *y_mu, *y_sd, *b1, *b2, *b3;
+  const uint16_t* Wp;              // [3][256][256]
+  float margin, tol;
+  double* out;
+  uint8_t* ood;
+  double* pabs;
+};
+
+// acc = act[64][K] W^T on the tile; wave (wr, wc) owns rows 32 wr .. 32 wr + 31
+// and the column blocks 128 wc + 32 cb (cb < 4) that start below N
+__device__ __forceinline__ void fused_layer(const uint16_t* act, const uint16_t* __restrict__ W, int K, int N,
+                                            f32x16* acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int Kp = (K + 15) & ~15;
+  bool on[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    on[cb] = wc * 128 + cb * 32 < N;
+    acc[cb] = f32x16{};
+  }
+  const uint16_t* arow = act + (wr * 32 + (lane & 31)) * kFP + 8 * (lane >> 5);
+  const uint16_t* wrow = W + (wc * 128 + (lane & 31)) * kFW + 8 * (lane >> 5);
+  u16x8 bn[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+    if (on[cb]) bn[cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 32 * kFW);
+  for (int k0 = 0; k0 < Kp; k0 += 16) {
+    u16x8 bc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) bc[cb] = bn[cb];
+    if (k0 + 16 < Kp) {                   // fetch the next step's fragments first
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (on[cb]) bn[cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 32 * kFW + k0 + 16);
+    }
+    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + k0);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      if (on[cb])
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                          __builtin_bit_cast(bf16x8, bc[cb]), acc[cb], 0, 0, 0);
+  }
+}
+
+// hidden-layer epilogue: bias, SiLU, bfloat16 into the next LDS buffer
+__device__ __forceinline__ void fused_hidden(const f32x16* acc, const float* __restrict__ bias, int N,
+                                             uint16_t* dst) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = wc * 128 + cb * 32 + (lane & 31);
+    if (wc * 128 + cb * 32 >= N) continue;
+    const float bcol = col < N ? bias[col] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      dst[row * kFP + col] = f2bf(silu(acc[cb][r] + bcol));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_infer(const InferP p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+  uint16_t* bufA = reinterpret_cast<uint16_t*>(fsm);               // [64][kFP]
+  uint16_t* bufB = bufA + kFT * kFP;                                // [64][kFP]
+  double* sPabs = reinterpret_cast<double*>(bufB + kFT * kFP);      // [64]
+  double* sRow = sPabs + kFT;                                       // [2][64]
+  int* sBad = reinterpret_cast<int*>(sRow + 2 * kFT);               // [64]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)blockIdx.x * kFT;
+  const int nl = p.nl, ni = p.ni;
+
+  // ---- features (wave w: rows 16 w .. 16 w + 15), standardised, range flag
+  for (int rr = 0; rr < kFT / 4; ++rr) {
+    const int row = wave * (kFT / 4) + rr;
+    const int64_t c = c0 + row;
+    const bool valid = c < p.n;
+    const float* Jc = p.J + c * nl;
+    double sum = 0.0;
+    if (valid)
+      for (int j = lane; j < nl; j += 64) sum += p.cabs[j] * (double)Jc[j] * p.dnu[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    const double inv = sum > 0.0 ? 1.0 / sum : 0.0;
+    const double pa = 4.0 * kPi * sum;
+    int bad = 0;
+    for (int j = lane; j < kFW; j += 64) {
+      uint16_t h = 0;
+      if (valid && j < ni) {
+        const float f = j < nl ? (float)(p.cabs[j] * (double)Jc[j] * p.dnu[j] * inv)
+                               : (float)log10(fmax(pa, 1e-300));
+        const float x = (f - p.x_mu[j]) / p.x_sd[j];
+        if (x < p.x_lo[j] - p.margin || x > p.x_hi[j] + p.margin) bad = 1;
+        h = f2bf(x);
+      }
+      bufA[row * kFP + j] = h;
+    }
+    bad = __any(bad);
+    if (lane == 0) {
+      sBad[row] = bad;
+      sPabs[row] = pa;
+    }
+  }
+  __syncthreads();
+
+  f32x16 acc[4];
+  fused_layer(bufA, p.Wp, ni, p.nh, acc);
+  fused_hidden(acc, p.b1, p.nh, bufB);
+  __syncthreads();
+  fused_layer(bufB, p.Wp + kFW * kFW, p.nh, p.nh, acc);
+  fused_hidden(acc, p.b2, p.nh, bufA);
+  __syncthreads();
+  fused_layer(bufA, p.Wp + 2 * kFW * kFW, p.nh, p.no, acc);
+
+  // ---- outputs F = 10^(y sd + mu) P_abs and their per-cell sum
+  const int wr = wave >> 1, wc = wave & 1;
+  double rs[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) rs[r] = 0.0;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = wc * 128 + cb * 32 + (lane & 31);
+    if (wc * 128 + cb * 32 >= p.no || col >= p.no) continue;
+    const float bcol = p.b3[col], sd = p.y_sd[col], mu = p.y_mu[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const float y = acc[cb][r] + bcol;
+      const double F = pow(10.0, (double)(y * sd + mu)) * sPabs[row];
+      if (c0 + row < p.n) p.out[(c0 + row) * p.no + col] = F;
+      rs[r] += F;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double v = rs[r];
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((lane & 31) == 0) sRow[wc * kFT + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kFT && c0 + threadIdx.x < p.n) {
+    const int row = threadIdx.x;
+    const double tot = sRow[row] + sRow[kFT + row], pa = sPabs[row];
+    const int bal = !(fabs(tot - pa) <= p.tol * pa);
+    p.ood[c0 + row] = (uint8_t)(sBad[row] | (bal << 1));
+    p.pabs[c0 + row] = pa;
+  }
+}
+
 }  // namespace
 
 struct pah_mlp {
@@ -524,7 +708,7 @@ int32_t pah_mlp_offsets(const pah_mlp* m, uint64_t* off, int32_t n_off) {
   const uint64_t v[32] = {L.params, L.grads, L.adam_m, L.adam_v, L.n_params, L.oW1, L.ob1, L.oW2,
                           L.ob2, L.oW3, L.ob3, L.W1h, L.W2h, L.W3h, L.x_mu, L.x_sd, L.x_lo, L.x_hi,
                           L.y_mu, L.y_sd, L.X16, L.Z1, L.H1, L.Z2, L.H2, L.Y, L.dY16, L.dZ2, L.dZ1,
-                          L.loss, L.total, 0};
+                          L.loss, L.Wpk, L.total};
   std::memcpy(off, v, sizeof v);
   return MCRT_OK;
 }
@@ -621,6 +805,27 @@ int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int6
   const double* dnu = pah_ctx_dnu(ctx);
   if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
   const MlpLayout& L = m->L;
+  if (n == 0) return MCRT_OK;
+  if (m->ni <= kFW && m->nh <= kFW && m->no <= kFW) {
+    k_pack<<<(3 * kFW * kFW + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.W1h), at<uint16_t>(m, L.W2h),
+                                                        at<uint16_t>(m, L.W3h), m->ni, m->nh, m->no,
+                                                        at<uint16_t>(m, L.Wpk));
+    InferP p{};
+    p.J = J; p.n = n; p.nl = d.n_lambda; p.ni = m->ni; p.nh = m->nh; p.no = m->no;
+    p.cabs = d.cabs; p.dnu = dnu;
+    p.x_mu = at<float>(m, L.x_mu); p.x_sd = at<float>(m, L.x_sd);
+    p.x_lo = at<float>(m, L.x_lo); p.x_hi = at<float>(m, L.x_hi);
+    p.y_mu = at<float>(m, L.y_mu); p.y_sd = at<float>(m, L.y_sd);
+    const float* P = at<float>(m, L.params);
+    p.b1 = P + L.ob1; p.b2 = P + L.ob2; p.b3 = P + L.ob3;
+    p.Wp = at<uint16_t>(m, L.Wpk);
+    p.margin = in_margin; p.tol = balance_tol;
+    p.out = out; p.ood = ood; p.pabs = pabs;
+    k_mlp_infer<<<(unsigned)((n + kFT - 1) / kFT), 256, fused_lds(), s>>>(p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+    return MCRT_OK;
+  }
   for (int64_t c0 = 0; c0 < n; c0 += m->batch) {
     const int64_t nc = n - c0 < m->batch ? n - c0 : m->batch;
     k_mlp_in<<<(unsigned)nc, 256, sizeof(float) * m->ni, s>>>(J + c0 * d.n_lambda, nc, d.n_lambda, d.cabs, dnu, at<float>(m, L.x_mu),

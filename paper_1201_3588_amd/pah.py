@@ -104,7 +104,7 @@ class PahSolver:
 
 OFFSET_NAMES = ["params", "grads", "adam_m", "adam_v", "n_params", "oW1", "ob1", "oW2", "ob2", "oW3",
                 "ob3", "W1h", "W2h", "W3h", "x_mu", "x_sd", "x_lo", "x_hi", "y_mu", "y_sd", "X16",
-                "Z1", "H1", "Z2", "H2", "Y", "dY16", "dZ2", "dZ1", "loss", "total"]
+                "Z1", "H1", "Z2", "H2", "Y", "dY16", "dZ2", "dZ1", "loss", "Wpk", "total"]
 
 
 def _mlp_lib():

@@ -76,3 +76,55 @@ def test_training_reduces_loss():
             net.train_step(Xt[b:b + 512], Tt[b:b + 512], 3e-3, step)
         losses.append(net.loss())
     assert losses[-1] < 0.1 * losses[0]
+
+
+@pytest.mark.parametrize("nh", [256, 320])
+def test_inference_matches_reference(nh):
+    # nh = 256 takes the fused on-chip path, nh = 320 the layer-by-layer one
+    import oracle
+    import synth
+    lam = synth.lambda_grid(200)
+    pm = synth.pah_model(30, lam)
+    solver = pah.PahSolver.from_model(pm)
+    ni, no = lam.size + 1, 17 + lam.size
+    rng = np.random.default_rng(21)
+    p = omlp.init_params(ni, nh, no, seed=8)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, size=p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    net = pah.PahMLP(ni, nh, no, batch=512)
+    net.load(p)
+    J = synth.pah_fields(1000, lam, seed=23)[0]
+    J[::7] *= rng.poisson(3.0, size=J[::7].shape)          # sparse Monte Carlo-like rows
+    J[5] = 0.0                                            # a dark cell
+    J = J.astype(np.float32)
+    # features as the network defines them, from the float32 field
+    nu, dnu = oracle.lambda_bins(lam)
+    cjd = pm.cabs * J.astype(np.float64) * dnu
+    tot = cjd.sum(1)
+    pabs_r = 4 * np.pi * tot
+    feat = np.hstack([(cjd / np.where(tot > 0, tot, 1.0)[:, None]).astype(np.float32),
+                      np.log10(np.maximum(pabs_r, 1e-300)).astype(np.float32)[:, None]])
+    x_mu, x_sd = feat.mean(0).astype(np.float32), (feat.std(0) + 1e-3).astype(np.float32)
+    Xs = (feat - x_mu) / x_sd
+    x_lo, x_hi = np.quantile(Xs, 0.02, axis=0), np.quantile(Xs, 0.98, axis=0)
+    y_mu, y_sd = rng.normal(-3.0, 0.5, size=no), rng.uniform(0.05, 0.2, size=no)
+    net.set_norm(x_mu, x_sd, x_lo, x_hi, y_mu, y_sd)
+    out, ood, pabs = (a.cpu().numpy() for a in net.infer(solver, torch.as_tensor(J).cuda(), 0.5, 0.02))
+    assert np.allclose(pabs, pabs_r, rtol=1e-12, atol=0)
+    Yr, _ = omlp.forward(p, Xs.astype(np.float64), bf16=True)
+    with np.errstate(divide="ignore"):
+        Yg = (np.log10(out / np.where(pabs > 0, pabs, 1.0)[:, None]) - y_mu.astype(np.float32)) / y_sd.astype(np.float32)
+    lit = pabs > 0
+    assert rel_fro(Yg[lit], Yr[lit]) < 1e-4
+    assert np.all(out[~lit] == 0.0)
+    # range flag: away from the margin it is exactly the reference's
+    dist = np.minimum(Xs - (x_lo - 0.5), (x_hi + 0.5) - Xs).min(1)
+    clear = np.abs(dist) > 1e-4
+    assert np.array_equal((ood[clear] & 1) == 1, dist[clear] < 0)
+    assert 0.05 < (ood & 1).mean() < 0.95
+    # balance flag from the network's own outputs
+    ratio = out.sum(1) / np.where(lit, pabs, 1.0)
+    far = lit & (np.abs(np.abs(ratio - 1) - 0.02) > 1e-9)
+    assert np.array_equal((ood[far] & 2) == 2, np.abs(ratio[far] - 1) > 0.02)
+    assert np.all(ood[~lit] & 1)             # a dark cell lies outside every trained range
