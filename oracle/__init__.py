@@ -62,7 +62,10 @@ class Problem(C.Structure):
                 ("K", C.c_int32), ("T_lo", C.c_double), ("T_hi", C.c_double),
                 ("n_total", C.c_uint64), ("seed", C.c_uint64), ("max_events", C.c_uint64),
                 ("n_theta", C.c_int32), ("n_phi", C.c_int32), ("flags", C.c_int32),
-                ("n_threads", C.c_int32), ("frozen_nabs", _u64p), ("pah_rows", _dp)]
+                ("n_threads", C.c_int32), ("frozen_nabs", _u64p), ("pah_rows", _dp),
+                ("n_obs", C.c_int32), ("npix", C.c_int32), ("n_img_lambda", C.c_int32), ("pad_img", C.c_int32),
+                ("img_lambda", C.c_int32 * 8), ("img_center", C.c_double * 3), ("img_half_width", C.c_double),
+                ("img_cos_cone", C.c_double), ("obs_dir", (C.c_double * 3) * 8)]
 
 
 class Tables(C.Structure):
@@ -70,7 +73,7 @@ class Tables(C.Structure):
 
 
 class Out(C.Structure):
-    _fields_ = [("nabs", _u64p), ("sed", _u64p), ("jq", _u64p), ("counters", _u64p),
+    _fields_ = [("nabs", _u64p), ("sed", _u64p), ("jq", _u64p), ("counters", _u64p), ("image", _u64p),
                 ("trace", C.c_void_p), ("trace_len", _i32p), ("trace_cap", C.c_int64)]
 
 
@@ -133,7 +136,8 @@ class Session:
     """Holds the ctypes problem for one workload (keeps its arrays alive)."""
 
     def __init__(self, w, n_threads: int = 1, n_total: int | None = None, seed: int | None = None,
-                 flags: int | None = None, frozen_nabs=None, pah_rows=None, max_events=None):
+                 flags: int | None = None, frozen_nabs=None, pah_rows=None, max_events=None,
+                 observers=None):
         g, sp, src = w.grid, w.species, w.source
         self.w = w
         self._keep = []
@@ -173,6 +177,17 @@ class Session:
             p.flags |= FLAG_FROZEN_T
         if pah_rows is not None:
             p.pah_rows = _p(keep(pah_rows, np.float64))
+        if observers is not None:
+            ob = observers
+            p.n_obs, p.npix = len(ob["dirs"]), int(ob["npix"])
+            p.n_img_lambda = len(ob["lambda_bins"])
+            for q, jb in enumerate(ob["lambda_bins"]):
+                p.img_lambda[q] = int(jb)
+            p.img_center = (C.c_double * 3)(*ob["center"])
+            p.img_half_width, p.img_cos_cone = float(ob["half_width"]), float(ob["cos_cone"])
+            for q, dv in enumerate(ob["dirs"]):
+                for a in range(3):
+                    p.obs_dir[q][a] = float(dv[a])
         self.p = p
         self.tables = self._build_tables()
 
@@ -199,7 +214,9 @@ class Session:
         sed = np.zeros(p.n_theta * p.n_phi * p.nl, np.uint64)
         jq = np.zeros(p.nl * p.n_cells, np.uint64) if (p.flags & FLAG_TALLY_J) else None
         cnt = np.zeros(16, np.uint64)
-        o = Out(nabs=_p(nabs, _u64p), sed=_p(sed, _u64p), jq=_p(jq, _u64p), counters=_p(cnt, _u64p))
+        img = np.zeros(p.n_obs * p.n_img_lambda * p.npix * p.npix, np.uint64) if p.n_obs > 0 else None
+        o = Out(nabs=_p(nabs, _u64p), sed=_p(sed, _u64p), jq=_p(jq, _u64p), counters=_p(cnt, _u64p),
+                image=_p(img, _u64p))
         tr = tl = None
         if trace_cap > 0:
             tr = np.zeros(n * trace_cap, TRACE_DTYPE)
@@ -212,7 +229,8 @@ class Session:
             raise RuntimeError(f"orc_transport failed: {rc}")
         res = dict(nabs=nabs.reshape(p.n_cells, p.S),
                    sed=sed.reshape(p.n_theta, p.n_phi, p.nl), counters=cnt,
-                   jq=jq.reshape(p.nl, p.n_cells) if jq is not None else None)
+                   jq=jq.reshape(p.nl, p.n_cells) if jq is not None else None,
+                   image=img.reshape(p.n_obs, p.n_img_lambda, p.npix, p.npix) if img is not None else None)
         if tr is not None:
             res["trace"] = [tr[k * trace_cap:k * trace_cap + tl[k]] for k in range(n)]
         return res
@@ -221,7 +239,8 @@ class Session:
         """Run packets [first_id, first_id+n) adding into acc (dict of uint64 arrays
         nabs, sed, jq, counters as made by new_accumulator)."""
         o = Out(nabs=_p(acc["nabs"], _u64p), sed=_p(acc["sed"], _u64p),
-                jq=_p(acc.get("jq"), _u64p), counters=_p(acc["counters"], _u64p))
+                jq=_p(acc.get("jq"), _u64p), counters=_p(acc["counters"], _u64p),
+                image=_p(acc.get("image"), _u64p))
         rc = lib().orc_transport(C.byref(self.p), C.byref(self._T), first_id, n, C.byref(o))
         if rc != 0:
             raise RuntimeError(f"orc_transport failed: {rc}")
@@ -232,7 +251,8 @@ class Session:
         return dict(nabs=np.zeros(p.n_cells * p.S, np.uint64),
                     sed=np.zeros(p.n_theta * p.n_phi * p.nl, np.uint64),
                     jq=np.zeros(p.nl * p.n_cells, np.uint64) if (p.flags & FLAG_TALLY_J) else None,
-                    counters=np.zeros(16, np.uint64))
+                    counters=np.zeros(16, np.uint64),
+                    image=np.zeros(p.n_obs * p.n_img_lambda * p.npix * p.npix, np.uint64) if p.n_obs else None)
 
     def temperatures(self, nabs):
         p = self.p

@@ -231,6 +231,48 @@ static void escape_tally(const orc_problem *p, orc_out *o, const double d[3], in
   add_u64(&o->sed[((int64_t)bt * p->n_phi + bp) * p->nl + j], 1, thr);
 }
 
+/* Escape images: observer o looks back along n_o (unit).  A packet leaving
+ * the grid at x (base-cube units) in direction d with d . n_o >= cos_cone,
+ * in an imaged bin, is placed where its ray, extended backwards, crosses the
+ * image plane through the centre c perpendicular to n_o; the plane's axes are
+ * e1 = (z x n_o)/|z x n_o| (the x axis when n_o is along z) and
+ * e2 = n_o x e1; pixel (px, py) = floor((a + w) / (2 w) npix) of the plane
+ * coordinates (a, b), counted when both lie in [0, npix). */
+static void image_tally(const orc_problem *p, orc_out *o, const double x[3], const double d[3],
+                        int j, int thr) {
+  if (!o->image || p->n_obs <= 0) return;
+  int l = -1;
+  for (int q = 0; q < p->n_img_lambda; ++q) if (p->img_lambda[q] == j) l = q;
+  if (l < 0) return;
+  double X[3];                                       /* exit point relative to c, cm */
+  for (int a = 0; a < 3; ++a) X[a] = p->box_min[a] + x[a] * p->base_size - p->img_center[a];
+  for (int ob = 0; ob < p->n_obs; ++ob) {
+    const double *m = p->obs_dir[ob];
+    const double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    const double n[3] = {m[0] / len, m[1] / len, m[2] / len};
+    const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+    if (dn < p->img_cos_cone) continue;
+    double e1[3], e2[3];
+    const double r = sqrt(n[0] * n[0] + n[1] * n[1]);
+    if (r > 1e-12) { e1[0] = -n[1] / r; e1[1] = n[0] / r; e1[2] = 0.0; }
+    else { e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0; }
+    e2[0] = n[1] * e1[2] - n[2] * e1[1];
+    e2[1] = n[2] * e1[0] - n[0] * e1[2];
+    e2[2] = n[0] * e1[1] - n[1] * e1[0];
+    /* back along the ray to the plane X . n = 0 */
+    const double s = (X[0] * n[0] + X[1] * n[1] + X[2] * n[2]) / dn;
+    double P[3];
+    for (int a = 0; a < 3; ++a) P[a] = X[a] - s * d[a];
+    const double ca = P[0] * e1[0] + P[1] * e1[1] + P[2] * e1[2];
+    const double cb = P[0] * e2[0] + P[1] * e2[1] + P[2] * e2[2];
+    const double w = p->img_half_width;
+    const double fx = floor((ca + w) / (2.0 * w) * p->npix), fy = floor((cb + w) / (2.0 * w) * p->npix);
+    if (fx < 0.0 || fy < 0.0 || fx >= p->npix || fy >= p->npix) continue;
+    add_u64(&o->image[(((int64_t)ob * p->n_img_lambda + l) * p->npix + (int64_t)fy) * p->npix + (int64_t)fx],
+            1, thr);
+  }
+}
+
 /* One packet from launch to escape / kill.  k indexes the trace buffer. */
 static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, uint64_t k,
                        orc_out *o, const int32_t *pah_slot, int thr) {
@@ -261,6 +303,7 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
   if (cell < 0) {
     add_u64(&cnt[ORC_CNT_ESCAPED], 1, thr);
     escape_tally(p, o, d, j, thr);
+    image_tally(p, o, x, d, j, thr);
     rec(o, k, ORC_EV_ESCAPE, -1, j, x, d, tau);
     return;
   }
@@ -363,6 +406,7 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
     if (cell < 0) {
       add_u64(&cnt[ORC_CNT_ESCAPED], 1, thr);
       escape_tally(p, o, d, j, thr);
+      image_tally(p, o, x, d, j, thr);
       rec(o, k, ORC_EV_ESCAPE, -1, j, x, d, tau);
       return;
     }

@@ -64,6 +64,13 @@ typedef struct {
   int32_t n_threads;               /* 1 = sequential definition */
   const uint64_t *frozen_nabs;     /* [n_cells*S] (frozen_T mode) */
   const double *pah_rows;          /* [n_pah][n_cells][nl] CDF rows or NULL */
+  /* escape images (n_obs = 0: none) */
+  int32_t n_obs, npix, n_img_lambda, pad_img;
+  int32_t img_lambda[8];           /* imaged wavelength bins */
+  double img_center[3];            /* cm */
+  double img_half_width;           /* cm */
+  double img_cos_cone;             /* in (0, 1] */
+  double obs_dir[8][3];            /* towards the observers (normalised here) */
 } orc_problem;
 
 typedef struct {
@@ -81,6 +88,7 @@ typedef struct {
   uint64_t *sed;                   /* [n_theta*n_phi*nl] */
   uint64_t *jq;                    /* [nl*n_cells] fixed-point path sums or NULL */
   uint64_t *counters;              /* [16] */
+  uint64_t *image;                 /* [n_obs*n_img_lambda*npix*npix] or NULL */
   orc_trace_rec *trace;            /* [n*trace_cap] or NULL */
   int32_t *trace_len;              /* [n] */
   int64_t trace_cap;
