@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MCRT_VERSION 100
+#define MCRT_VERSION 101
 
 #define MCRT_OK 0
 #define MCRT_E_INVALID (-1)     /* null pointer, bad size or range */
@@ -119,7 +119,34 @@ typedef struct {
                                   base_size * 2^-(max_level+16) cm; NULL if
                                   TALLY_J is off */
   uint64_t *counters;          /* [MCRT_N_COUNTERS] */
+  uint64_t *image;             /* [n_obs][n_img_lambda][npix][npix] escaped
+                                  packets per pixel (mcrt_observers); NULL
+                                  when no observers are set */
 } mcrt_tallies;
+
+/* Escape images (paper Sec. 2, Fig. 2: the model seen from chosen
+ * directions).  Observer o looks back along dir[o].  A packet that leaves the
+ * grid in direction d with d . dir[o] >= cos_cone, in one of the imaged bins
+ * img_lambda[l], is placed where its ray, extended backwards from the exit
+ * point, crosses the image plane through `center` perpendicular to dir[o].
+ * The plane's axes are e1 = (z x n)/|z x n| (the x axis when n is along z)
+ * and e2 = n x e1 (n = dir[o] normalised); plane coordinates (a, b) map to
+ * pixel (floor((a + w) / (2 w) npix), floor((b + w) / (2 w) npix)),
+ * w = half_width, counted in image[o][l][py][px] when both lie in
+ * [0, npix).  Direct starlight from a star at `center` lands in the centre. */
+#define MCRT_MAX_OBSERVERS 8
+#define MCRT_MAX_IMAGE_BINS 8
+typedef struct {
+  int32_t n_obs;               /* 0..8; 0 turns the images off */
+  int32_t npix;                /* pixels per image side, 1..4096 */
+  int32_t n_img_lambda;        /* 1..8 */
+  int32_t img_lambda[MCRT_MAX_IMAGE_BINS];  /* distinct bins in [0, n_lambda) */
+  int32_t pad;
+  double center[3];            /* cm */
+  double half_width;           /* cm, > 0 */
+  double cos_cone;             /* (0, 1] */
+  double dir[MCRT_MAX_OBSERVERS][3];        /* non-zero; normalised here */
+} mcrt_observers;
 
 /* Per-packet event trace (debug/test only). */
 typedef struct {
@@ -174,9 +201,14 @@ int32_t mcrt_table_layout_get(const mcrt_ctx *ctx, mcrt_table_layout *out);
 int32_t mcrt_build_tables(mcrt_ctx *ctx, const mcrt_source *src, void *tables,
                           uint64_t tables_bytes, hipStream_t stream);
 
+/* Sets (copies, validates) the observers of the escape images used by the
+ * following runs; n_obs = 0 turns them off.  Host only, no device work. */
+int32_t mcrt_set_observers(mcrt_ctx *ctx, const mcrt_observers *obs);
+
 /* Transports packets with ids [first_id, first_id + n_packets) (paper Sec. 2)
  * and adds their tallies.  Random numbers: Philox4x32-10 keyed by seed,
- * counter (id_lo, id_hi, event, 0|1).  Requires mcrt_build_tables. */
+ * counter (id_lo, id_hi, event, 0|1).  Requires mcrt_build_tables; requires
+ * tallies->image when observers are set. */
 int32_t mcrt_run(mcrt_ctx *ctx, uint64_t first_id, uint64_t n_packets,
                  const mcrt_run_opts *opts, const mcrt_tallies *tallies,
                  hipStream_t stream);
@@ -200,6 +232,10 @@ int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
  * r_c the distance from the source to the leaf centre, at least half the leaf
  * side.  J_out: device float [n_cells * n_lambda]. */
 int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
+
+/* Copies the MCRT_N_COUNTERS counters of `tallies` to host memory and waits
+ * for the stream (so for every launch queued on it before). */
+int32_t mcrt_read_counters_sync(const mcrt_tallies *tallies, uint64_t *host_out, hipStream_t stream);
 
 /* Random-access microbenchmark defining the achievable ceiling of the
  * transport kernel's memory traffic.  mode 0: ceil(n_ops / threads) * threads

@@ -134,6 +134,65 @@ int32_t mcrt_build_tables(mcrt_ctx* ctx, const mcrt_source* src, void* tables, u
   return MCRT_OK;
 }
 
+int32_t mcrt_set_observers(mcrt_ctx* ctx, const mcrt_observers* obs) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!obs) return fail(ctx, MCRT_E_INVALID, "null observers");
+  if (obs->n_obs == 0) {
+    ctx->img = ImgP{};
+    return MCRT_OK;
+  }
+  if (obs->n_obs < 0 || obs->n_obs > MCRT_MAX_OBSERVERS) return fail(ctx, MCRT_E_INVALID, "n_obs must be in 0..8");
+  if (obs->npix < 1 || obs->npix > 4096) return fail(ctx, MCRT_E_INVALID, "npix must be in 1..4096");
+  if (obs->n_img_lambda < 1 || obs->n_img_lambda > MCRT_MAX_IMAGE_BINS)
+    return fail(ctx, MCRT_E_INVALID, "n_img_lambda must be in 1..8");
+  if (!(obs->half_width > 0.0) || !std::isfinite(obs->half_width))
+    return fail(ctx, MCRT_E_INVALID, "half_width must be positive and finite");
+  if (!(obs->cos_cone > 0.0 && obs->cos_cone <= 1.0)) return fail(ctx, MCRT_E_INVALID, "cos_cone must be in (0, 1]");
+  ImgP I{};
+  I.n_obs = obs->n_obs;
+  I.npix = obs->npix;
+  I.n_l = obs->n_img_lambda;
+  for (int q = 0; q < I.n_l; ++q) {
+    const int jb = obs->img_lambda[q];
+    if (jb < 0 || jb >= ctx->d.n_lambda) return fail(ctx, MCRT_E_INVALID, "imaged bin out of range");
+    for (int r = 0; r < q; ++r)
+      if (I.lsel[r] == jb) return fail(ctx, MCRT_E_INVALID, "imaged bins must be distinct");
+    I.lsel[q] = jb;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(obs->center[a])) return fail(ctx, MCRT_E_INVALID, "center not finite");
+    I.off[a] = ctx->d.box_min[a] - obs->center[a];
+  }
+  for (int o = 0; o < I.n_obs; ++o) {
+    const double* m = obs->dir[o];
+    const double len = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    if (!(len > 0.0) || !std::isfinite(len)) return fail(ctx, MCRT_E_INVALID, "observer direction zero or not finite");
+    double* n = I.n[o];
+    for (int a = 0; a < 3; ++a) n[a] = m[a] / len;
+    double* e1 = I.e1[o];
+    double* e2 = I.e2[o];
+    const double r = std::sqrt(n[0] * n[0] + n[1] * n[1]);   // |z x n|
+    if (r > 1e-12) { e1[0] = -n[1] / r; e1[1] = n[0] / r; e1[2] = 0.0; }
+    else { e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0; }
+    e2[0] = n[1] * e1[2] - n[2] * e1[1];
+    e2[1] = n[2] * e1[0] - n[0] * e1[2];
+    e2[2] = n[0] * e1[1] - n[1] * e1[0];
+  }
+  I.h = ctx->d.base_size;
+  I.w = obs->half_width;
+  I.cos_cone = obs->cos_cone;
+  ctx->img = I;
+  return MCRT_OK;
+}
+
+int32_t mcrt_read_counters_sync(const mcrt_tallies* t, uint64_t* host_out, hipStream_t stream) {
+  if (!t || !t->counters || !host_out) return MCRT_E_INVALID;
+  hipError_t e = hipMemcpyAsync(host_out, t->counters, sizeof(uint64_t) * MCRT_N_COUNTERS,
+                                hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+
 int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcrt_run_opts* opts,
                  const mcrt_tallies* tallies, hipStream_t stream) {
   if (!ctx) return MCRT_E_INVALID;
@@ -152,6 +211,8 @@ int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcr
   if (first_id + n_packets < first_id) return fail(ctx, MCRT_E_INVALID, "packet id range overflows");
   if (ctx->n_pah > 0 && !opts->pah_rows && !(opts->flags & MCRT_FLAG_KILL_ON_ABSORB))
     return fail(ctx, MCRT_E_INVALID, "PAH species need pah_rows");
+  if (ctx->img.n_obs > 0 && !tallies->image)
+    return fail(ctx, MCRT_E_INVALID, "observers are set: tallies->image needed");
   if (n_packets == 0) return MCRT_OK;
   const hipError_t e = launch_transport(ctx, first_id, n_packets, *opts, *tallies, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "transport launch");

@@ -63,8 +63,21 @@ Layout make_layout(const mcrt_desc& d);
 
 }  // namespace mcrt
 
+namespace mcrt {
+// observers of the escape images, as the kernel uses them: unit line of sight
+// n, plane axes e1, e2, and the grid origin relative to the image centre (cm)
+struct ImgP {
+  int n_obs, npix, n_l;
+  int lsel[MCRT_MAX_IMAGE_BINS];
+  double n[MCRT_MAX_OBSERVERS][3], e1[MCRT_MAX_OBSERVERS][3], e2[MCRT_MAX_OBSERVERS][3];
+  double off[3], h, w, cos_cone;
+  unsigned long long* image;
+};
+}  // namespace mcrt
+
 struct mcrt_ctx {
   mcrt_desc d;
+  mcrt::ImgP img{};
   mcrt::Layout lay;
   int n_pah = 0;
   bool tables_built = false;

@@ -51,6 +51,7 @@ struct TP {
   unsigned long long* work;
   mcrt_trace_rec* trace;
   int32_t* trace_len;
+  ImgP img;
 };
 
 __device__ __forceinline__ float rlog(float v) { return logf(v); }
@@ -155,13 +156,39 @@ __device__ __forceinline__ void escape_tally(const TP<R>& P, R d0, R d1, R d2, i
   atomicAdd(&P.sed[((int64_t)bt * P.n_phi + bp) * P.nl + j], 1ull);
 }
 
+// escape images: the exit point x (base-cube units), moved back along the ray
+// to the observer's image plane, in plane pixels (see mcrt_observers)
+template <typename R>
+__device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1, double x2, R d0, R d1,
+                                         R d2, int j) {
+  const ImgP& I = P.img;
+  int l = -1;
+  for (int q = 0; q < I.n_l; ++q)
+    if (I.lsel[q] == j) l = q;
+  if (l < 0) return;
+  const double X0 = I.off[0] + x0 * I.h, X1 = I.off[1] + x1 * I.h, X2 = I.off[2] + x2 * I.h;
+  const double e0 = d0, e1 = d1, e2 = d2;
+  for (int o = 0; o < I.n_obs; ++o) {
+    const double* n = I.n[o];
+    const double dn = e0 * n[0] + e1 * n[1] + e2 * n[2];
+    if (dn < I.cos_cone) continue;
+    const double t = (X0 * n[0] + X1 * n[1] + X2 * n[2]) / dn;
+    const double p0 = X0 - t * e0, p1 = X1 - t * e1, p2 = X2 - t * e2;
+    const double a = p0 * I.e1[o][0] + p1 * I.e1[o][1] + p2 * I.e1[o][2];
+    const double b = p0 * I.e2[o][0] + p1 * I.e2[o][1] + p2 * I.e2[o][2];
+    const double fx = floor((a + I.w) / (2.0 * I.w) * I.npix), fy = floor((b + I.w) / (2.0 * I.w) * I.npix);
+    if (fx < 0.0 || fy < 0.0 || fx >= I.npix || fy >= I.npix) continue;
+    atomicAdd(&I.image[(((int64_t)o * I.n_l + l) * I.npix + (int64_t)fy) * I.npix + (int64_t)fx], 1ull);
+  }
+}
+
 constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the shared counter
 
 // Packet state: current leaf (integer lower corner lo* in finest units, level
 // lev) and the position u* relative to that corner in base-cube units, so that
 // rounding scales with the cell, not with the distance from the grid origin;
 // crossing into a neighbour re-bases u by an exact integer offset.
-template <typename R, bool TRACE>
+template <typename R, bool TRACE, bool IMG>
 __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
   __shared__ unsigned int s_cnt[12];
@@ -249,6 +276,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
             if (cell < 0) {
               bump(1);
               escape_tally(P, d0, d1, d2, j);
+              if (IMG) image_tally(P, P.x0, P.y0, P.z0, d0, d1, d2, j);
               if (TRACE) record(P, kidx, 4, -1, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
             } else {
               alive = true;
@@ -412,6 +440,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
       bump(1);
       alive = false;
       escape_tally(P, d0, d1, d2, j);
+      if (IMG) image_tally(P, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
       if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
     } else {
       // re-base the local position on the new leaf (exact integer offsets)
@@ -487,21 +516,22 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   P.work = &scr->work_counter;
   P.trace = o.trace;
   P.trace_len = o.trace_len;
+  P.img = c->img;
+  P.img.image = reinterpret_cast<unsigned long long*>(t.image);
+  const bool img = c->img.n_obs > 0;
   k_zero_u64<<<1, 64, 0, s>>>(&scr->work_counter, 1);
   const uint64_t want = (n + 255) / 256;
   const size_t lds = (size_t)d.n_lambda * (2 * sizeof(double) + sizeof(R));
   // persistent grid: as many blocks as can be resident at once
+  auto kern = o.trace ? (img ? k_transport<R, true, true> : k_transport<R, true, false>)
+                      : (img ? k_transport<R, false, true> : k_transport<R, false, false>);
   int per_cu = 0;
-  if (o.trace)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, true>, 256, lds);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, false>, 256, lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
   if (per_cu < 1) per_cu = 1;
   uint64_t blocks = o.grid_blocks > 0 ? (uint64_t)o.grid_blocks : (uint64_t)c->n_cu * per_cu;
   if (blocks > want) blocks = want;
   if (blocks < 1) blocks = 1;
-  if (o.trace) k_transport<R, true><<<(unsigned)blocks, 256, lds, s>>>(P);
-  else k_transport<R, false><<<(unsigned)blocks, 256, lds, s>>>(P);
+  kern<<<(unsigned)blocks, 256, lds, s>>>(P);
   return hipGetLastError();
 }
 

@@ -43,7 +43,13 @@ class Source(C.Structure):
 
 
 class Tallies(C.Structure):
-    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp)]
+    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp), ("image", _dp)]
+
+
+class Observers(C.Structure):
+    _fields_ = [("n_obs", C.c_int32), ("npix", C.c_int32), ("n_img_lambda", C.c_int32),
+                ("img_lambda", C.c_int32 * 8), ("pad", C.c_int32), ("center", C.c_double * 3),
+                ("half_width", C.c_double), ("cos_cone", C.c_double), ("dir", (C.c_double * 3) * 8)]
 
 
 class RunOpts(C.Structure):
@@ -88,6 +94,10 @@ def lib():
         L.mcrt_mean_intensity.argtypes = [P, P, C.c_uint64, P, P]
         L.mcrt_thin_field.argtypes = [P, P, P]
         L.mcrt_thin_field.restype = C.c_int32
+        L.mcrt_set_observers.argtypes = [P, C.POINTER(Observers)]
+        L.mcrt_set_observers.restype = C.c_int32
+        L.mcrt_read_counters_sync.argtypes = [C.POINTER(Tallies), P, P]
+        L.mcrt_read_counters_sync.restype = C.c_int32
         for name in ("mcrt_tables_bytes", "mcrt_ctx_create", "mcrt_table_layout_get", "mcrt_build_tables",
                      "mcrt_run", "mcrt_temperatures", "mcrt_mean_intensity"):
             getattr(L, name).restype = C.c_int32
@@ -194,19 +204,45 @@ class Engine:
         self._check(lib().mcrt_build_tables(self.ctx, C.byref(s), _ptr(self.tables),
                                             self.tables.numel(), _stream()), "mcrt_build_tables")
 
+    def set_observers(self, dirs=(), npix=1, half_width=1.0, center=(0.0, 0.0, 0.0), cos_cone=1.0,
+                      lambda_bins=()):
+        """Escape images (see mcrt_observers); no directions turns them off."""
+        ob = Observers()
+        ob.n_obs, ob.npix, ob.n_img_lambda = len(dirs), int(npix), len(lambda_bins)
+        for q, jb in enumerate(lambda_bins):
+            ob.img_lambda[q] = int(jb)
+        ob.center = (C.c_double * 3)(*[float(v) for v in center])
+        ob.half_width, ob.cos_cone = float(half_width), float(cos_cone)
+        for q, dv in enumerate(dirs):
+            for a in range(3):
+                ob.dir[q][a] = float(dv[a])
+        self._check(lib().mcrt_set_observers(self.ctx, C.byref(ob)), "mcrt_set_observers")
+        self.image_shape = (len(dirs), len(lambda_bins), int(npix), int(npix)) if len(dirs) else None
+
     def new_tallies(self, tally_j=True):
         z = lambda n: torch.zeros(int(n), dtype=torch.int64, device=self.device)
+        shape = getattr(self, "image_shape", None)
         return dict(nabs=z(self.n_cells * self.n_species),
                     sed=z(self.n_theta * self.n_phi * self.n_lambda),
                     jq=z(self.n_lambda * self.n_cells) if tally_j else None,
-                    counters=z(16))
+                    counters=z(16),
+                    image=z(np.prod(shape)) if shape else None)
+
+    def counters_sync(self, tallies):
+        """The run counters as numpy uint64, after the stream has drained."""
+        t = Tallies(None, None, None, _ptr(tallies["counters"]), None)
+        out = np.zeros(16, np.uint64)
+        rc = lib().mcrt_read_counters_sync(C.byref(t), out.ctypes.data, _stream())
+        if rc != 0:
+            raise MCRTError(rc, "mcrt_read_counters_sync")
+        return out
 
     def run(self, tallies, first_id, n, n_total, seed, max_events=1_000_000, flags=None,
             frozen_nabs=None, pah_rows=None, trace_cap=0, grid_blocks=0):
         if flags is None:
             flags = FLAG_TALLY_J if tallies.get("jq") is not None else 0
         t = Tallies(_ptr(tallies["nabs"]), _ptr(tallies["sed"]), _ptr(tallies.get("jq")),
-                    _ptr(tallies["counters"]))
+                    _ptr(tallies["counters"]), _ptr(tallies.get("image")))
         o = RunOpts()
         o.n_total, o.seed, o.max_events = int(n_total), int(seed), int(max_events)
         o.flags, o.grid_blocks = int(flags), int(grid_blocks)

@@ -25,7 +25,7 @@ def test_every_declared_symbol_is_exported():
     assert "mcrt_run" in names and "mcrt_build_tables" in names
     for n in names:
         assert hasattr(L, n), n
-    assert L.mcrt_version() == 100
+    assert L.mcrt_version() == 101
 
 
 def good_desc():
@@ -109,3 +109,36 @@ def test_pah_descriptor_limits():
     d = desc(500, 200)
     d.U = None
     assert L.pah_tables_bytes(C.byref(d), C.byref(nb)) == -1
+
+
+def test_observer_validation_codes():
+    L = mcrt.lib()
+    ctx = C.c_void_p()
+    assert L.mcrt_ctx_create(C.byref(good_desc()), C.byref(ctx)) == 0
+    try:
+        def obs(**kw):
+            o = mcrt.Observers()
+            o.n_obs, o.npix, o.n_img_lambda, o.half_width, o.cos_cone = 2, 16, 2, 1.0, 0.9
+            o.img_lambda[0], o.img_lambda[1] = 0, 1
+            o.dir[0][2], o.dir[1][0] = 1.0, 2.0
+            for k, v in kw.items():
+                setattr(o, k, v)
+            return o
+        assert L.mcrt_set_observers(ctx, C.byref(obs())) == 0
+        for bad in [dict(n_obs=9), dict(n_obs=-1), dict(npix=0), dict(n_img_lambda=0), dict(n_img_lambda=9),
+                    dict(half_width=0.0), dict(half_width=float("inf")), dict(cos_cone=0.0), dict(cos_cone=1.5)]:
+            assert L.mcrt_set_observers(ctx, C.byref(obs(**bad))) == -1, bad
+        o = obs()
+        o.img_lambda[1] = 0                              # repeated bin
+        assert L.mcrt_set_observers(ctx, C.byref(o)) == -1
+        o = obs()
+        o.img_lambda[1] = 10_000                         # beyond the wavelength grid
+        assert L.mcrt_set_observers(ctx, C.byref(o)) == -1
+        o = obs()
+        o.dir[1][0] = 0.0                                # zero direction
+        assert L.mcrt_set_observers(ctx, C.byref(o)) == -1
+        assert L.mcrt_set_observers(ctx, C.byref(obs(n_obs=0))) == 0
+        assert L.mcrt_set_observers(ctx, None) == -1
+    finally:
+        L.mcrt_ctx_destroy(ctx)
+    assert L.mcrt_read_counters_sync(None, None, None) == -1

@@ -89,19 +89,59 @@ def test_fixed_random_traces(precision, tol, min_frac):
         assert same >= min_frac * 400, (precision, same)
 
 
+def disk_observers(w, npix=24):
+    # face-on, edge-on and inclined views of the disk, centred on the star,
+    # field of view the whole grid, three near- and mid-infrared bins
+    half = 0.5 * w.grid.nb * w.grid.base_size
+    return dict(dirs=[(0, 0, 1), (1, 0, 0), (0, 0.5, 0.866)], npix=npix, half_width=1.2 * half,
+                center=list(w.source.pos), cos_cone=float(np.cos(np.radians(35.0))), lambda_bins=[10, 14, 16])
+
+
 def test_fp64_frozen_tallies_equal_oracle():
     w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
     w.precision = "f64"
     base = oracle.Session(w).transport()["nabs"]
     e = engine(w)
+    obs = disk_observers(w)
+    e.set_observers(**obs)
     tal = e.new_tallies()
     e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
     g = host(tal)
-    o = oracle.Session(w, frozen_nabs=base).transport()
+    o = oracle.Session(w, frozen_nabs=base, observers=obs).transport()
     assert np.array_equal(g["counters"], o["counters"])
     assert np.array_equal(g["nabs"], o["nabs"].reshape(-1))
     assert np.array_equal(g["sed"], o["sed"].reshape(-1))
     assert np.array_equal(g["jq"], o["jq"].reshape(-1))
+    assert o["image"].sum() > 100
+    assert np.array_equal(g["image"], o["image"].reshape(-1))
+    assert np.array_equal(e.counters_sync(tal), o["counters"])
+
+
+def test_images_count_every_in_cone_escape():
+    # FP32 transport, traced: each image holds exactly the escapes whose
+    # direction lies in the observer's cone (the field of view encloses every
+    # back-projected point), and nothing of other bins
+    w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
+    e = engine(w)
+    obs = disk_observers(w, npix=16)
+    obs["half_width"] = 4.0 * w.grid.nb * w.grid.base_size
+    e.set_observers(**obs)
+    tal = e.new_tallies()
+    tr = e.run(tal, 0, 3000, 3000, w.seed, trace_cap=400)
+    img = host(tal)["image"].reshape(3, 3, 16, 16)
+    last = [t[-1] for t in tr]
+    assert all(r["type"] == 4 for r in last)
+    d = np.array([r["d"] for r in last])
+    jj = np.array([r["j"] for r in last])
+    for o, dv in enumerate(obs["dirs"]):
+        n = np.asarray(dv, float) / np.linalg.norm(dv)
+        for l, jb in enumerate(obs["lambda_bins"]):
+            assert img[o, l].sum() == np.sum((d @ n >= obs["cos_cone"]) & (jj == jb)), (o, l)
+    assert img.sum() > 100
+    e.set_observers()                       # off again: runs need no image tally
+    tal2 = e.new_tallies()
+    assert tal2["image"] is None
+    e.run(tal2, 0, 100, 3000, w.seed)
 
 
 def test_shards_add_up_bit_exact():
