@@ -89,9 +89,11 @@ def test_fixed_random_traces(precision, tol, min_frac):
         assert same >= min_frac * 400, (precision, same)
 
 
-def disk_observers(w, npix=24):
+def disk_observers(w, npix=25):
     # face-on, edge-on and inclined views of the disk, centred on the star,
-    # field of view the whole grid, three near- and mid-infrared bins
+    # field of view the whole grid, three near- and mid-infrared bins; an odd
+    # pixel count puts the star at a pixel centre (direct starlight projects to
+    # the centre up to rounding, which must not decide the pixel)
     half = 0.5 * w.grid.nb * w.grid.base_size
     return dict(dirs=[(0, 0, 1), (1, 0, 0), (0, 0.5, 0.866)], npix=npix, half_width=1.2 * half,
                 center=list(w.source.pos), cos_cone=float(np.cos(np.radians(35.0))), lambda_bins=[10, 14, 16])
