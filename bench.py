@@ -86,7 +86,7 @@ def main():
         t_prep = time.perf_counter()
         Jd = []
         for k in range(args.train_passes):
-            for v in tal.values():
+            for v in (t for t in tal.values() if t is not None):
                 v.zero_()
             eng.run(tal, 0, N, N, w.seed + 101 * (k + 1))
             Jd.append(eng.mean_intensity(tal["jq"], N).index_select(0, dusty))
@@ -109,7 +109,7 @@ def main():
     pah_t = []
 
     def step():
-        for v in tal.values():
+        for v in (t for t in tal.values() if t is not None):
             v.zero_()
         eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
         e0 = torch.cuda.Event(enable_timing=True)
