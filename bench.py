@@ -30,6 +30,85 @@ METRIC = "photon packets/sec + cell-crossings/sec (1 GPU); PAH cells/sec surroga
 HBM_PEAK_GBS = 8000.0
 
 
+def random_atomic_rate(n_slots, stream):
+    """Achievable rate of random 64-bit atomic adds over a table of n_slots
+    words (the size of the path-length tally), measured with HIP events."""
+    import ctypes as C
+    import torch
+    from paper_1201_3588_amd import mcrt
+    table = torch.zeros(n_slots, dtype=torch.int64, device="cuda")
+    n_ops = 1 << 28
+    L = mcrt.lib()
+    L.mcrt_bench_random.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_uint64,
+                                    C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p]
+    s = C.c_void_p(stream.cuda_stream)
+    L.mcrt_bench_random(C.c_void_p(table.data_ptr()), n_slots, None, 0, n_ops, 1, 0, None, s)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.mcrt_bench_random(C.c_void_p(table.data_ptr()), n_slots, None, 0, n_ops, 2, 0, None, s)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    issued = int(table.sum().item()) // 2
+    del table
+    return issued / (e0.elapsed_time(e1) / 1e3)
+
+
+def c3_block(n_packets, micro, stream):
+    """The gap + spiral disk with PAHs (128^3 base, depth 3, 2,098,552 leaves,
+    26 species, 200 bins): PAH re-emission rows from the optically thin field
+    (first pass of the PAH iteration, exact solver), then one timed transport
+    pass whose 3.4 GB path-length tally is HBM resident."""
+    import torch
+    import synth
+    from paper_1201_3588_amd import mcrt
+    from paper_1201_3588_amd.pipeline import PahLoop
+    t0 = time.perf_counter()
+    w = synth.c3_gap_spiral(n_packets=n_packets)
+    t_synth = time.perf_counter() - t0
+    loop = PahLoop(w)
+    eng = loop.eng
+    N = w.n_packets
+    J = eng.thin_field()
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    loop.emission(J)
+    p1.record(stream)
+    del J
+    tal = eng.new_tallies(tally_j=True)
+    eng.run(tal, 0, min(N, 2_000_000), N, w.seed, pah_rows=loop.rows)        # warm-up
+    for v in (t for t in tal.values() if t is not None):
+        v.zero_()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    eng.run(tal, 0, N, N, w.seed, pah_rows=loop.rows)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    c = mcrt.u64_view(tal["counters"])
+    cnt = {k: int(c[v]) for k, v in mcrt.CNT.items()}
+    assert cnt["launched"] == N and cnt["launched"] == cnt["escaped"] + cnt["killed"] + cnt["terminated"]
+    alg = 8 * cnt["crossings"] + 16 * (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"])
+    res = {"workload": "gap_spiral_disk_128cube_depth3_2098552leaves_26species_200lambda_1e8packets_pah",
+           "leaves": w.grid.n_cells, "packets": N, "transport_kernel_ms": dt * 1e3,
+           "packets_per_s": N / dt, "crossings_per_s": cnt["crossings"] / dt, "per_pass_counts": cnt,
+           "pah_rows_from_thin_field_ms": p0.elapsed_time(p1),
+           "pah_cells_solved": 2 * w.grid.n_cells, "synth_build_s": t_synth,
+           "roofline": {"bound": "hbm", "achieved": alg / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_transport<float>", "alg_bytes_per_launch": alg}}
+    del tal, loop, eng
+    if micro:
+        rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
+        tr = (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / dt
+        res["random_access_ceiling"] = {"atomics_per_s": rate, "table_bytes": w.species.n_lambda * w.grid.n_cells * 8,
+                                        "transport_atomics_per_s": tr, "frac_of_ceiling": tr / rate}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +123,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--train-passes", type=int, default=3,
                     help="transport passes (other seeds) whose disk fields join the training set")
+    ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
+    ap.add_argument("--c3-packets", type=int, default=100_000_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
                          "the reference for scaling hardware byte counters")
@@ -235,31 +317,15 @@ def main():
     }
 
     if not args.no_micro:
-        # achievable random 64-bit atomic rate over a table of the J tally's size
-        n_slots = w.species.n_lambda * w.grid.n_cells
-        table = torch.zeros(n_slots, dtype=torch.int64, device="cuda")
-        n_ops = 1 << 28
-        L = mcrt.lib()
-        import ctypes as C
-        L.mcrt_bench_random.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_uint64,
-                                        C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p]
-        s = C.c_void_p(stream.cuda_stream)
-        L.mcrt_bench_random(C.c_void_p(table.data_ptr()), n_slots, None, 0, n_ops, 1, 0, None, s)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        L.mcrt_bench_random(C.c_void_p(table.data_ptr()), n_slots, None, 0, n_ops, 2, 0, None, s)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        issued = int(table.sum().item()) // 2
-        dt = e0.elapsed_time(e1) / 1e3
-        atom_rate = issued / dt
+        atom_rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
+        tr_atoms = (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg
         out["random_access_ceiling"] = {
-            "atomics_per_s": atom_rate, "table_bytes": n_slots * 8,
+            "atomics_per_s": atom_rate, "table_bytes": w.species.n_lambda * w.grid.n_cells * 8,
             "gbs_at_16B_per_op": atom_rate * 16 / 1e9,
-            "transport_atomics_per_s": (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg,
-            "frac_of_ceiling": (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg / atom_rate}
-        del table
+            "transport_atomics_per_s": tr_atoms, "frac_of_ceiling": tr_atoms / atom_rate}
+
+    if args.c3:
+        out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream)
 
     if not args.no_cpu:
         import oracle

@@ -493,7 +493,7 @@ __device__ __forceinline__ void fused_hidden(const f32x16* acc, const float* __r
   }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_infer(const InferP p) {
+__global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
   uint16_t* bufA = reinterpret_cast<uint16_t*>(fsm);               // [64][kFP]
   uint16_t* bufB = bufA + kFT * kFP;                                // [64][kFP]
@@ -504,25 +504,52 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const InferP p) {
   const int64_t c0 = (int64_t)blockIdx.x * kFT;
   const int nl = p.nl, ni = p.ni;
 
-  // ---- features (wave w: rows 16 w .. 16 w + 15), standardised, range flag
-  for (int rr = 0; rr < kFT / 4; ++rr) {
-    const int row = wave * (kFT / 4) + rr;
-    const int64_t c = c0 + row;
-    const bool valid = c < p.n;
-    const float* Jc = p.J + c * nl;
-    double sum = 0.0;
-    if (valid)
-      for (int j = lane; j < nl; j += 64) sum += p.cabs[j] * (double)Jc[j] * p.dnu[j];
+  // ---- features (wave w: rows 16 w .. 16 w + 15), standardised, range flag.
+  // Every lane first loads its bins of all 16 rows (n_lambda <= 255 here, so
+  // at most 4 bins per lane), then the rows are reduced and written.
+  constexpr int kR = kFT / 4;
+  double ca[4], dn[4];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    const double inv = sum > 0.0 ? 1.0 / sum : 0.0;
-    const double pa = 4.0 * kPi * sum;
+  for (int k = 0; k < 4; ++k) {
+    const int j = lane + 64 * k;
+    ca[k] = j < nl ? p.cabs[j] : 0.0;
+    dn[k] = j < nl ? p.dnu[j] : 0.0;
+  }
+  float Jv[kR][4];
+#pragma unroll
+  for (int rr = 0; rr < kR; ++rr) {
+    const int64_t c = c0 + wave * kR + rr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = lane + 64 * k;
+      Jv[rr][k] = (c < p.n && j < nl) ? p.J[c * nl + j] : 0.0f;
+    }
+  }
+  double sum[kR];
+#pragma unroll
+  for (int rr = 0; rr < kR; ++rr) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += ca[k] * (double)Jv[rr][k] * dn[k];
+    sum[rr] = s;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) sum[rr] += __shfl_xor(sum[rr], off);
+#pragma unroll
+  for (int rr = 0; rr < kR; ++rr) {
+    const int row = wave * kR + rr;
+    const bool valid = c0 + row < p.n;
+    const double inv = sum[rr] > 0.0 ? 1.0 / sum[rr] : 0.0;
+    const double pa = 4.0 * kPi * sum[rr];
     int bad = 0;
-    for (int j = lane; j < kFW; j += 64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = lane + 64 * k;
       uint16_t h = 0;
       if (valid && j < ni) {
-        const float f = j < nl ? (float)(p.cabs[j] * (double)Jc[j] * p.dnu[j] * inv)
-                               : (float)log10(fmax(pa, 1e-300));
+        const float f = j < nl ? (float)(ca[k] * (double)Jv[rr][k] * dn[k] * inv) : (float)log10(fmax(pa, 1e-300));
         const float x = (f - p.x_mu[j]) / p.x_sd[j];
         if (x < p.x_lo[j] - p.margin || x > p.x_hi[j] + p.margin) bad = 1;
         h = f2bf(x);

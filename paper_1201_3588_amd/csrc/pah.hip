@@ -151,33 +151,38 @@ __global__ void k_pah_bandw(int nl, const double* __restrict__ cband, const doub
 }
 
 // re-emission CDF row per cell: continuum power per bin plus band powers
-// spread by their profiles, running sum normalised to end at exactly 1
+// spread by their profiles, running sum normalised to end at exactly 1.
+// One wave per cell (four per workgroup): chunks of 64 bins are scanned with
+// shuffles, the running sums parked in `rows`, then divided by the total.
 __global__ void __launch_bounds__(256) k_pah_rows(int nl, int nbd, int64_t n, const double* __restrict__ out,
                                                   const double* __restrict__ w, double* __restrict__ rows) {
-  extern __shared__ double sc[];                 // [nl] scan buffer
-  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
   const int no = nbd + nl;
   const double* o = out + c * no;
-  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
-    double e = o[nbd + j];
-    for (int b = 0; b < nbd; ++b) e += o[b] * w[(int64_t)b * nl + j];
-    sc[j] = e;
+  double* r = rows + c * nl;
+  const double ob = lane < nbd ? o[lane] : 0.0;          // band powers, nbd <= 64
+  double carry = 0.0;
+  for (int base = 0; base < nl; base += 64) {
+    const int j = base + lane;
+    double e = j < nl ? o[nbd + j] : 0.0;
+    for (int bd = 0; bd < nbd; ++bd) {                     // every lane takes part in the shuffle
+      const double obd = __shfl(ob, bd);
+      if (j < nl) e += obd * w[(int64_t)bd * nl + j];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(e, off);
+      if (lane >= off) e += y;
+    }
+    e += carry;
+    if (j < nl) r[j] = e;
+    carry = __shfl(e, 63);
   }
-  __syncthreads();
-  // inclusive scan (Hillis-Steele) over nl entries
-  for (int off = 1; off < nl; off <<= 1) {
-    double v[16];
-    int cnt = 0;
-    for (int j = threadIdx.x; j < nl; j += blockDim.x) v[cnt++] = j >= off ? sc[j - off] : 0.0;
-    __syncthreads();
-    cnt = 0;
-    for (int j = threadIdx.x; j < nl; j += blockDim.x) sc[j] += v[cnt++];
-    __syncthreads();
-  }
-  const double tot = sc[nl - 1];
-  for (int j = threadIdx.x; j < nl; j += blockDim.x)
-    rows[c * nl + j] = (j == nl - 1 || !(tot > 0.0)) ? 1.0 : sc[j] / tot;
+  const double tot = carry;
+  for (int j = lane; j < nl; j += 64)
+    r[j] = (j == nl - 1 || !(tot > 0.0)) ? 1.0 : r[j] / tot;
 }
 
 struct SolveP {
@@ -215,28 +220,33 @@ __device__ __forceinline__ double wave_scan_d(double v, int lane) {
   return v;
 }
 
-// B_{f,i} (f > i) for the kNC cells of the workgroup
-__device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, const double* sC,
-                                          const double* sH, int f, int i, double* Bv) {
-  const int M = P.M, nl = P.nl;
-  const int m = P.mtab[(int64_t)f * M + i];
+// B_{f,i} (f > i) for the kNC cells of the workgroup, from the counts
+// m = m(f,i) and m1 = m(f-1,i) (m1 unused when i = f-1)
+__device__ __forceinline__ void cum_rates_at(const SolveP& P, const double* sN, const double* sC,
+                                             const double* sH, int f, int i, int m, int m1, double* Bv) {
+  const int nl = P.nl;
 #pragma unroll
   for (int w = 0; w < kNC; ++w) Bv[w] = sC[w * (nl + 1) + m];
   const double inv = P.invdu[f];
   if (i == f - 1) {
 #pragma unroll
     for (int w = 0; w < kNC; ++w) Bv[w] += inv * sH[w * (nl + 1) + m];
-  } else {
-    const int m1 = P.mtab[(int64_t)(f - 1) * M + i];
-    if (m1 > m) {
-      const double Ui = P.U[i], Uf1 = P.U[f - 1];
-      for (int j = m; j < m1; ++j) {
-        const double wt = ((Ui + P.E[j]) - Uf1) * inv;
+  } else if (m1 > m) {
+    const double Ui = P.U[i], Uf1 = P.U[f - 1];
+    for (int j = m; j < m1; ++j) {
+      const double wt = ((Ui + P.E[j]) - Uf1) * inv;
 #pragma unroll
-        for (int w = 0; w < kNC; ++w) Bv[w] += wt * sN[w * nl + j];
-      }
+      for (int w = 0; w < kNC; ++w) Bv[w] += wt * sN[w * nl + j];
     }
   }
+}
+
+__device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, const double* sC,
+                                          const double* sH, int f, int i, double* Bv) {
+  const int M = P.M;
+  const int m = P.mtab[(int64_t)f * M + i];
+  const int m1 = i < f - 1 ? P.mtab[(int64_t)(f - 1) * M + i] : 0;
+  cum_rates_at(P, sN, sC, sH, f, i, m, m1, Bv);
 }
 
 // kNC cells per workgroup: every cell-independent table entry is loaded once
@@ -312,9 +322,28 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
         double acc[kNC] = {};
         if (kk < bk) {
           const int f = fb + kk;
-          for (int i = g; i < fb; i += 8) {
+          const uint16_t* rowf = P.mtab + (int64_t)f * M;
+          const uint16_t* rowf1 = rowf - M;       // row f-1 (its entry at i = f-1 is unused)
+          int i = g;
+          // four states per pass with all eight index loads issued first
+          for (; i + 24 < fb; i += 32) {
+            int m[4], m1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              m[u] = rowf[i + 8 * u];
+              m1[u] = rowf1[i + 8 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              double Bv[kNC];
+              cum_rates_at(P, sN, sC, sH, f, i + 8 * u, m[u], m1[u], Bv);
+#pragma unroll
+              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i + 8 * u] * Bv[w];
+            }
+          }
+          for (; i < fb; i += 8) {
             double Bv[kNC];
-            cum_rates(P, sN, sC, sH, f, i, Bv);
+            cum_rates_at(P, sN, sC, sH, f, i, rowf[i], rowf1[i], Bv);
 #pragma unroll
             for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * Bv[w];
           }
@@ -549,8 +578,7 @@ int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, h
   if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
   if (n == 0) return MCRT_OK;
   if (!out || !rows) return pfail(c, MCRT_E_INVALID, "null out or rows");
-  if (c->d.n_lambda > 16 * 256) return pfail(c, MCRT_E_UNSUPPORTED, "n_lambda > 4096");
-  k_pah_rows<<<(unsigned)n, 256, sizeof(double) * c->d.n_lambda, s>>>(
+  k_pah_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(
       c->d.n_lambda, c->d.n_bands, n, out, reinterpret_cast<const double*>(c->tables + c->lay.bandw), rows);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("rows launch: ") + hipGetErrorString(e));
