@@ -43,7 +43,7 @@ typedef struct pah_ctx pah_ctx;
 
 typedef struct {
   int32_t M;                  /* enthalpy bins, >= 3 */
-  int32_t n_lambda;           /* wavelength bins, >= 2; M + 3 n_lambda <= 4061 */
+  int32_t n_lambda;           /* wavelength bins, >= 2; 6 M + 13 n_lambda <= 16246 */
   int32_t n_bands;            /* emission bands, 0..64 */
   int32_t pad;
   const double *T;            /* device [M] bin temperatures (K), increasing */

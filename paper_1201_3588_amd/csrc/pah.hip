@@ -222,19 +222,21 @@ __device__ __forceinline__ double wave_scan_d(double v, int lane) {
 
 // B_{f,i} (f > i) for the kNC cells of the workgroup, from the counts
 // m = m(f,i) and m1 = m(f-1,i) (m1 unused when i = f-1)
+// (sU, sInv, sE: the enthalpies, 1/dU and photon energies staged in LDS)
 __device__ __forceinline__ void cum_rates_at(const SolveP& P, const double* sN, const double* sC,
-                                             const double* sH, int f, int i, int m, int m1, double* Bv) {
+                                             const double* sH, const double* sU, const double* sInv,
+                                             const double* sE, int f, int i, int m, int m1, double* Bv) {
   const int nl = P.nl;
 #pragma unroll
   for (int w = 0; w < kNC; ++w) Bv[w] = sC[w * (nl + 1) + m];
-  const double inv = P.invdu[f];
+  const double inv = sInv[f];
   if (i == f - 1) {
 #pragma unroll
     for (int w = 0; w < kNC; ++w) Bv[w] += inv * sH[w * (nl + 1) + m];
   } else if (m1 > m) {
-    const double Ui = P.U[i], Uf1 = P.U[f - 1];
+    const double Ui = sU[i], Uf1 = sU[f - 1];
     for (int j = m; j < m1; ++j) {
-      const double wt = ((Ui + P.E[j]) - Uf1) * inv;
+      const double wt = ((Ui + sE[j]) - Uf1) * inv;
 #pragma unroll
       for (int w = 0; w < kNC; ++w) Bv[w] += wt * sN[w * nl + j];
     }
@@ -242,11 +244,12 @@ __device__ __forceinline__ void cum_rates_at(const SolveP& P, const double* sN, 
 }
 
 __device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, const double* sC,
-                                          const double* sH, int f, int i, double* Bv) {
+                                          const double* sH, const double* sU, const double* sInv,
+                                          const double* sE, int f, int i, double* Bv) {
   const int M = P.M;
   const int m = P.mtab[(int64_t)f * M + i];
   const int m1 = i < f - 1 ? P.mtab[(int64_t)(f - 1) * M + i] : 0;
-  cum_rates_at(P, sN, sC, sH, f, i, m, m1, Bv);
+  cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, m, m1, Bv);
 }
 
 // kNC cells per workgroup: every cell-independent table entry is loaded once
@@ -261,9 +264,19 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
   double* sH = sC + kNC * (nl + 1);             // [kNC][nl + 1] sum_{j>=m} N_j E_j
   double* sBin = sH + kNC * (nl + 1);           // [kNC][kBk * kBk]
   double* sX = sBin + kNC * kBk * kBk;          // [kNC][kBk]
-  int* sScale = reinterpret_cast<int*>(sX + kNC * kBk);   // [kNC]
+  double* sU = sX + kNC * kBk;                  // [M]  enthalpies      (shared by the cells)
+  double* sInv = sU + M;                        // [M]  1 / (U_f - U_{f-1})
+  double* sE = sInv + M;                        // [nl] photon energies
+  int* sScale = reinterpret_cast<int*>(sE + nl);          // [kNC]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
+
+  for (int i = t; i < M; i += kThreads) {
+    sU[i] = P.U[i];
+    sInv[i] = P.invdu[i];
+  }
+  for (int j = t; j < nl; j += kThreads) sE[j] = P.E[j];
+  __syncthreads();
 
   const int64_t n_cells = P.n_dev ? *P.n_dev : P.n;
   const int64_t n_groups = (n_cells + kNC - 1) / kNC;
@@ -302,7 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       if (lane == 0) sH[w * (nl + 1) + nl] = 0.0;
       for (int base = 0; base < nl; base += 64) {
         const int j = nl - 1 - (base + lane);
-        const double v = wave_scan_d(j >= 0 ? sN[w * nl + j] * P.E[j] : 0.0, lane) + carry;
+        const double v = wave_scan_d(j >= 0 ? sN[w * nl + j] * sE[j] : 0.0, lane) + carry;
         if (j >= 0) sH[w * (nl + 1) + j] = v;
         carry = __shfl(v, 63);
       }
@@ -336,14 +349,14 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               double Bv[kNC];
-              cum_rates_at(P, sN, sC, sH, f, i + 8 * u, m[u], m1[u], Bv);
+              cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i + 8 * u, m[u], m1[u], Bv);
 #pragma unroll
               for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i + 8 * u] * Bv[w];
             }
           }
           for (; i < fb; i += 8) {
             double Bv[kNC];
-            cum_rates_at(P, sN, sC, sH, f, i, rowf[i], rowf1[i], Bv);
+            cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, rowf[i], rowf1[i], Bv);
 #pragma unroll
             for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * Bv[w];
           }
@@ -361,7 +374,7 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
         const int fl = q / kBk, col = q % kBk;
         if (col < fl && fl < bk) {
           double Bv[kNC];
-          cum_rates(P, sN, sC, sH, fb + fl, fb + col, Bv);
+          cum_rates(P, sN, sC, sH, sU, sInv, sE, fb + fl, fb + col, Bv);
 #pragma unroll
           for (int w = 0; w < kNC; ++w) sBin[w * kBk * kBk + q] = Bv[w];
         }
@@ -412,6 +425,7 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       }
     for (int q = t; q < no; q += kThreads) {
       double acc[kNC] = {};
+#pragma unroll 8
       for (int i = 1; i < M; ++i) {
         const double e = P.em[(int64_t)i * no + q];
 #pragma unroll
@@ -438,7 +452,8 @@ __global__ void k_compact(const uint8_t* __restrict__ ood, int64_t n, int64_t* _
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
 size_t solve_lds(const pah_desc& d) {
-  return sizeof(double) * kNC * ((size_t)d.M + 3 * (size_t)d.n_lambda + 2 + kBk * kBk + kBk) +
+  return sizeof(double) * (kNC * ((size_t)d.M + 3 * (size_t)d.n_lambda + 2 + kBk * kBk + kBk) +
+                           2 * (size_t)d.M + d.n_lambda) +
          sizeof(int) * kNC;
 }
 
@@ -473,7 +488,7 @@ const char* pcheck(const pah_desc* d) {
   if (d->n_bands < 0 || d->n_bands > 64) return "n_bands must be in 0..64";
   if (!d->T || !d->U || !d->lambda_um || !d->cabs || !d->ccont || (d->n_bands > 0 && !d->cband))
     return "null device array";
-  if (solve_lds(*d) > kMaxLds) return "M + 3 n_lambda exceeds the solver's LDS (at most 4061)";
+  if (solve_lds(*d) > kMaxLds) return "M and n_lambda exceed the solver's LDS (6 M + 13 n_lambda <= 16246)";
   return nullptr;
 }
 int nblocks_of(int M) { return (M - 1 + kBk - 1) / kBk; }

@@ -101,8 +101,8 @@ def test_pah_descriptor_limits():
         return d
 
     assert L.pah_tables_bytes(C.byref(desc(500, 200)), C.byref(nb)) == 0 and nb.value > 500 * 500 * 2
-    assert L.pah_tables_bytes(C.byref(desc(4061 - 3 * 200, 200)), C.byref(nb)) == 0
-    for M, nl in [(2, 200), (500, 1), (4062 - 3 * 200, 200), (500, 1500)]:
+    assert L.pah_tables_bytes(C.byref(desc(2274, 200)), C.byref(nb)) == 0     # 6 M + 13 nl = 16244
+    for M, nl in [(2, 200), (500, 1), (2275, 200), (500, 1500)]:
         assert L.pah_tables_bytes(C.byref(desc(M, nl)), C.byref(nb)) == -1, (M, nl)
         ctx = C.c_void_p()
         assert L.pah_ctx_create(C.byref(desc(M, nl)), C.byref(ctx)) == -1 and not ctx.value
