@@ -210,6 +210,14 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// the value of v in lane l (l wave-uniform), for every lane
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // inclusive prefix sum over the 64 lanes of a wave
 __device__ __forceinline__ double wave_scan_d(double v, int lane) {
 #pragma unroll
@@ -369,9 +377,9 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
           if (g == 0 && kk < kBk) sX[w * kBk + kk] = kk < bk ? acc[w] : 0.0;
         }
       }
-      // in-block entries B_{f,i}, fb <= i < f < eb
+      // in-block entries B_{f,i}, fb <= i < f < eb, column-major: [i - fb][f - fb]
       for (int q = t; q < kBk * kBk; q += kThreads) {
-        const int fl = q / kBk, col = q % kBk;
+        const int col = q / kBk, fl = q % kBk;
         if (col < fl && fl < bk) {
           double Bv[kNC];
           cum_rates(P, sN, sC, sH, sU, sInv, sE, fb + fl, fb + col, Bv);
@@ -380,23 +388,28 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
         }
       }
       __syncthreads();
-      // sequential recurrence: wave w for cell w; lane l holds P_{fb+l}
+      // sequential recurrence, right-looking: wave w for cell w; lane l owns
+      // row fb+l and its running sum S of P_i B_{fb+l,i} over solved i of the
+      // block; each step divides in the owning lane, broadcasts P_f with
+      // v_readlane and updates the later rows with one FMA
       if (wave < kNC) {
         const int w = wave;
-        const double* bin = sBin + w * kBk * kBk;
-        const double* xs = sX + w * kBk;
-        double myP = 0.0;
+        const double* binT = sBin + w * kBk * kBk;
+        const double Al = lane < bk ? P.adown[fb + lane] : 1.0;
+        const double Xl = lane < bk ? sX[w * kBk + lane] : 0.0;
+        double S = 0.0, myP = 0.0;
         int nsc = 0;                       // rescales by 2^-664 inside this block
         for (int fl = 0; fl < bk; ++fl) {
-          const double term = lane < fl ? myP * bin[fl * kBk + lane] : 0.0;
-          const double s = wave_sum_d(term);
-          const double xf = nsc ? ldexp(xs[fl], -664 * nsc) : xs[fl];
-          const double Pf = (xf + s) / P.adown[fb + fl];
+          const double cand = ((nsc ? ldexp(Xl, -664 * nsc) : Xl) + S) / Al;
+          double Pf = readlane_d(cand, fl);
           if (lane == fl) myP = Pf;
           if (Pf > 1e200) {                 // keep the unnormalised P finite
             ++nsc;
             if (lane <= fl) myP = ldexp(myP, -664);
+            S = ldexp(S, -664);
+            Pf = ldexp(Pf, -664);
           }
+          if (lane > fl && lane < bk) S += Pf * binT[fl * kBk + lane];
         }
         if (lane < bk) sP[w * M + fb + lane] = myP;
         if (lane == 0) sScale[w] = nsc;
