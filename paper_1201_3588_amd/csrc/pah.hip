@@ -55,7 +55,7 @@ PahLayout pah_layout(const pah_desc& d) {
   L.E = take(8 * nl);
   L.fac = take(8 * nl);
   L.invdu = take(8 * M);
-  L.mtab = take(2 * M * M);
+  L.mtab = take(4 * M * M);
   L.adown = take(8 * M);
   L.em = take(8 * M * no);
   L.bandw = take(8 * (uint64_t)(d.n_bands > 0 ? d.n_bands : 1) * nl);
@@ -85,22 +85,29 @@ __global__ void k_pah_bins(int nl, int M, const double* __restrict__ lam, const 
 }
 
 // m(f,i) = number of wavelength bins whose photons lift state i to U_f or
-// beyond (a leading run of j: the photon energy falls with j); f > i only
+// beyond (a leading run of j: the photon energy falls with j)
+__device__ int count_reaching(int nl, const double* __restrict__ E, double Ui, double Uf) {
+  int lo = 0, hi = nl;                   // first j with U_i + E_j < U_f
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Uf <= Ui + E[mid]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// both counts a pair (f, i), f > i, needs, in one word:
+// m(f,i) | m(f-1,i) << 16 (the high half is 0 for i = f-1)
 __global__ void k_pah_m(int M, int nl, const double* __restrict__ U, const double* __restrict__ E,
-                        uint16_t* __restrict__ mtab) {
+                        uint32_t* __restrict__ mtab) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)M * M) return;
   const int f = (int)(q / M), i = (int)(q % M);
-  int lo = 0;
+  uint32_t v = 0;
   if (i < f) {
-    const double Uf = U[f], Ui = U[i];
-    int hi = nl;                         // first j with U_i + E_j < U_f
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (Uf <= Ui + E[mid]) lo = mid + 1; else hi = mid;
-    }
+    v = (uint32_t)count_reaching(nl, E, U[i], U[f]);
+    if (i < f - 1) v |= (uint32_t)count_reaching(nl, E, U[i], U[f - 1]) << 16;
   }
-  mtab[q] = (uint16_t)lo;
+  mtab[q] = v;
 }
 
 // cooling rates and emission table
@@ -194,7 +201,7 @@ struct SolveP {
   const double* E;
   const double* fac;
   const double* invdu;
-  const uint16_t* mtab;
+  const uint32_t* mtab;   // m(f,i) | m(f-1,i) << 16
   const double* adown;
   const double* em;
   double* out;
@@ -255,8 +262,8 @@ __device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, con
                                           const double* sH, const double* sU, const double* sInv,
                                           const double* sE, int f, int i, double* Bv) {
   const int M = P.M;
-  const int m = P.mtab[(int64_t)f * M + i];
-  const int m1 = i < f - 1 ? P.mtab[(int64_t)(f - 1) * M + i] : 0;
+  const uint32_t v = P.mtab[(int64_t)f * M + i];
+  const int m = (int)(v & 0xFFFFu), m1 = (int)(v >> 16);
   cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, m, m1, Bv);
 }
 
@@ -343,16 +350,16 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
         double acc[kNC] = {};
         if (kk < bk) {
           const int f = fb + kk;
-          const uint16_t* rowf = P.mtab + (int64_t)f * M;
-          const uint16_t* rowf1 = rowf - M;       // row f-1 (its entry at i = f-1 is unused)
+          const uint32_t* rowf = P.mtab + (int64_t)f * M;
           int i = g;
-          // four states per pass with all eight index loads issued first
+          // four states per pass with all index loads issued first
           for (; i + 24 < fb; i += 32) {
             int m[4], m1[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              m[u] = rowf[i + 8 * u];
-              m1[u] = rowf1[i + 8 * u];
+              const uint32_t v = rowf[i + 8 * u];
+              m[u] = (int)(v & 0xFFFFu);
+              m1[u] = (int)(v >> 16);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -364,7 +371,8 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
           }
           for (; i < fb; i += 8) {
             double Bv[kNC];
-            cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, rowf[i], rowf1[i], Bv);
+            const uint32_t v = rowf[i];
+            cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, (int)(v & 0xFFFFu), (int)(v >> 16), Bv);
 #pragma unroll
             for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * Bv[w];
           }
@@ -517,7 +525,7 @@ SolveP solve_params(const pah_ctx* c) {
   P.E = reinterpret_cast<const double*>(T + L.E);
   P.fac = reinterpret_cast<const double*>(T + L.fac);
   P.invdu = reinterpret_cast<const double*>(T + L.invdu);
-  P.mtab = reinterpret_cast<const uint16_t*>(T + L.mtab);
+  P.mtab = reinterpret_cast<const uint32_t*>(T + L.mtab);
   P.adown = reinterpret_cast<const double*>(T + L.adown);
   P.em = reinterpret_cast<const double*>(T + L.em);
   return P;
@@ -571,7 +579,7 @@ int32_t pah_build_tables(pah_ctx* c, void* tables, uint64_t bytes, hipStream_t s
                                D(L.fac), D(L.invdu));
   const int64_t mm = (int64_t)M * M;
   k_pah_m<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(M, nl, d.U, D(L.E),
-                                                       reinterpret_cast<uint16_t*>(T + L.mtab));
+                                                       reinterpret_cast<uint32_t*>(T + L.mtab));
   k_pah_em<<<M, 256, 0, s>>>(M, nl, d.n_bands, d.T, d.U, D(L.nu), D(L.dnu), d.cabs, d.cband, d.ccont,
                              D(L.adown), D(L.em));
   if (d.n_bands > 0) k_pah_bandw<<<d.n_bands, 256, 0, s>>>(nl, d.cband, D(L.dnu), D(L.bandw));
