@@ -217,6 +217,26 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// The per-cell LDS arrays interleave the kNC = 4 cells ([index][cell]), so the
+// four values at one index are two 16-byte LDS reads.
+static_assert(kNC == 4, "the LDS gathers read four cells at a time");
+__device__ __forceinline__ void ld4(const double* p, double* v) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void ld4_add(const double* p, double s, double* acc) {
+  double v[4];
+  ld4(p, v);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) acc[w] += s * v[w];
+}
+__device__ __forceinline__ void ld4_mul_add(const double* p, const double* x, double* acc) {
+  double v[4];
+  ld4(p, v);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) acc[w] += v[w] * x[w];
+}
+
 // the value of v in lane l (l wave-uniform), for every lane
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
@@ -242,18 +262,15 @@ __device__ __forceinline__ void cum_rates_at(const SolveP& P, const double* sN, 
                                              const double* sH, const double* sU, const double* sInv,
                                              const double* sE, int f, int i, int m, int m1, double* Bv) {
   const int nl = P.nl;
-#pragma unroll
-  for (int w = 0; w < kNC; ++w) Bv[w] = sC[w * (nl + 1) + m];
+  ld4(sC + m * kNC, Bv);
   const double inv = sInv[f];
   if (i == f - 1) {
-#pragma unroll
-    for (int w = 0; w < kNC; ++w) Bv[w] += inv * sH[w * (nl + 1) + m];
+    ld4_add(sH + m * kNC, inv, Bv);
   } else if (m1 > m) {
     const double Ui = sU[i], Uf1 = sU[f - 1];
     for (int j = m; j < m1; ++j) {
       const double wt = ((Ui + sE[j]) - Uf1) * inv;
-#pragma unroll
-      for (int w = 0; w < kNC; ++w) Bv[w] += wt * sN[w * nl + j];
+      ld4_add(sN + j * kNC, wt, Bv);
     }
   }
 }
@@ -270,13 +287,13 @@ __device__ __forceinline__ void cum_rates(const SolveP& P, const double* sN, con
 // kNC cells per workgroup: every cell-independent table entry is loaded once
 // and applied to kNC cells; the in-block recurrence of cell w runs on wave w.
 __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
-  extern __shared__ double sm[];
+  extern __shared__ __attribute__((aligned(16))) double sm[];
   const int M = P.M, nl = P.nl, nbd = P.nbd, nblk = P.nblk;
   const int no = nbd + nl;
-  double* sP = sm;                              // [kNC][M]
-  double* sN = sP + kNC * M;                    // [kNC][nl]     photons per second
-  double* sC = sN + kNC * nl;                   // [kNC][nl + 1] sum_{j<m} N_j
-  double* sH = sC + kNC * (nl + 1);             // [kNC][nl + 1] sum_{j>=m} N_j E_j
+  double* sP = sm;                              // [M][kNC]
+  double* sN = sP + kNC * M;                    // [nl][kNC]     photons per second
+  double* sC = sN + kNC * nl;                   // [nl + 1][kNC] sum_{j<m} N_j
+  double* sH = sC + kNC * (nl + 1);             // [nl + 1][kNC] sum_{j>=m} N_j E_j
   double* sBin = sH + kNC * (nl + 1);           // [kNC][kBk * kBk]
   double* sX = sBin + kNC * kBk * kBk;          // [kNC][kBk]
   double* sU = sX + kNC * kBk;                  // [M]  enthalpies      (shared by the cells)
@@ -311,7 +328,7 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       if (valid[w])
         Jj = P.j_f32 ? (double)reinterpret_cast<const float*>(P.J)[cell[w] * nl + j]
                      : reinterpret_cast<const double*>(P.J)[cell[w] * nl + j];
-      sN[w * nl + j] = P.cabs[j] * Jj * P.fac[j];
+      sN[j * kNC + w] = P.cabs[j] * Jj * P.fac[j];
     }
     __syncthreads();
     // ---- prefix sums C (from the most energetic bin) and H (from the least):
@@ -319,23 +336,23 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
     if (wave < kNC) {
       const int w = wave;
       double carry = 0.0;
-      if (lane == 0) sC[w * (nl + 1)] = 0.0;
+      if (lane == 0) sC[w] = 0.0;
       for (int base = 0; base < nl; base += 64) {
         const int j = base + lane;
-        const double v = wave_scan_d(j < nl ? sN[w * nl + j] : 0.0, lane) + carry;
-        if (j < nl) sC[w * (nl + 1) + j + 1] = v;
+        const double v = wave_scan_d(j < nl ? sN[j * kNC + w] : 0.0, lane) + carry;
+        if (j < nl) sC[(j + 1) * kNC + w] = v;
         carry = __shfl(v, 63);
       }
       carry = 0.0;
-      if (lane == 0) sH[w * (nl + 1) + nl] = 0.0;
+      if (lane == 0) sH[nl * kNC + w] = 0.0;
       for (int base = 0; base < nl; base += 64) {
         const int j = nl - 1 - (base + lane);
-        const double v = wave_scan_d(j >= 0 ? sN[w * nl + j] * sE[j] : 0.0, lane) + carry;
-        if (j >= 0) sH[w * (nl + 1) + j] = v;
+        const double v = wave_scan_d(j >= 0 ? sN[j * kNC + w] * sE[j] : 0.0, lane) + carry;
+        if (j >= 0) sH[j * kNC + w] = v;
         carry = __shfl(v, 63);
       }
-      if (lane == 0 && P.pabs && valid[w]) P.pabs[cell[w]] = sH[w * (nl + 1)];
-      if (lane == 0) { sP[w * M] = 1.0; sScale[w] = 0; }
+      if (lane == 0 && P.pabs && valid[w]) P.pabs[cell[w]] = sH[w];
+      if (lane == 0) { sP[w] = 1.0; sScale[w] = 0; }
     }
     __syncthreads();
 
@@ -365,16 +382,14 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
             for (int u = 0; u < 4; ++u) {
               double Bv[kNC];
               cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i + 8 * u, m[u], m1[u], Bv);
-#pragma unroll
-              for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i + 8 * u] * Bv[w];
+              ld4_mul_add(sP + (i + 8 * u) * kNC, Bv, acc);
             }
           }
           for (; i < fb; i += 8) {
             double Bv[kNC];
             const uint32_t v = rowf[i];
             cum_rates_at(P, sN, sC, sH, sU, sInv, sE, f, i, (int)(v & 0xFFFFu), (int)(v >> 16), Bv);
-#pragma unroll
-            for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * Bv[w];
+            ld4_mul_add(sP + i * kNC, Bv, acc);
           }
         }
 #pragma unroll
@@ -403,12 +418,12 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
       if (wave < kNC) {
         const int w = wave;
         const double* binT = sBin + w * kBk * kBk;
-        const double Al = lane < bk ? P.adown[fb + lane] : 1.0;
+        const double rAl = lane < bk ? 1.0 / P.adown[fb + lane] : 0.0;
         const double Xl = lane < bk ? sX[w * kBk + lane] : 0.0;
         double S = 0.0, myP = 0.0;
         int nsc = 0;                       // rescales by 2^-664 inside this block
         for (int fl = 0; fl < bk; ++fl) {
-          const double cand = ((nsc ? ldexp(Xl, -664 * nsc) : Xl) + S) / Al;
+          const double cand = ((nsc ? ldexp(Xl, -664 * nsc) : Xl) + S) * rAl;
           double Pf = readlane_d(cand, fl);
           if (lane == fl) myP = Pf;
           if (Pf > 1e200) {                 // keep the unnormalised P finite
@@ -419,14 +434,14 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
           }
           if (lane > fl && lane < bk) S += Pf * binT[fl * kBk + lane];
         }
-        if (lane < bk) sP[w * M + fb + lane] = myP;
+        if (lane < bk) sP[(fb + lane) * kNC + w] = myP;
         if (lane == 0) sScale[w] = nsc;
       }
       __syncthreads();
       for (int q = t; q < kNC * fb; q += kThreads) {
         const int w = q / fb, i = q % fb;
         const int nsc = sScale[w];
-        if (nsc) sP[w * M + i] = ldexp(sP[w * M + i], -664 * nsc);
+        if (nsc) sP[i * kNC + w] = ldexp(sP[i * kNC + w], -664 * nsc);
       }
       __syncthreads();
     }
@@ -434,23 +449,22 @@ __global__ void __launch_bounds__(kThreads) k_pah_solve(const SolveP P) {
     // ---- normalise (wave w: cell w) and emit
     if (wave < kNC) {
       double tot = 0.0;
-      for (int i = lane; i < M; i += 64) tot += sP[wave * M + i];
+      for (int i = lane; i < M; i += 64) tot += sP[i * kNC + wave];
       tot = wave_sum_d(tot);
-      for (int i = lane; i < M; i += 64) sP[wave * M + i] /= tot;
+      for (int i = lane; i < M; i += 64) sP[i * kNC + wave] /= tot;
     }
     __syncthreads();
     if (P.P_out)
       for (int q = t; q < kNC * M; q += kThreads) {
         const int w = q / M, i = q % M;
-        if (valid[w]) P.P_out[cell[w] * M + i] = sP[w * M + i];
+        if (valid[w]) P.P_out[cell[w] * M + i] = sP[i * kNC + w];
       }
     for (int q = t; q < no; q += kThreads) {
       double acc[kNC] = {};
 #pragma unroll 8
       for (int i = 1; i < M; ++i) {
         const double e = P.em[(int64_t)i * no + q];
-#pragma unroll
-        for (int w = 0; w < kNC; ++w) acc[w] += sP[w * M + i] * e;
+        ld4_add(sP + i * kNC, e, acc);
       }
 #pragma unroll
       for (int w = 0; w < kNC; ++w)
