@@ -150,7 +150,9 @@ int32_t pah_mlp_train_step(pah_mlp *m, const float *X, const float *T, int32_t n
  * solver defines it, pabs (device double [n]), and ood (device uint8 [n]):
  * bit 0 set when a standardised input lies more than in_margin outside the
  * training range, bit 1 when the emitted total differs from P_abs by more than
- * balance_tol (relative).  The network must match the PAH model's shape and
+ * balance_tol (relative).  A cell with no absorbed power gets its exact
+ * answer, out = 0 (the molecule stays in the ground state, which emits
+ * nothing), and no flag.  The network must match the PAH model's shape and
  * the PAH tables must be built. */
 int32_t pah_surrogate_infer(pah_mlp *m, const pah_ctx *ctx, const float *J, int64_t n, double *out,
                             uint8_t *ood, double *pabs, float in_margin, float balance_tol,

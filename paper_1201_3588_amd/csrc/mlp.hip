@@ -301,7 +301,7 @@ __global__ void k_mlp_in(const float* __restrict__ J, int64_t n, int nl, const d
   __syncthreads();
   if (threadIdx.x == 0) {
     pabs[c] = pa;
-    ood[c] = bad ? 1 : 0;
+    ood[c] = (bad && pa > 0.0) ? 1 : 0;     // a dark cell's answer is exact: F = 0
   }
 }
 
@@ -314,7 +314,7 @@ __global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const 
   __shared__ double red[256];
   double s = 0.0;
   for (int q = threadIdx.x; q < no; q += blockDim.x) {
-    const double f = pow(10.0, (double)(Y[c * no + q] * sd[q] + mu[q])) * pabs[c];
+    const double f = pabs[c] > 0.0 ? pow(10.0, (double)(Y[c * no + q] * sd[q] + mu[q])) * pabs[c] : 0.0;
     out[c * no + q] = f;
     s += f;
   }
@@ -556,7 +556,9 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
       }
       bufA[row * kFP + j] = h;
     }
-    bad = __any(bad);
+    // a dark cell (no absorbed power) has the exact answer F = 0 (the
+    // molecule stays in its ground state), whatever its inputs look like
+    bad = __any(bad) && pa > 0.0;
     if (lane == 0) {
       sBad[row] = bad;
       sPabs[row] = pa;
@@ -587,7 +589,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
     for (int r = 0; r < 16; ++r) {
       const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       const float y = acc[cb][r] + bcol;
-      const double F = pow(10.0, (double)(y * sd + mu)) * sPabs[row];
+      const double F = sPabs[row] > 0.0 ? pow(10.0, (double)(y * sd + mu)) * sPabs[row] : 0.0;
       if (c0 + row < p.n) p.out[(c0 + row) * p.no + col] = F;
       rs[r] += F;
     }

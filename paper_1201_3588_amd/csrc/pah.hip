@@ -159,37 +159,57 @@ __global__ void k_pah_bandw(int nl, const double* __restrict__ cband, const doub
 
 // re-emission CDF row per cell: continuum power per bin plus band powers
 // spread by their profiles, running sum normalised to end at exactly 1.
-// One wave per cell (four per workgroup): chunks of 64 bins are scanned with
-// shuffles, the running sums parked in `rows`, then divided by the total.
+// Sixteen cells per workgroup, one wave per cell at a time: the band
+// profiles are staged in LDS once per workgroup (when they fit), chunks of 64
+// bins are scanned with shuffles, and the running sums stay in registers for
+// up to 256 bins (parked in `rows` beyond that) until the total is known.
+constexpr int kRowCells = 16;
+constexpr int kRowLdsMax = 48 * 1024;
+
 __global__ void __launch_bounds__(256) k_pah_rows(int nl, int nbd, int64_t n, const double* __restrict__ out,
-                                                  const double* __restrict__ w, double* __restrict__ rows) {
-  const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= n) return;
-  const int no = nbd + nl;
-  const double* o = out + c * no;
-  double* r = rows + c * nl;
-  const double ob = lane < nbd ? o[lane] : 0.0;          // band powers, nbd <= 64
-  double carry = 0.0;
-  for (int base = 0; base < nl; base += 64) {
-    const int j = base + lane;
-    double e = j < nl ? o[nbd + j] : 0.0;
-    for (int bd = 0; bd < nbd; ++bd) {                     // every lane takes part in the shuffle
-      const double obd = __shfl(ob, bd);
-      if (j < nl) e += obd * w[(int64_t)bd * nl + j];
-    }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double y = __shfl_up(e, off);
-      if (lane >= off) e += y;
-    }
-    e += carry;
-    if (j < nl) r[j] = e;
-    carry = __shfl(e, 63);
+                                                  const double* __restrict__ wg, double* __restrict__ rows,
+                                                  int w_in_lds) {
+  extern __shared__ double sw[];                      // [nbd][nl] when w_in_lds
+  if (w_in_lds) {
+    for (int q = threadIdx.x; q < nbd * nl; q += blockDim.x) sw[q] = wg[q];
+    __syncthreads();
   }
-  const double tot = carry;
-  for (int j = lane; j < nl; j += 64)
-    r[j] = (j == nl - 1 || !(tot > 0.0)) ? 1.0 : r[j] / tot;
+  const double* w = w_in_lds ? sw : wg;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int no = nbd + nl;
+  for (int k = 0; k < kRowCells / 4; ++k) {
+    const int64_t c = (int64_t)blockIdx.x * kRowCells + wave * (kRowCells / 4) + k;
+    if (c >= n) break;                                // wave-uniform
+    const double* o = out + c * no;
+    double* r = rows + c * nl;
+    const double ob = lane < nbd ? o[lane] : 0.0;     // band powers, nbd <= 64
+    double keep[4];
+    double carry = 0.0;
+    for (int base = 0, ch = 0; base < nl; base += 64, ++ch) {
+      const int j = base + lane;
+      double e = j < nl ? o[nbd + j] : 0.0;
+      for (int bd = 0; bd < nbd; ++bd) {              // every lane takes part in the shuffle
+        const double obd = __shfl(ob, bd);
+        if (j < nl) e += obd * w[bd * nl + j];
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(e, off);
+        if (lane >= off) e += y;
+      }
+      e += carry;
+      if (ch < 4) keep[ch & 3] = e;
+      else if (j < nl) r[j] = e;
+      carry = __shfl(e, 63);
+    }
+    const double tot = carry;
+    for (int base = 0, ch = 0; base < nl; base += 64, ++ch) {
+      const int j = base + lane;
+      if (j >= nl) break;
+      const double e = ch < 4 ? keep[ch & 3] : r[j];
+      r[j] = (j == nl - 1 || !(tot > 0.0)) ? 1.0 : e / tot;
+    }
+  }
 }
 
 struct SolveP {
@@ -628,8 +648,11 @@ int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, h
   if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
   if (n == 0) return MCRT_OK;
   if (!out || !rows) return pfail(c, MCRT_E_INVALID, "null out or rows");
-  k_pah_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(
-      c->d.n_lambda, c->d.n_bands, n, out, reinterpret_cast<const double*>(c->tables + c->lay.bandw), rows);
+  const size_t wbytes = sizeof(double) * (size_t)c->d.n_bands * c->d.n_lambda;
+  const int in_lds = wbytes <= (size_t)kRowLdsMax ? 1 : 0;
+  k_pah_rows<<<(unsigned)((n + kRowCells - 1) / kRowCells), 256, in_lds ? wbytes : 0, s>>>(
+      c->d.n_lambda, c->d.n_bands, n, out, reinterpret_cast<const double*>(c->tables + c->lay.bandw), rows,
+      in_lds);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("rows launch: ") + hipGetErrorString(e));
   return MCRT_OK;

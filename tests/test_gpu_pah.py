@@ -85,12 +85,15 @@ def test_sparse_monte_carlo_fields(nc):
     assert np.all(np.abs(g_out[lit].sum(1) / g_pabs[lit] - 1) < 1e-8)
 
 
-def test_reemission_rows_match_oracle():
-    pm = synth.pah_model(200, LAM)
+@pytest.mark.parametrize("nl", [200, 400])
+def test_reemission_rows_match_oracle(nl):
+    # 400 bins: profiles read from global memory, running sums parked in the rows
+    lam = synth.lambda_grid(nl)
+    pm = synth.pah_model(200, lam)
     s = pah.PahSolver.from_model(pm)
-    J = fields(40, seed=5)
+    J = synth.pah_fields(40, lam, seed=5)[0]
     out, _, _ = s.solve(torch.as_tensor(J).cuda())
     rows = s.rows(out).cpu().numpy()
-    ref = oracle.pah_rows(LAM, pm.cband, out.cpu().numpy())
+    ref = oracle.pah_rows(lam, pm.cband, out.cpu().numpy())
     assert np.all(rows[:, -1] == 1.0)
     assert np.max(np.abs(rows - ref)) < 1e-12
