@@ -49,6 +49,8 @@ struct GemmP {
   int ldh;
   const float* Z;       // EPI_DSILU: stored pre-activation [M][ldz]
   int ldz;
+  int kchunk;           // EPI_F32 split over K: blockIdx.z takes [z kchunk, (z+1) kchunk)
+  float* part;          // and writes its partial product to part[z][M][N] (null: no split)
 };
 
 constexpr int BM = 64, BN = 64, BK = 32, PADK = 40;
@@ -83,10 +85,13 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmP p) {
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool split = EPI == EPI_F32 && p.part != nullptr;
+  const int kbeg = split ? (int)blockIdx.z * p.kchunk : 0;
+  const int kend = split ? min(p.K, kbeg + p.kchunk) : p.K;
   f32x16 acc = {};
-  for (int k0 = 0; k0 < p.K; k0 += BK) {
-    load_tile(As, p.A, p.lda, p.ta != 0, m0, k0, p.M, p.K);
-    load_tile(Bs, p.B, p.ldb, p.tb == 0, n0, k0, p.N, p.K);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    load_tile(As, p.A, p.lda, p.ta != 0, m0, k0, p.M, kend);
+    load_tile(Bs, p.B, p.ldb, p.tb == 0, n0, k0, p.N, kend);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
@@ -107,7 +112,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmP p) {
     if (row >= p.M) continue;
     const float v = acc[r] + bcol;
     if (EPI == EPI_F32) {
-      p.C[(int64_t)row * p.ldc + col] = v;
+      if (split) p.part[((int64_t)blockIdx.z * p.M + row) * p.N + col] = acc[r];
+      else p.C[(int64_t)row * p.ldc + col] = v;
     } else if (EPI == EPI_SILU) {
       if (p.C) p.C[(int64_t)row * p.ldc + col] = v;
       p.H[(int64_t)row * p.ldh + col] = f2bf(silu(v));
@@ -124,6 +130,34 @@ hipError_t gemm(const GemmP& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// C = sum over the splits of part[z], in split order (deterministic)
+__global__ void k_split_sum(const float* __restrict__ part, int ks, int M, int N, float* __restrict__ C, int ldc) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * N) return;
+  float acc = 0.0f;
+  for (int z = 0; z < ks; ++z) acc += part[(int64_t)z * M * N + q];
+  C[(q / N) * ldc + q % N] = acc;
+}
+
+constexpr int kMaxSplit = 16;
+
+// weight gradients: few output tiles and a long K (the batch), so K is split
+// until the grid covers the chip; partial tiles go to `part`, then are summed
+hipError_t gemm_f32_split(GemmP p, float* part, hipStream_t s) {
+  const int tiles = ((p.N + BN - 1) / BN) * ((p.M + BM - 1) / BM);
+  int ks = 1;
+  while (ks < kMaxSplit && tiles * ks < 256 && p.K / (2 * ks) >= 4 * BK) ks *= 2;
+  if (ks == 1) return gemm<EPI_F32>(p, s);
+  p.kchunk = ((p.K + ks - 1) / ks + BK - 1) / BK * BK;
+  ks = (p.K + p.kchunk - 1) / p.kchunk;
+  p.part = part;
+  dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM, ks);
+  k_gemm<EPI_F32><<<grid, 256, 0, s>>>(p);
+  const int64_t mn = (int64_t)p.M * p.N;
+  k_split_sum<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(part, ks, p.M, p.N, p.C, p.ldc);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 struct MlpLayout {
   // fp32 parameter block [W1 b1 W2 b2 W3 b3] and three blocks like it
@@ -131,7 +165,7 @@ struct MlpLayout {
   uint64_t oW1, ob1, oW2, ob2, oW3, ob3;     // element offsets inside a block
   uint64_t W1h, W2h, W3h;                    // bf16 copies
   uint64_t x_mu, x_sd, x_lo, x_hi, y_mu, y_sd;
-  uint64_t X16, Z1, H1, Z2, H2, Y, dY16, dZ2, dZ1, loss, Wpk, total;
+  uint64_t X16, Z1, H1, Z2, H2, Y, dY16, dZ2, dZ1, loss, Wpk, part, total;
 };
 
 MlpLayout mlp_layout(int ni, int nh, int no, int batch) {
@@ -174,6 +208,12 @@ MlpLayout mlp_layout(int ni, int nh, int no, int batch) {
   L.dZ1 = take(2 * B * nh);
   L.loss = take(256);
   L.Wpk = take(2ull * 3 * 256 * 256);
+  {
+    uint64_t mx = (uint64_t)no * nh;
+    if ((uint64_t)nh * nh > mx) mx = (uint64_t)nh * nh;
+    if ((uint64_t)nh * ni > mx) mx = (uint64_t)nh * ni;
+    L.part = take(4ull * kMaxSplit * mx);      // split-K partial products
+  }
   L.total = off;
   return L;
 }
@@ -314,7 +354,7 @@ __global__ void k_mlp_out(const float* __restrict__ Y, int64_t n, int no, const 
   __shared__ double red[256];
   double s = 0.0;
   for (int q = threadIdx.x; q < no; q += blockDim.x) {
-    const double f = pabs[c] > 0.0 ? pow(10.0, (double)(Y[c * no + q] * sd[q] + mu[q])) * pabs[c] : 0.0;
+    const double f = pabs[c] > 0.0 ? (double)exp10f(Y[c * no + q] * sd[q] + mu[q]) * pabs[c] : 0.0;
     out[c * no + q] = f;
     s += f;
   }
@@ -588,8 +628,10 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      // 10^z in FP32: the network's own error (BF16 operands, ~1e-3) dwarfs
+      // the exponential's (~1e-7 relative)
       const float y = acc[cb][r] + bcol;
-      const double F = sPabs[row] > 0.0 ? pow(10.0, (double)(y * sd + mu)) * sPabs[row] : 0.0;
+      const double F = sPabs[row] > 0.0 ? (double)exp10f(y * sd + mu) * sPabs[row] : 0.0;
       if (c0 + row < p.n) p.out[(c0 + row) * p.no + col] = F;
       rs[r] += F;
     }
@@ -670,7 +712,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   // dW3 [no][nh] = dY^T H2
   g.M = no; g.N = nh; g.K = (int)n; g.A = dY; g.lda = no; g.ta = 1;
   g.B = at<uint16_t>(m, L.H2); g.ldb = nh; g.tb = 0; g.C = G + L.oW3; g.ldc = nh;
-  hipError_t e = gemm<EPI_F32>(g, s);
+  hipError_t e = gemm_f32_split(g, at<float>(m, L.part), s);
   k_colsum<<<(no + 63) / 64, 64 * kColRows, 0, s>>>(dY, n, no, G + L.ob3);
   // dZ2 = (dY W3) * silu'(Z2); W3 [no][nh] read as (k=o, n=j) -> W3h with tb = 0
   g = GemmP{};
@@ -682,7 +724,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   g = GemmP{};
   g.M = nh; g.N = nh; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ2); g.lda = nh; g.ta = 1;
   g.B = at<uint16_t>(m, L.H1); g.ldb = nh; g.tb = 0; g.C = G + L.oW2; g.ldc = nh;
-  if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
+  if (e == hipSuccess) e = gemm_f32_split(g, at<float>(m, L.part), s);
   k_colsum<<<(nh + 63) / 64, 64 * kColRows, 0, s>>>(at<uint16_t>(m, L.dZ2), n, nh, G + L.ob2);
   // dZ1 = (dZ2 W2) * silu'(Z1)
   g = GemmP{};
@@ -694,7 +736,7 @@ hipError_t backward(pah_mlp* m, int64_t n, hipStream_t s) {
   g = GemmP{};
   g.M = nh; g.N = ni; g.K = (int)n; g.A = at<uint16_t>(m, L.dZ1); g.lda = nh; g.ta = 1;
   g.B = at<uint16_t>(m, L.X16); g.ldb = ni; g.tb = 0; g.C = G + L.oW1; g.ldc = ni;
-  if (e == hipSuccess) e = gemm<EPI_F32>(g, s);
+  if (e == hipSuccess) e = gemm_f32_split(g, at<float>(m, L.part), s);
   k_colsum<<<(nh + 63) / 64, 64 * kColRows, 0, s>>>(at<uint16_t>(m, L.dZ1), n, nh, G + L.ob1);
   if (e != hipSuccess) return e;
   return hipGetLastError();
