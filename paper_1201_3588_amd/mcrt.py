@@ -248,7 +248,10 @@ class Engine:
         o.flags, o.grid_blocks = int(flags), int(grid_blocks)
         keep = []
         if frozen_nabs is not None:
-            fz = torch.as_tensor(np.ascontiguousarray(frozen_nabs, np.uint64).view(np.int64)).to(self.device)
+            if isinstance(frozen_nabs, torch.Tensor):
+                fz = frozen_nabs.contiguous()
+            else:
+                fz = torch.as_tensor(np.ascontiguousarray(frozen_nabs, np.uint64).view(np.int64)).to(self.device)
             keep.append(fz)
             o.frozen_nabs = _ptr(fz)
             o.flags |= FLAG_FROZEN_T
