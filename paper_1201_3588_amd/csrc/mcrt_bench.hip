@@ -1,7 +1,7 @@
 // Random-access microbenchmark: the achievable rate of the transaction mix of
 // the transport kernel (uniformly random 64-bit atomic adds over a tally of the
 // path-length tally's size, random 4-byte loads over the density grid), used
-// as the ceiling against which the traversal kernel is judged.
+// as the ceiling against which the traversal kernel is measured.
 #include "mcrt_internal.h"
 
 namespace {
