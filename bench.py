@@ -109,6 +109,92 @@ def c3_block(n_packets, micro, stream):
     return res
 
 
+def c5_block(n_packets, stream):
+    """The gap + spiral disk with PAHs on a 256^3 base grid (depth 3,
+    16,784,776 leaves, 26 species, 200 bins, 1e9 packets), one pass timed end
+    to end in both forms from the same field: plain (exact PAH solver for both
+    PAH species) and with the surrogate in the loop (exact fallback on flagged
+    cells).  A pass = PAH emission and re-emission rows from the previous
+    field + transport + temperatures + mean intensity.  The surrogates are
+    trained on the disk's own first-pass fields."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1201_3588_amd import mcrt
+    from paper_1201_3588_amd.pah import PahSolver
+    from paper_1201_3588_amd.surrogate import Surrogate, band_error
+    t0 = time.perf_counter()
+    w = synth.c5_full(n_packets=n_packets)
+    t_synth = time.perf_counter() - t0
+    eng = mcrt.Engine.from_workload(w)
+    eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    N, nc, nl = w.n_packets, w.grid.n_cells, w.species.n_lambda
+    solvers = [PahSolver.from_model(pm) for pm in w.pah]
+    rows = torch.empty((len(solvers), nc, nl), dtype=torch.float64, device="cuda")
+    chunk = 1 << 22
+
+    def pah_step(J, surs=None):
+        n_flag = 0
+        for p, s in enumerate(solvers):
+            for a in range(0, nc, chunk):
+                b = min(nc, a + chunk)
+                if surs is None:
+                    out = s.solve(J[a:b])[0]
+                else:
+                    out, ood = surs[p].solve(J[a:b])[:2]
+                    n_flag += int((ood != 0).sum().item())
+                s.rows(out, rows=rows[p, a:b])
+        return n_flag
+
+    def one_pass(J, seed, surs=None):
+        tal = eng.new_tallies(tally_j=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        n_flag = pah_step(J, surs)
+        eng.run(tal, 0, N, N, seed, pah_rows=rows)
+        T = eng.temperatures(tal["nabs"], N)
+        Jn = eng.mean_intensity(tal["jq"], N)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        c = mcrt.u64_view(tal["counters"])
+        del tal, T
+        return Jn, dt, c, n_flag
+
+    J1, t_first, c1, _ = one_pass(eng.thin_field(), w.seed)
+    assert int(c1[0]) == N and int(c1[0]) == int(c1[1] + c1[2] + c1[3])
+    # surrogates trained on a sample of the first pass's lit cells plus synthetic fields
+    t_train = time.perf_counter()
+    lit = torch.nonzero(J1.sum(1) > 0).squeeze(1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    samp = lit[torch.randperm(lit.numel(), generator=g, device="cuda")[:1_000_000]]
+    Jtr = torch.cat([J1.index_select(0, samp),
+                     torch.as_tensor(synth.pah_fields(400_000, w.species.lam_um, seed=4)[0].astype(np.float32)).cuda()])
+    surs, errs = [], []
+    held = lit[torch.randperm(lit.numel(), generator=g, device="cuda")[:200_000]]
+    for s in solvers:
+        sur = Surrogate(s, batch=2048, seed=4)
+        out, pabs = sur.exact(Jtr)
+        sur.fit(Jtr, out, pabs, epochs=12, lr=2e-3)
+        Jh = J1.index_select(0, held)
+        pred, ood, _ = sur.predict(Jh)
+        ex, _ = sur.exact(Jh)
+        ok = (ood == 0) & (ex[:, :17].sum(1) > 0)
+        errs.append(float(torch.quantile(band_error(pred, ex)[ok], 0.95).item()))
+        surs.append(sur)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    _, t_plain, c_plain, _ = one_pass(J1, w.seed + 1)
+    _, t_sur, c_sur, n_flag = one_pass(J1, w.seed + 1, surs)
+    return {"workload": "gap_spiral_disk_256cube_depth3_16784776leaves_26species_200lambda_1e9packets_pah",
+            "leaves": nc, "packets": N, "synth_build_s": t_synth,
+            "pass_plain_s": t_plain, "pass_surrogate_s": t_sur,
+            "packets_per_s_plain": N / t_plain, "packets_per_s_surrogate": N / t_sur,
+            "crossings_per_pass": int(c_plain[6]), "pah_absorptions_per_pass": int(c_plain[9]),
+            "pah_cells_per_pass": len(solvers) * nc, "surrogate_flagged_per_pass": n_flag,
+            "surrogate_band_error_p95": errs, "surrogate_training_s": t_train}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +212,10 @@ def main():
     ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
                     help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
     ap.add_argument("--c3-packets", type=int, default=100_000_000)
+    ap.add_argument("--c5", action="store_true",
+                    help="also time the 256^3 gap + spiral disk (1e9 packets) end to end, plain and "
+                         "with the surrogate in the loop (minutes; needs ~150 GB of device memory)")
+    ap.add_argument("--c5-packets", type=int, default=1_000_000_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
                          "the reference for scaling hardware byte counters")
@@ -326,6 +416,8 @@ def main():
 
     if args.c3:
         out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream)
+    if args.c5:
+        out["c5"] = c5_block(args.c5_packets, stream)
 
     if not args.no_cpu:
         import oracle

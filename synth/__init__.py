@@ -418,7 +418,7 @@ def _disk_density(rho0, gap_spiral=False):
 
 
 def _disk_workload(name, nb, n_packets, seed, nl, gap_spiral, with_pah, n_sizes=8,
-                   max_level=3):
+                   max_level=3, sub=4):
     lam = lambda_grid(nl)
     extra = 30.0 if with_pah else 0.0
     kabs, ksca, names, kV = grain_species(lam, n_sizes=n_sizes, extra_weight=extra)
@@ -441,7 +441,7 @@ def _disk_workload(name, nb, n_packets, seed, nl, gap_spiral, with_pah, n_sizes=
     box = 100.0 * AU
     grid = nested_grid(nb, [-box, -box, -box], 2 * box / nb, max_level,
                        refine_centre=np.zeros(3), refine_radius=1.0 * AU)
-    grid.rho = subsample_density(grid, _disk_density(rho0, gap_spiral))
+    grid.rho = subsample_density(grid, _disk_density(rho0, gap_spiral), sub=sub)
     sp = Species(lam_um=lam, kabs=kabs, ksca=ksca, g=hg_g_disk(lam),
                  kind=np.array(kind, np.int32), names=names)
     src = Source(pos=np.zeros(3), lum=L_SUN, teff=5800.0)
@@ -460,6 +460,13 @@ def c3_gap_spiral(n_packets: int = 100_000_000, seed: int = 3, nl: int = 200,
     """C2 disk x planet gap at 20 AU x log spiral (pitch 15 deg), 128^3 base,
     plus PAH species with 30 and 200 C atoms."""
     return _disk_workload(f"c3_gapspiral{nb}", nb, n_packets, seed, nl, True, True)
+
+
+def c5_full(n_packets: int = 1_000_000_000, seed: int = 5, nl: int = 200, nb: int = 256) -> Workload:
+    """C3 physics on a 256^3 base grid refined to depth 3 inside 1 AU
+    (16,784,776 leaves), 1e9 packets.  Cell densities are means over 2^3
+    sub-samples per leaf (4^3 for the smaller disks) to keep the build short."""
+    return _disk_workload(f"c5_gapspiral{nb}", nb, n_packets, seed, nl, True, True, sub=2)
 
 
 def small_disk(n_packets: int = 20_000, seed: int = 2, nl: int = 40, nb: int = 16,
