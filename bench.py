@@ -186,6 +186,8 @@ def c5_block(n_packets, stream):
     t_train = time.perf_counter() - t_train
     _, t_plain, c_plain, _ = one_pass(J1, w.seed + 1)
     _, t_sur, c_sur, n_flag = one_pass(J1, w.seed + 1, surs)
+    for c in (c_plain, c_sur):
+        assert int(c[0]) == N and int(c[0]) == int(c[1] + c[2] + c[3])
     return {"workload": "gap_spiral_disk_256cube_depth3_16784776leaves_26species_200lambda_1e9packets_pah",
             "leaves": nc, "packets": N, "synth_build_s": t_synth,
             "pass_plain_s": t_plain, "pass_surrogate_s": t_sur,
