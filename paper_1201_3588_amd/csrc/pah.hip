@@ -159,38 +159,36 @@ __global__ void k_pah_bandw(int nl, const double* __restrict__ cband, const doub
 
 // re-emission CDF row per cell: continuum power per bin plus band powers
 // spread by their profiles, running sum normalised to end at exactly 1.
-// Sixteen cells per workgroup, one wave per cell at a time: the band
-// profiles are staged in LDS once per workgroup (when they fit), chunks of 64
-// bins are scanned with shuffles, and the running sums stay in registers for
-// up to 256 bins (parked in `rows` beyond that) until the total is known.
-constexpr int kRowCells = 16;
+// Persistent grid, one wave per cell at a time: the band profiles are staged
+// in LDS once per workgroup (when they fit), a cell's band powers are
+// wave-uniform scalar loads, chunks of 64 bins are scanned with shuffles, and
+// the running sums stay in registers for up to 256 bins (parked in `rows`
+// beyond that) until the total is known.
 constexpr int kRowLdsMax = 48 * 1024;
 
+template <bool W_IN_LDS>
 __global__ void __launch_bounds__(256) k_pah_rows(int nl, int nbd, int64_t n, const double* __restrict__ out,
-                                                  const double* __restrict__ wg, double* __restrict__ rows,
-                                                  int w_in_lds) {
-  extern __shared__ double sw[];                      // [nbd][nl] when w_in_lds
-  if (w_in_lds) {
+                                                  const double* __restrict__ wg, double* __restrict__ rows) {
+  extern __shared__ double sw[];                      // [nbd][nl] when W_IN_LDS
+  if (W_IN_LDS) {
     for (int q = threadIdx.x; q < nbd * nl; q += blockDim.x) sw[q] = wg[q];
     __syncthreads();
   }
-  const double* w = w_in_lds ? sw : wg;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* w = W_IN_LDS ? sw : wg;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int no = nbd + nl;
-  for (int k = 0; k < kRowCells / 4; ++k) {
-    const int64_t c = (int64_t)blockIdx.x * kRowCells + wave * (kRowCells / 4) + k;
-    if (c >= n) break;                                // wave-uniform
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < n; c += (int64_t)gridDim.x * 4) {
     const double* o = out + c * no;
     double* r = rows + c * nl;
-    const double ob = lane < nbd ? o[lane] : 0.0;     // band powers, nbd <= 64
     double keep[4];
     double carry = 0.0;
     for (int base = 0, ch = 0; base < nl; base += 64, ++ch) {
       const int j = base + lane;
-      double e = j < nl ? o[nbd + j] : 0.0;
-      for (int bd = 0; bd < nbd; ++bd) {              // every lane takes part in the shuffle
-        const double obd = __shfl(ob, bd);
-        if (j < nl) e += obd * w[bd * nl + j];
+      double e = 0.0;
+      if (j < nl) {
+        e = o[nbd + j];
+        for (int bd = 0; bd < nbd; ++bd) e += o[bd] * w[bd * nl + j];
       }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
@@ -650,9 +648,13 @@ int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, h
   if (!out || !rows) return pfail(c, MCRT_E_INVALID, "null out or rows");
   const size_t wbytes = sizeof(double) * (size_t)c->d.n_bands * c->d.n_lambda;
   const int in_lds = wbytes <= (size_t)kRowLdsMax ? 1 : 0;
-  k_pah_rows<<<(unsigned)((n + kRowCells - 1) / kRowCells), 256, in_lds ? wbytes : 0, s>>>(
-      c->d.n_lambda, c->d.n_bands, n, out, reinterpret_cast<const double*>(c->tables + c->lay.bandw), rows,
-      in_lds);
+  const int64_t want = (n + 3) / 4;
+  const int64_t blocks = want < (int64_t)c->n_cu * 8 ? want : (int64_t)c->n_cu * 8;
+  const double* wb = reinterpret_cast<const double*>(c->tables + c->lay.bandw);
+  if (in_lds)
+    k_pah_rows<true><<<(unsigned)blocks, 256, wbytes, s>>>(c->d.n_lambda, c->d.n_bands, n, out, wb, rows);
+  else
+    k_pah_rows<false><<<(unsigned)blocks, 256, 0, s>>>(c->d.n_lambda, c->d.n_bands, n, out, wb, rows);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("rows launch: ") + hipGetErrorString(e));
   return MCRT_OK;
