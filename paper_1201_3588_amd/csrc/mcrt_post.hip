@@ -52,7 +52,28 @@ __global__ void __launch_bounds__(256) k_temperatures(
     if (Es[m] <= p) a = m; else b = m;
   }
   double lo = Tk[a], hi = Tk[b];
-  double t = lo * exp(log(hi / lo) * (log(p / Es[a]) / log(Es[b] / Es[a])));
+  // starting point: the table index as a cubic in ln E through the four
+  // nearest table points (ln T is linear in the index), so that one exact
+  // evaluation usually converges
+  double t;
+  {
+    const int k0 = a - 1 < 0 ? 0 : (a + 2 > K - 1 ? K - 4 : a - 1);
+    const double y = log(p);
+    double kk = 0.0;
+    if (K >= 4) {
+      double ys[4];
+      for (int q = 0; q < 4; ++q) ys[q] = log(Es[k0 + q]);
+      for (int q = 0; q < 4; ++q) {
+        double l = 1.0;
+        for (int r = 0; r < 4; ++r)
+          if (r != q) l *= (y - ys[r]) / (ys[q] - ys[r]);
+        kk += l * (double)(k0 + q);
+      }
+    }
+    t = (K >= 4 && kk >= (double)a && kk <= (double)b)
+            ? Tk[0] * exp(log(Tk[K - 1] / Tk[0]) * kk / (double)(K - 1))
+            : lo * exp(log(hi / lo) * (log(p / Es[a]) / log(Es[b] / Es[a])));
+  }
   for (int it = 0; it < 40; ++it) {
     const double it_ = 1.0 / t;
     double e = 0.0, de = 0.0;
