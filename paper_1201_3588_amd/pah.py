@@ -166,6 +166,22 @@ class PahMLP:
         if rc != 0:
             raise MCRTError(rc, f"{what}: {_mlp_lib().pah_mlp_last_error(self.h).decode()}")
 
+    def checkpoint(self):
+        """Host copy of the persistent network state (FP32 masters, gradients,
+        Adam moments, bfloat16 copies, normalisation): the state buffer up to
+        the batch activations.  With the step count and the batch order it
+        resumes training exactly (every training kernel is deterministic)."""
+        torch.cuda.current_stream().synchronize()
+        return self.state[:self.off["X16"]].cpu().clone()
+
+    def restore(self, ck):
+        """Puts back a checkpoint taken from a network of the same shape."""
+        n = self.off["X16"]
+        if ck.numel() != n:
+            raise ValueError("checkpoint of a network of another shape")
+        self.state[:n].copy_(ck.to(self.device))
+        torch.cuda.current_stream().synchronize()
+
     def _shapes(self):
         ni, nh, no = self.n_in, self.n_h, self.n_out
         return [("W1", (nh, ni)), ("b1", (nh,)), ("W2", (nh, nh)), ("b2", (nh,)), ("W3", (no, nh)), ("b3", (no,))]

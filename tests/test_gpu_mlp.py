@@ -128,3 +128,31 @@ def test_inference_matches_reference(nh):
     far = lit & (np.abs(np.abs(ratio - 1) - 0.02) > 1e-9)
     assert np.array_equal((ood[far] & 2) == 2, np.abs(ratio[far] - 1) > 0.02)
     assert np.all(ood[~lit] == 0)            # a dark cell's answer, zero, is exact
+
+
+def test_checkpoint_resumes_training_exactly():
+    # every training kernel is deterministic, so a network restored from a
+    # checkpoint and fed the same batches ends bit-identical to one never stopped
+    rng = np.random.default_rng(31)
+    ni, nh, no, B = 201, 256, 217, 512
+    p = omlp.init_params(ni, nh, no, seed=9)
+    batches = [(torch.as_tensor(rng.normal(size=(B, ni)).astype(np.float32)).cuda(),
+                torch.as_tensor(rng.normal(size=(B, no)).astype(np.float32)).cuda()) for _ in range(6)]
+    a = pah.PahMLP(ni, nh, no, batch=B)
+    a.load(p)
+    ck = None
+    for s, (X, T) in enumerate(batches, start=1):
+        a.train_step(X, T, 1e-3, s)
+        if s == 3:
+            ck = a.checkpoint()
+    b = pah.PahMLP(ni, nh, no, batch=B)
+    b.restore(ck)
+    for s, (X, T) in list(enumerate(batches, start=1))[3:]:
+        b.train_step(X, T, 1e-3, s)
+    torch.cuda.synchronize()
+    n = a.off["X16"]
+    assert torch.equal(a.state[:n], b.state[:n])
+    Y = batches[0][0][:64]
+    assert torch.equal(a.forward(Y), b.forward(Y))
+    with pytest.raises(ValueError):
+        pah.PahMLP(37, 70, 29, batch=64).restore(ck)
