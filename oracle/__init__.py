@@ -22,7 +22,7 @@ _lib = None
 
 CNT = dict(launched=0, escaped=1, killed=2, terminated=3, scatters=4, absorptions=5,
            crossings=6, tclamp_lo=7, tclamp_hi=8, pah_abs=9, zero_cross=10, jseg=11)
-FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB = 1, 2, 4
+FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW = 1, 2, 4, 8
 EV_LAUNCH, EV_CROSS, EV_SCATTER, EV_ABSORB, EV_ESCAPE, EV_KILLED = range(6)
 
 

@@ -356,9 +356,18 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
         }
         if (p->kind[sp] == 0) {
           /* temperature bracket before this absorption:
-           * k = max{k : E_s(T_k) <= N_before eps / (rho V)}, clamped */
+           * k = max{k : E_s(T_k) <= N_before eps / (rho V)}, clamped.
+           * Exact Bjorkman-Wood form: the new frequency follows
+           * kabs [B(T_after) - B(T_before)], with T_before and T_after the
+           * temperatures at N_before and N_before + 1 absorptions.  On the
+           * table this difference is the sum of the bracket rows between the
+           * two, each weighted by the part of [E(T_before), E(T_after)] it
+           * covers; a bracket drawn with those weights is the bracket of a
+           * point spread uniformly over that interval, (N_before + u6) eps/(rho V). */
           double vol = ldexp(h * h * h, -3 * lev);
-          double pw = (double)before * eps / (p->rho[cell] * vol);
+          double nb = (double)before;
+          if (p->flags & ORC_FLAG_EXACT_BW) nb += u[6];
+          double pw = nb * eps / (p->rho[cell] * vol);
           const double *E = t->E + (int64_t)sp * K;
           int kb;
           if (pw < E[0]) { kb = 0; add_u64(&cnt[ORC_CNT_TCLAMP_LO], 1, thr); }

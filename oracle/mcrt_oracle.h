@@ -23,6 +23,7 @@
 #define ORC_FLAG_TALLY_J        1
 #define ORC_FLAG_FROZEN_T       2
 #define ORC_FLAG_KILL_ON_ABSORB 4
+#define ORC_FLAG_EXACT_BW        8
 
 enum {
   ORC_CNT_LAUNCHED = 0, ORC_CNT_ESCAPED, ORC_CNT_KILLED, ORC_CNT_TERMINATED,
