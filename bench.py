@@ -109,6 +109,63 @@ def c3_block(n_packets, micro, stream):
     return res
 
 
+def reemission_block(w, stream, label):
+    """The re-emission law: the paper's (bracket of the temperature before the
+    absorption) against the Bjorkman-Wood difference spectrum of the
+    absorption's own temperature rise, one full pass of each with the same
+    seed and running absorption counts.  Reports the transport rate of each,
+    the mean relative temperature difference per decade of absorptions in the
+    (cell, species) pair with its standard error, and the total-variation
+    distance between the escaping spectra beside that of two seeds of the
+    paper's law (the Monte Carlo noise floor)."""
+    import torch
+    from paper_1201_3588_amd import mcrt
+    eng = mcrt.Engine.from_workload(w)
+    eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    N = w.n_packets
+    runs = {}
+    for name, flags, seed in (("before", 0, w.seed), ("exact_bw", mcrt.FLAG_EXACT_BW, w.seed),
+                              ("before_seed2", 0, w.seed + 7)):
+        tal = eng.new_tallies(tally_j=w.tally_j)
+        fl = flags | (mcrt.FLAG_TALLY_J if w.tally_j else 0)
+        eng.run(tal, 0, min(N, 1_000_000), N, seed, flags=fl)                 # warm-up
+        for v in (t for t in tal.values() if t is not None):
+            v.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        eng.run(tal, 0, N, N, seed, flags=fl)
+        e1.record(stream)
+        T = eng.temperatures(tal["nabs"], N)
+        torch.cuda.synchronize()
+        sed = tal["sed"].reshape(-1, w.species.n_lambda).sum(0).double()
+        runs[name] = dict(ms=e0.elapsed_time(e1), T=T.reshape(-1),
+                          n=tal["nabs"].reshape(-1).double(), sed=sed / sed.sum())
+        del tal
+    a, b = runs["before"], runs["exact_bw"]
+    both = (a["n"] > 0) & (b["n"] > 0)
+    nmean = 0.5 * (a["n"] + b["n"])
+    rel = a["T"] / b["T"] - 1.0
+    bins = []
+    for lo in (1, 10, 100, 1000, 10000, 100000):
+        m = both & (nmean >= lo) & (nmean < 10 * lo)
+        k = int(m.sum().item())
+        if k < 10:
+            continue
+        r = rel[m]
+        bins.append({"n_abs_from": lo, "pairs": k, "mean_rel_T_diff": float(r.mean().item()),
+                     "stderr": float((r.std() / k ** 0.5).item()),
+                     "median_rel_T_diff": float(r.median().item())})
+    tv = 0.5 * float((a["sed"] - b["sed"]).abs().sum().item())
+    tv0 = 0.5 * float((a["sed"] - runs["before_seed2"]["sed"]).abs().sum().item())
+    absorbed = float(a["n"].sum().item())
+    return {"workload": label, "packets": N, "absorptions_per_dusty_pair": absorbed / int((a["n"] > 0).sum().item()),
+            "transport_ms": {"before": a["ms"], "exact_bw": b["ms"]},
+            "packets_per_s": {"before": N / a["ms"] * 1e3, "exact_bw": N / b["ms"] * 1e3},
+            "T_before_over_T_exact_bw_minus_1_by_n_abs": bins,
+            "sed_total_variation": tv, "sed_total_variation_two_seeds": tv0}
+
+
 def c5_block(n_packets, stream):
     """The gap + spiral disk with PAHs on a 256^3 base grid (depth 3,
     16,784,776 leaves, 26 species, 200 bins, 1e9 packets), one pass timed end
@@ -214,6 +271,8 @@ def main():
     ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
                     help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
     ap.add_argument("--c3-packets", type=int, default=100_000_000)
+    ap.add_argument("--reemission", action=argparse.BooleanOptionalAction, default=True,
+                    help="compare the paper's re-emission law with the Bjorkman-Wood one")
     ap.add_argument("--c5", action="store_true",
                     help="also time the 256^3 gap + spiral disk (1e9 packets) end to end, plain and "
                          "with the surrogate in the loop (minutes; needs ~150 GB of device memory)")
@@ -416,6 +475,13 @@ def main():
             "gbs_at_16B_per_op": atom_rate * 16 / 1e9,
             "transport_atomics_per_s": tr_atoms, "frac_of_ceiling": tr_atoms / atom_rate}
 
+    if args.reemission:
+        out["reemission_law"] = [
+            reemission_block(synth.c1_sphere(n_packets=n), stream,
+                             f"uniform_sphere_32cube_100lambda_{n:.0e}packets_f64".replace("+0", ""))
+            for n in (100_000, 1_000_000, 10_000_000)]
+        out["reemission_law"].append(reemission_block(synth.c2_disk(n_packets=N), stream,
+                                                      out["config"]["workload"]))
     if args.c3:
         out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream)
     if args.c5:

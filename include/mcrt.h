@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MCRT_VERSION 101
+#define MCRT_VERSION 102
 
 #define MCRT_OK 0
 #define MCRT_E_INVALID (-1)     /* null pointer, bad size or range */
@@ -52,6 +52,13 @@ extern "C" {
 #define MCRT_FLAG_TALLY_J 1         /* path-length mean-intensity tally */
 #define MCRT_FLAG_FROZEN_T 2        /* temperature bracket from frozen_nabs */
 #define MCRT_FLAG_KILL_ON_ABSORB 4  /* test mode: absorption ends the packet */
+/* Re-emission from the Bjorkman & Wood (2001) difference spectrum
+ * kabs [B(T_after) - B(T_before)] of the absorption's own temperature rise
+ * (the corrected law the paper's method drops, Sec. 2) instead of the bracket
+ * holding T_before: the bracket is looked up at (N_before + u) eps / (rho V),
+ * u the seventh uniform of the event, so the rows between the two temperatures
+ * are drawn in proportion to the energy each covers. */
+#define MCRT_FLAG_EXACT_BW 8
 
 /* counter slots of mcrt_tallies.counters */
 #define MCRT_CNT_LAUNCHED 0

@@ -373,8 +373,14 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
           continue;
         }
         if (P.kind[sp_i] == 0) {
+          // Bracket of the absorbed energy; with the exact Bjorkman-Wood form
+          // a point uniform between the energies before and after this
+          // absorption, which picks the rows spanning T_before..T_after in
+          // proportion to the energy each covers.
           const double vol = ldexp(P.h3, -3 * lev);
-          const double pw = (double)before * P.eps / (P.rho[cell] * vol);
+          double nb = (double)before;
+          if (P.flags & MCRT_FLAG_EXACT_BW) nb += u24(v[2]);
+          const double pw = nb * P.eps / (P.rho[cell] * vol);
           const double* E = P.E + (int64_t)sp_i * P.K;
           int kb;
           if (pw < E[0]) {

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcrt.so")
 
 F32, F64 = 0, 1
-FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB = 1, 2, 4
+FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW = 1, 2, 4, 8
 CNT = dict(launched=0, escaped=1, killed=2, terminated=3, scatters=4, absorptions=5,
            crossings=6, tclamp_lo=7, tclamp_hi=8, pah_abs=9, zero_cross=10, jseg=11)
 ERRORS = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_HIP", -4: "E_CAPACITY",

@@ -107,7 +107,11 @@ def disk_observers(w, npix=25):
                 center=list(w.source.pos), cos_cone=float(np.cos(np.radians(35.0))), lambda_bins=[10, 14, 16])
 
 
-def test_fp64_frozen_tallies_equal_oracle():
+@pytest.mark.parametrize("law", ["before", "exact_bw"])
+def test_fp64_frozen_tallies_equal_oracle(law):
+    # law: re-emission from the bracket holding T_before (the paper's method)
+    # or from the Bjorkman-Wood difference spectrum of the temperature rise
+    extra = mcrt.FLAG_EXACT_BW if law == "exact_bw" else 0
     w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
     w.precision = "f64"
     base = oracle.Session(w).transport()["nabs"]
@@ -115,9 +119,9 @@ def test_fp64_frozen_tallies_equal_oracle():
     obs = disk_observers(w)
     e.set_observers(**obs)
     tal = e.new_tallies()
-    e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T | extra)
     g = host(tal)
-    o = oracle.Session(w, frozen_nabs=base, observers=obs).transport()
+    o = oracle.Session(w, frozen_nabs=base, observers=obs, flags=oracle.FLAG_TALLY_J | extra).transport()
     assert np.array_equal(g["counters"], o["counters"])
     assert np.array_equal(g["nabs"], o["nabs"].reshape(-1))
     assert np.array_equal(g["sed"], o["sed"].reshape(-1))
@@ -125,6 +129,9 @@ def test_fp64_frozen_tallies_equal_oracle():
     assert o["image"].sum() > 100
     assert np.array_equal(g["image"], o["image"].reshape(-1))
     assert np.array_equal(e.counters_sync(tal), o["counters"])
+    if extra:
+        d = oracle.Session(w, frozen_nabs=base, flags=oracle.FLAG_TALLY_J).transport()
+        assert not np.array_equal(d["sed"], o["sed"])
 
 
 def test_images_count_every_in_cone_escape():
@@ -219,19 +226,21 @@ def batch_runs(run, B):
     return rows
 
 
-def statistical_check(w, B=32, seed_gpu=None, seed_orc=None, frozen=None):
+def statistical_check(w, B=32, seed_gpu=None, seed_orc=None, frozen=None, extra_flags=0):
     nb_ = w.n_packets // B
     e = engine(w)
     tal = e.new_tallies(tally_j=w.tally_j)
     sg = seed_gpu if seed_gpu is not None else w.seed
     so = seed_orc if seed_orc is not None else 1000 + w.seed
     flags = (mcrt.FLAG_TALLY_J if w.tally_j else 0) | (mcrt.FLAG_FROZEN_T if frozen is not None else 0)
+    flags |= extra_flags
 
     def gpu_run(b):
         e.run(tal, b * nb_, nb_, w.n_packets, sg, frozen_nabs=frozen, flags=flags)
         return host(tal)
 
-    s = oracle.Session(w, seed=so, n_threads=8, frozen_nabs=frozen)
+    s = oracle.Session(w, seed=so, n_threads=8, frozen_nabs=frozen,
+                       flags=(oracle.FLAG_TALLY_J if w.tally_j else 0) | extra_flags)
     acc = s.new_accumulator()
 
     def orc_run(b):
@@ -248,9 +257,10 @@ def statistical_check(w, B=32, seed_gpu=None, seed_orc=None, frozen=None):
     return res
 
 
-@pytest.mark.parametrize("name", ["c1", "disk_frozen", "disk_frozen_f64"])
+@pytest.mark.parametrize("name", ["c1", "c1_exact_bw", "disk_frozen", "disk_frozen_f64"])
 def test_statistical_parity(name):
-    """c1: the full method (running absorption counts), path-length tally on.
+    """c1: the full method (running absorption counts), path-length tally on;
+    c1_exact_bw: the same with the Bjorkman-Wood re-emission law.
     disk: FP32 and FP64 transport with the temperature bracket taken from a
     frozen absorption field, so the comparison does not depend on the order in
     which concurrently flying packets update the counts.  The disk's per-bin
@@ -260,7 +270,8 @@ def test_statistical_parity(name):
     (test_fp64_frozen_tallies_equal_oracle) instead."""
     frozen = None
     keys = ("sed", "shells", "jq")
-    if name == "c1":
+    extra = mcrt.FLAG_EXACT_BW if name.endswith("exact_bw") else 0
+    if name.startswith("c1"):
         w = synth.c1_sphere(n_packets=320000)
         w.tally_j = True
     else:
@@ -269,7 +280,7 @@ def test_statistical_parity(name):
             w.precision = "f64"
         frozen = oracle.Session(w, n_threads=8).transport()["nabs"]
         keys = ("sed", "shells")
-    res = statistical_check(w, frozen=frozen)
+    res = statistical_check(w, frozen=frozen, extra_flags=extra)
     for k in keys:
         frac, zmax, chi2, n = res[k]
         assert n >= 5, (k, n)
@@ -353,3 +364,29 @@ def test_pah_loop_iterates():
     assert len(h) >= 2 and all(x["pah_abs"] > 0 for x in h)
     conservation(host(res["tallies"]), w.n_packets)
     assert h[-1]["change"] < 0.2
+
+
+def test_exact_bw_correction_vanishes_with_many_absorptions():
+    """The paper drops the Bjorkman-Wood correction, arguing it is negligible
+    once a cell has absorbed many packets (Sec. 2).  On the dust sphere the
+    escaping spectra of the two laws (same seed, running counts) differ by a
+    total-variation distance far above the Monte Carlo noise at ~3 absorptions
+    per cell and fall to that noise at ~200; the exact law costs no speed."""
+    def sed_dist(n, flags, seed):
+        w = synth.c1_sphere(n_packets=n)
+        e = engine(w)
+        tal = e.new_tallies(tally_j=False)
+        e.run(tal, 0, n, n, seed, flags=flags)
+        s = tal["sed"].reshape(-1, w.species.n_lambda).sum(0).double()
+        return s / s.sum()
+
+    tv, noise = {}, {}
+    for n in (100_000, 10_000_000):
+        a = sed_dist(n, 0, 1)
+        b = sed_dist(n, mcrt.FLAG_EXACT_BW, 1)
+        c = sed_dist(n, 0, 8)
+        tv[n] = 0.5 * float((a - b).abs().sum())
+        noise[n] = 0.5 * float((a - c).abs().sum())
+    assert tv[100_000] > 4 * noise[100_000], (tv, noise)
+    assert tv[10_000_000] < 0.05 * tv[100_000], (tv, noise)
+    assert tv[10_000_000] < 3 * noise[10_000_000], (tv, noise)
