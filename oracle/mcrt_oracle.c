@@ -273,6 +273,99 @@ static void image_tally(const orc_problem *p, orc_out *o, const double x[3], con
   }
 }
 
+/* Henyey-Greenstein phase function normalised to a mean of 1 over the sphere:
+ * (1 - g^2) / (1 + g^2 - 2 g mu)^(3/2); isotropic below |g| = 1e-5, as the
+ * deflection sampler. */
+static double hg_phase(double g, double mu) {
+  if (fabs(g) < 1e-5) return 1.0;
+  const double den = 1.0 + g * g - 2.0 * g * mu;
+  return (1.0 - g * g) / (den * sqrt(den));
+}
+
+/* Optical depth at bin j from x (base-cube units, inside leaf `cell` of
+ * depth lev and lower corner lo) along unit n to the edge of the grid, cell
+ * by cell with the transport's own face rules. */
+static double peel_tau(const orc_problem *p, const orc_tables *t, const double x0[3], int cell,
+                       int lev, const int64_t lo0[3], int j, const double n[3]) {
+  const int L = p->L;
+  const int64_t nf = (int64_t)1 << L;
+  const double h = p->base_size;
+  double x[3] = {x0[0], x0[1], x0[2]}, tau = 0.0;
+  int64_t lo[3] = {lo0[0], lo0[1], lo0[2]};
+  for (;;) {
+    const double side = ldexp(1.0, -lev);
+    double tex = INFINITY;
+    int ax = -1;
+    for (int a = 0; a < 3; ++a) {
+      const double boxlo = (double)lo[a] / (double)nf;
+      double ta;
+      if (n[a] > 0.0) ta = (boxlo + side - x[a]) / n[a];
+      else if (n[a] < 0.0) ta = (boxlo - x[a]) / n[a];
+      else continue;
+      if (ta < 0.0) ta = 0.0;
+      if (ta < tex) { tex = ta; ax = a; }
+    }
+    tau += p->rho[cell] * t->kext[j] * h * tex;
+    for (int a = 0; a < 3; ++a) x[a] += tex * n[a];
+    const int64_t span = (int64_t)1 << (L - lev);
+    x[ax] = (double)(n[ax] > 0.0 ? lo[ax] + span : lo[ax]) / (double)nf;
+    int64_t G[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a == ax) G[a] = n[a] > 0.0 ? lo[a] + span : lo[a] - 1;
+      else {
+        int64_t f = (int64_t)floor(x[a] * (double)nf);
+        if (f < lo[a]) f = lo[a];
+        if (f > lo[a] + span - 1) f = lo[a] + span - 1;
+        G[a] = f;
+      }
+    }
+    cell = orc_locate(p, G, &lev, lo);
+    if (cell < 0) return tau;
+  }
+}
+
+/* Next-event (peel-off) images: at every emission (the star's, unless it
+ * is a pencil beam; a re-emission after absorption) and every scattering in
+ * an imaged bin, each
+ * observer receives the packet's chance per unit solid angle of leaving
+ * towards it, times 4 pi: 1 for isotropic emission, hg_phase(g, din . n) for
+ * a scattering of a packet that arrived along din; times exp(-tau) of the
+ * path from the event to the grid edge along n.  The weight is added in
+ * fixed point (round to nearest of 2^24 w) at the pixel of the event's
+ * projection on the image plane (the escape images' axes and pixels).  The
+ * flux of a pixel at distance D is eps / (4 pi D^2) 2^-24 times its sum. */
+static void peel_tally(const orc_problem *p, const orc_tables *t, orc_out *o, const double x[3],
+                       int cell, int lev, const int64_t lo[3], int j, const double *din, int thr) {
+  if (!o->peel || !(p->flags & ORC_FLAG_PEEL) || p->n_obs <= 0 || cell < 0) return;
+  int l = -1;
+  for (int q = 0; q < p->n_img_lambda; ++q) if (p->img_lambda[q] == j) l = q;
+  if (l < 0) return;
+  add_u64(&o->counters[ORC_CNT_PEEL], 1, thr);
+  double X[3];
+  for (int a = 0; a < 3; ++a) X[a] = p->box_min[a] + x[a] * p->base_size - p->img_center[a];
+  for (int ob = 0; ob < p->n_obs; ++ob) {
+    const double *m = p->obs_dir[ob];
+    const double len = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    const double n[3] = {m[0] / len, m[1] / len, m[2] / len};
+    double e1[3], e2[3];
+    const double r = sqrt(n[0] * n[0] + n[1] * n[1]);
+    if (r > 1e-12) { e1[0] = -n[1] / r; e1[1] = n[0] / r; e1[2] = 0.0; }
+    else { e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0; }
+    e2[0] = n[1] * e1[2] - n[2] * e1[1];
+    e2[1] = n[2] * e1[0] - n[0] * e1[2];
+    e2[2] = n[0] * e1[1] - n[1] * e1[0];
+    const double ca = X[0] * e1[0] + X[1] * e1[1] + X[2] * e1[2];
+    const double cb = X[0] * e2[0] + X[1] * e2[1] + X[2] * e2[2];
+    const double w = p->img_half_width;
+    const double fx = floor((ca + w) / (2.0 * w) * p->npix), fy = floor((cb + w) / (2.0 * w) * p->npix);
+    if (fx < 0.0 || fy < 0.0 || fx >= p->npix || fy >= p->npix) continue;
+    const double phase = din ? hg_phase(p->g[j], din[0] * n[0] + din[1] * n[1] + din[2] * n[2]) : 1.0;
+    const double wgt = phase * exp(-peel_tau(p, t, x, cell, lev, lo, j, n));
+    add_u64(&o->peel[(((int64_t)ob * p->n_img_lambda + l) * p->npix + (int64_t)fy) * p->npix + (int64_t)fx],
+            (uint64_t)rint(wgt * 16777216.0), thr);
+  }
+}
+
 /* One packet from launch to escape / kill.  k indexes the trace buffer. */
 static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, uint64_t k,
                        orc_out *o, const int32_t *pah_slot, int thr) {
@@ -300,6 +393,7 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
   int64_t lo[3];
   int cell = orc_locate(p, F, &lev, lo);
   rec(o, k, ORC_EV_LAUNCH, cell, j, x, d, tau);
+  if (!p->beam_on) peel_tally(p, t, o, x, cell, lev, lo, j, NULL, thr);   /* a beam sends nothing sideways */
   if (cell < 0) {
     add_u64(&cnt[ORC_CNT_ESCAPED], 1, thr);
     escape_tally(p, o, d, j, thr);
@@ -340,6 +434,8 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
       }
       draw_slot(p->seed, pid, (uint32_t)events, u);
       if (u[0] <= t->albedo[j]) {
+        const double din[3] = {d[0], d[1], d[2]};
+        peel_tally(p, t, o, x, cell, lev, lo, j, din, thr);
         rotate_dir(d, hg_mu(p->g[j], u[1]), 2.0 * PI * u[2]);
         add_u64(&cnt[ORC_CNT_SCATTERS], 1, thr);
         tau = -log(u[3]);
@@ -386,6 +482,7 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
         }
         iso_dir(2.0 * u[5] - 1.0, 2.0 * PI * u[2], d);
         tau = -log(u[3]);
+        peel_tally(p, t, o, x, cell, lev, lo, j, NULL, thr);
         rec(o, k, ORC_EV_ABSORB, cell, j, x, d, tau);
       }
       continue;

@@ -24,11 +24,13 @@
 #define ORC_FLAG_FROZEN_T       2
 #define ORC_FLAG_KILL_ON_ABSORB 4
 #define ORC_FLAG_EXACT_BW        8
+#define ORC_FLAG_PEEL           16
 
 enum {
   ORC_CNT_LAUNCHED = 0, ORC_CNT_ESCAPED, ORC_CNT_KILLED, ORC_CNT_TERMINATED,
   ORC_CNT_SCATTERS, ORC_CNT_ABSORPTIONS, ORC_CNT_CROSSINGS, ORC_CNT_TCLAMP_LO,
-  ORC_CNT_TCLAMP_HI, ORC_CNT_PAH_ABS, ORC_CNT_ZERO_CROSS, ORC_CNT_JSEG, ORC_N_COUNTERS = 16
+  ORC_CNT_TCLAMP_HI, ORC_CNT_PAH_ABS, ORC_CNT_ZERO_CROSS, ORC_CNT_JSEG, ORC_CNT_PEEL,
+  ORC_N_COUNTERS = 16
 };
 
 enum { ORC_EV_LAUNCH = 0, ORC_EV_CROSS = 1, ORC_EV_SCATTER = 2, ORC_EV_ABSORB = 3,
@@ -93,6 +95,8 @@ typedef struct {
   orc_trace_rec *trace;            /* [n*trace_cap] or NULL */
   int32_t *trace_len;              /* [n] */
   int64_t trace_cap;
+  uint64_t *peel;                  /* [n_obs*n_img_lambda*npix*npix] next-event
+                                      weights, fixed point 2^-24, or NULL */
 } orc_out;
 
 #ifdef __cplusplus
