@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MCRT_VERSION 102
+#define MCRT_VERSION 103
 
 #define MCRT_OK 0
 #define MCRT_E_INVALID (-1)     /* null pointer, bad size or range */
@@ -59,6 +59,8 @@ extern "C" {
  * u the seventh uniform of the event, so the rows between the two temperatures
  * are drawn in proportion to the energy each covers. */
 #define MCRT_FLAG_EXACT_BW 8
+/* Next-event (peel-off) images for the observers; see mcrt_run_opts.peel_queue. */
+#define MCRT_FLAG_PEEL 16
 
 /* counter slots of mcrt_tallies.counters */
 #define MCRT_CNT_LAUNCHED 0
@@ -73,6 +75,8 @@ extern "C" {
 #define MCRT_CNT_PAH_ABS 9
 #define MCRT_CNT_ZERO_CROSS 10   /* zero-length face crossings (ties) */
 #define MCRT_CNT_JSEG 11         /* segments added to the path-length tally */
+#define MCRT_CNT_PEEL 12         /* events queued for the next-event images */
+#define MCRT_CNT_PEEL_DROPPED 13 /* of those, not stored: peel_queue full */
 #define MCRT_N_COUNTERS 16
 
 typedef struct mcrt_ctx mcrt_ctx;
@@ -129,6 +133,9 @@ typedef struct {
   uint64_t *image;             /* [n_obs][n_img_lambda][npix][npix] escaped
                                   packets per pixel (mcrt_observers); NULL
                                   when no observers are set */
+  uint64_t *peel;              /* [n_obs][n_img_lambda][npix][npix] next-event
+                                  weights in units of 2^-24 (MCRT_FLAG_PEEL);
+                                  NULL when the flag is off */
 } mcrt_tallies;
 
 /* Escape images (paper Sec. 2, Fig. 2: the model seen from chosen
@@ -155,6 +162,28 @@ typedef struct {
   double dir[MCRT_MAX_OBSERVERS][3];        /* non-zero; normalised here */
 } mcrt_observers;
 
+/* Next-event (peel-off) images, MCRT_FLAG_PEEL (paper Sec. 4 and Fig. 2: the
+ * disk imaged at 11.3 and 10 um).  At every emission of a packet in an imaged
+ * bin (the star's, unless it is a pencil beam, and each re-emission after an
+ * absorption) and every scattering in an imaged bin, each observer receives
+ * the chance per unit solid angle that the packet leaves towards it, times
+ * 4 pi: 1 for isotropic emission, the Henyey-Greenstein function
+ * (1 - g^2) / (1 + g^2 - 2 g mu)^(3/2) for a scattering (mu: cosine between
+ * the arriving direction and the line of sight; 1 when |g| < 1e-5), times
+ * exp(-tau) of the path from the event to the edge of the grid along the
+ * line of sight, at the pixel of the event's projection on the image plane
+ * (the escape images' axes and pixels).  Each weight w is added as
+ * round-to-nearest(2^24 w) to tallies->peel; a pixel's flux at distance D is
+ * eps / (4 pi D^2) 2^-24 times its sum (erg s^-1 cm^-2 in its bin).  The
+ * transport stores one MCRT_PEEL_REC_BYTES record per such event in
+ * opts->peel_queue (device, caller-owned, peel_capacity records); a second
+ * kernel on the same stream then marches every record's lines of sight.
+ * Events beyond the capacity are counted in MCRT_CNT_PEEL_DROPPED and are
+ * missing from the images: run smaller id ranges.  A source outside the grid
+ * adds no direct light. */
+#define MCRT_PEEL_REC_BYTES 64
+#define MCRT_PEEL_UNIT 16777216.0
+
 /* Per-packet event trace (debug/test only). */
 typedef struct {
   int32_t type, cell, j, pad;  /* type: 0 launch 1 cross 2 scatter 3 absorb 4 escape 5 killed */
@@ -174,6 +203,8 @@ typedef struct {
   int32_t *trace_len;          /* device [n_packets] */
   int32_t trace_cap;
   int32_t pad;
+  void *peel_queue;            /* device, peel_capacity * MCRT_PEEL_REC_BYTES, for MCRT_FLAG_PEEL */
+  uint64_t peel_capacity;      /* records */
 } mcrt_run_opts;
 
 /* Byte offsets of the tables inside the tables buffer (for inspection). */
@@ -215,7 +246,8 @@ int32_t mcrt_set_observers(mcrt_ctx *ctx, const mcrt_observers *obs);
 /* Transports packets with ids [first_id, first_id + n_packets) (paper Sec. 2)
  * and adds their tallies.  Random numbers: Philox4x32-10 keyed by seed,
  * counter (id_lo, id_hi, event, 0|1).  Requires mcrt_build_tables; requires
- * tallies->image when observers are set. */
+ * tallies->image when observers are set; MCRT_FLAG_PEEL requires observers,
+ * tallies->peel, peel_queue and peel_capacity >= 1. */
 int32_t mcrt_run(mcrt_ctx *ctx, uint64_t first_id, uint64_t n_packets,
                  const mcrt_run_opts *opts, const mcrt_tallies *tallies,
                  hipStream_t stream);

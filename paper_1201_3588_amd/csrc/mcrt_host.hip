@@ -204,7 +204,13 @@ int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcr
     return fail(ctx, MCRT_E_INVALID, "TALLY_J needs tallies->jq");
   if ((opts->flags & MCRT_FLAG_FROZEN_T) && !opts->frozen_nabs)
     return fail(ctx, MCRT_E_INVALID, "FROZEN_T needs frozen_nabs");
-  if (opts->flags & ~15) return fail(ctx, MCRT_E_INVALID, "unknown flag bits");
+  if (opts->flags & ~31) return fail(ctx, MCRT_E_INVALID, "unknown flag bits");
+  if (opts->flags & MCRT_FLAG_PEEL) {
+    if (ctx->img.n_obs == 0) return fail(ctx, MCRT_E_INVALID, "PEEL needs observers");
+    if (!tallies->peel) return fail(ctx, MCRT_E_INVALID, "PEEL needs tallies->peel");
+    if (!opts->peel_queue || opts->peel_capacity < 1)
+      return fail(ctx, MCRT_E_INVALID, "PEEL needs peel_queue and peel_capacity >= 1");
+  }
   if (opts->n_total == 0) return fail(ctx, MCRT_E_INVALID, "n_total must be > 0");
   if (opts->trace && (!opts->trace_len || opts->trace_cap < 1))
     return fail(ctx, MCRT_E_INVALID, "trace needs trace_len and trace_cap >= 1");

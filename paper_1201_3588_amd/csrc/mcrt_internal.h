@@ -56,7 +56,8 @@ struct Layout {
 struct RunScratch {
   unsigned long long work_counter;
   unsigned long long bad_input;
-  unsigned long long pad[30];
+  unsigned long long peel_count;     // next-event records claimed by the run
+  unsigned long long pad[29];
 };
 
 Layout make_layout(const mcrt_desc& d);

@@ -52,7 +52,24 @@ struct TP {
   mcrt_trace_rec* trace;
   int32_t* trace_len;
   ImgP img;
+  // next-event images: record queue, its capacity and fill counter, leaf
+  // tables for restarting a march from a record, and the images
+  unsigned char* peel_q;
+  uint64_t peel_cap;
+  unsigned long long* peel_count;
+  const int8_t* level;
+  const int4* leaf_lo;
+  unsigned long long* peel;
 };
+
+// One queued next-event: where (base-cube units, inside leaf `cell`), in which
+// bin, and for a scattering the direction the packet arrived along.
+struct PeelRec {
+  double x[3];
+  double din[3];
+  int32_t cell, j, type, pad;     // type 0: isotropic emission, 1: scattering
+};
+static_assert(sizeof(PeelRec) == MCRT_PEEL_REC_BYTES, "peel record size");
 
 __device__ __forceinline__ float rlog(float v) { return logf(v); }
 __device__ __forceinline__ double rlog(double v) { return log(v); }
@@ -182,6 +199,23 @@ __device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1
   }
 }
 
+// Queues a next-event record when bin j is imaged (rare: a few imaged bins
+// out of the whole grid); records past the capacity are dropped and counted
+// by the march kernel.
+template <typename R>
+__device__ __forceinline__ void peel_push(const TP<R>& P, double x0, double x1, double x2, int cell, int j,
+                                       int type, R d0, R d1, R d2) {
+  bool imaged = false;
+  for (int q = 0; q < P.img.n_l; ++q) imaged |= P.img.lsel[q] == j;
+  if (!imaged) return;
+  const unsigned long long k = atomicAdd(P.peel_count, 1ull);
+  if (k >= P.peel_cap) return;
+  PeelRec* r = reinterpret_cast<PeelRec*>(P.peel_q) + k;
+  r->x[0] = x0; r->x[1] = x1; r->x[2] = x2;
+  r->din[0] = (double)d0; r->din[1] = (double)d1; r->din[2] = (double)d2;
+  r->cell = cell; r->j = j; r->type = type; r->pad = 0;
+}
+
 constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the shared counter
 
 // Packet state: current leaf (integer lower corner lo* in finest units, level
@@ -272,6 +306,8 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
             u1 = (R)(P.y0 - (double)lo1 * ifn);
             u2 = (R)(P.z0 - (double)lo2 * ifn);
             bump(0);
+            if (IMG && P.peel_q && cell >= 0 && !P.beam_on)
+              peel_push(P, P.x0, P.y0, P.z0, cell, j, 0, d0, d1, d2);
             if (TRACE) record(P, kidx, 0, cell, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
             if (cell < 0) {
               bump(1);
@@ -343,6 +379,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
       sincos_rev(u24(w[2]), &sp, &cp);
       if (u24(w[0]) <= s_alb[j]) {
         // scattering: new direction from the phase function
+        if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 1, d0, d1, d2);
         const R mu = (R)hg_mu(P.gpar[j], u24(w[1]));
         const R st = rsqrt0(R(1) - mu * mu);
         if (d2 > R(0.99999) || d2 < R(-0.99999)) {
@@ -408,6 +445,7 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
         d0 = st * cp; d1 = st * sp; d2 = mu;
         set_recip();
         tau = -rlog((R)u24(w[3]));
+        if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 0, d0, d1, d2);
         if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
       }
       continue;
@@ -473,6 +511,114 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
     atomicAdd(&P.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
 }
 
+// Next-event march: one lane per (record, observer).  Optical depth from the
+// record's position along the line of sight to the edge of the grid, cell by
+// cell with the transport's face rules, then the weight (phase function for a
+// scattering, times exp(-tau)) added in fixed point at the record's pixel.
+// Every lane ends: each step moves the finest-level index along the exit axis
+// by at least one in the direction of travel, and a step cap bounds the march.
+template <typename R>
+__global__ void __launch_bounds__(256) k_peel(const TP<R> P) {
+  const unsigned long long cnt = *P.peel_count;
+  const uint64_t n_rec = cnt < P.peel_cap ? cnt : P.peel_cap;
+  const ImgP& I = P.img;
+  const int n_obs = I.n_obs, L = P.L;
+  const uint64_t total = n_rec * (uint64_t)n_obs;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const R inv_nf = P.inv_nf;
+  const R nf = (R)(1 << L);
+  const int max_steps = 4 * (P.nb << L) + 64;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const uint64_t k = i / (uint64_t)n_obs;
+    const int o = (int)(i - k * (uint64_t)n_obs);
+    const PeelRec r = reinterpret_cast<const PeelRec*>(P.peel_q)[k];
+    const int j = r.j;
+    int l = -1;
+    for (int q = 0; q < I.n_l; ++q)
+      if (I.lsel[q] == j) l = q;
+    if (l < 0) continue;
+    const double X0 = I.off[0] + r.x[0] * I.h, X1 = I.off[1] + r.x[1] * I.h, X2 = I.off[2] + r.x[2] * I.h;
+    const double a = X0 * I.e1[o][0] + X1 * I.e1[o][1] + X2 * I.e1[o][2];
+    const double b = X0 * I.e2[o][0] + X1 * I.e2[o][1] + X2 * I.e2[o][2];
+    const double fx = floor((a + I.w) / (2.0 * I.w) * I.npix), fy = floor((b + I.w) / (2.0 * I.w) * I.npix);
+    if (fx < 0.0 || fy < 0.0 || fx >= I.npix || fy >= I.npix) continue;
+    double ph = 1.0;
+    if (r.type == 1) {
+      const double g = P.gpar[j];
+      if (fabs(g) >= 1e-5) {
+        const double mu = r.din[0] * I.n[o][0] + r.din[1] * I.n[o][1] + r.din[2] * I.n[o][2];
+        const double den = 1.0 + g * g - 2.0 * g * mu;
+        ph = (1.0 - g * g) / (den * sqrt(den));
+      }
+    }
+    const R n0 = (R)I.n[o][0], n1 = (R)I.n[o][1], n2 = (R)I.n[o][2];
+    const R kx = sizeof(R) == 8 ? (R)P.kext64[j] : (R)P.kext32[j];
+    int cell = r.cell, lev = P.level[cell];
+    const int4 lo4 = P.leaf_lo[cell];
+    int lo0 = lo4.x, lo1 = lo4.y, lo2 = lo4.z;
+    R dens = sizeof(R) == 8 ? (R)P.rho[cell] : (R)P.rho_h32[cell];
+    R u0 = (R)(r.x[0] - (double)lo0 * (double)inv_nf);
+    R u1 = (R)(r.x[1] - (double)lo1 * (double)inv_nf);
+    R u2 = (R)(r.x[2] - (double)lo2 * (double)inv_nf);
+    R tau = 0;
+    for (int step = 0; step < max_steps; ++step) {
+      const int span = 1 << (L - lev);
+      const R side = (R)span * inv_nf;
+      R tex = (R)INFINITY;
+      int ax = 0;
+      R t;
+      if (n0 != R(0)) {
+        t = (n0 > R(0) ? side - u0 : -u0) / n0;
+        t = t < R(0) ? R(0) : t;
+        if (t < tex) { tex = t; ax = 0; }
+      }
+      if (n1 != R(0)) {
+        t = (n1 > R(0) ? side - u1 : -u1) / n1;
+        t = t < R(0) ? R(0) : t;
+        if (t < tex) { tex = t; ax = 1; }
+      }
+      if (n2 != R(0)) {
+        t = (n2 > R(0) ? side - u2 : -u2) / n2;
+        t = t < R(0) ? R(0) : t;
+        if (t < tex) { tex = t; ax = 2; }
+      }
+      const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)kx * P.h) : dens * kx;
+      tau += alpha * tex;
+      u0 += tex * n0; u1 += tex * n1; u2 += tex * n2;
+      int G0, G1, G2;
+      {
+        const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
+        G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
+        G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
+        G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
+      }
+      if (ax == 0) {
+        u0 = n0 > R(0) ? side : R(0);
+        G0 = n0 > R(0) ? lo0 + span : lo0 - 1;
+      } else if (ax == 1) {
+        u1 = n1 > R(0) ? side : R(0);
+        G1 = n1 > R(0) ? lo1 + span : lo1 - 1;
+      } else {
+        u2 = n2 > R(0) ? side : R(0);
+        G2 = n2 > R(0) ? lo2 + span : lo2 - 1;
+      }
+      const int o0 = lo0, o1 = lo1, o2 = lo2;
+      cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
+      if (cell < 0) break;
+      u0 += (R)(o0 - lo0) * inv_nf;
+      u1 += (R)(o1 - lo1) * inv_nf;
+      u2 += (R)(o2 - lo2) * inv_nf;
+    }
+    const double wgt = ph * exp(-(double)tau);
+    atomicAdd(&P.peel[(((int64_t)o * I.n_l + l) * I.npix + (int64_t)fy) * I.npix + (int64_t)fx],
+              (unsigned long long)rint(wgt * MCRT_PEEL_UNIT));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (cnt) atomicAdd(&P.counters[MCRT_CNT_PEEL], cnt);
+    if (cnt > P.peel_cap) atomicAdd(&P.counters[MCRT_CNT_PEEL_DROPPED], cnt - P.peel_cap);
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
@@ -525,6 +671,16 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   P.img = c->img;
   P.img.image = reinterpret_cast<unsigned long long*>(t.image);
   const bool img = c->img.n_obs > 0;
+  const bool peel = img && (o.flags & MCRT_FLAG_PEEL);
+  if (peel) {
+    P.peel_q = static_cast<unsigned char*>(o.peel_queue);
+    P.peel_cap = o.peel_capacity;
+    P.peel_count = &scr->peel_count;
+    P.level = reinterpret_cast<const int8_t*>(T + L.level);
+    P.leaf_lo = reinterpret_cast<const int4*>(T + L.leaf_lo);
+    P.peel = reinterpret_cast<unsigned long long*>(t.peel);
+    k_zero_u64<<<1, 64, 0, s>>>(&scr->peel_count, 1);
+  }
   k_zero_u64<<<1, 64, 0, s>>>(&scr->work_counter, 1);
   const uint64_t want = (n + 255) / 256;
   const size_t lds = (size_t)d.n_lambda * (2 * sizeof(double) + sizeof(R));
@@ -538,6 +694,7 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   if (blocks > want) blocks = want;
   if (blocks < 1) blocks = 1;
   kern<<<(unsigned)blocks, 256, lds, s>>>(P);
+  if (peel) k_peel<R><<<(unsigned)(c->n_cu * 4), 256, 0, s>>>(P);
   return hipGetLastError();
 }
 

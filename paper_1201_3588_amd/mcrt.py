@@ -17,9 +17,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcrt.so")
 
 F32, F64 = 0, 1
-FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW = 1, 2, 4, 8
+FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW, FLAG_PEEL = 1, 2, 4, 8, 16
+PEEL_REC_BYTES = 64
+PEEL_UNIT = 1 << 24                     # fixed-point unit of the next-event images
 CNT = dict(launched=0, escaped=1, killed=2, terminated=3, scatters=4, absorptions=5,
-           crossings=6, tclamp_lo=7, tclamp_hi=8, pah_abs=9, zero_cross=10, jseg=11)
+           crossings=6, tclamp_lo=7, tclamp_hi=8, pah_abs=9, zero_cross=10, jseg=11, peel=12,
+           peel_dropped=13)
 ERRORS = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_HIP", -4: "E_CAPACITY",
           -5: "E_NUMERIC", -6: "E_UNSUPPORTED"}
 
@@ -43,7 +46,7 @@ class Source(C.Structure):
 
 
 class Tallies(C.Structure):
-    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp), ("image", _dp)]
+    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp), ("image", _dp), ("peel", _dp)]
 
 
 class Observers(C.Structure):
@@ -56,7 +59,8 @@ class RunOpts(C.Structure):
     _fields_ = [("n_total", C.c_uint64), ("seed", C.c_uint64), ("max_events", C.c_uint64),
                 ("flags", C.c_int32), ("grid_blocks", C.c_int32),
                 ("frozen_nabs", _dp), ("pah_rows", _dp), ("trace", _dp), ("trace_len", _dp),
-                ("trace_cap", C.c_int32), ("pad", C.c_int32)]
+                ("trace_cap", C.c_int32), ("pad", C.c_int32),
+                ("peel_queue", _dp), ("peel_capacity", C.c_uint64)]
 
 
 class TableLayout(C.Structure):
@@ -205,8 +209,10 @@ class Engine:
                                             self.tables.numel(), _stream()), "mcrt_build_tables")
 
     def set_observers(self, dirs=(), npix=1, half_width=1.0, center=(0.0, 0.0, 0.0), cos_cone=1.0,
-                      lambda_bins=()):
-        """Escape images (see mcrt_observers); no directions turns them off."""
+                      lambda_bins=(), peel=False, peel_capacity=1 << 22):
+        """Escape images (see mcrt_observers); no directions turns them off.
+        peel: also next-event images (MCRT_FLAG_PEEL) in tallies["peel"], with a
+        device queue of peel_capacity records held by the engine."""
         ob = Observers()
         ob.n_obs, ob.npix, ob.n_img_lambda = len(dirs), int(npix), len(lambda_bins)
         for q, jb in enumerate(lambda_bins):
@@ -218,6 +224,12 @@ class Engine:
                 ob.dir[q][a] = float(dv[a])
         self._check(lib().mcrt_set_observers(self.ctx, C.byref(ob)), "mcrt_set_observers")
         self.image_shape = (len(dirs), len(lambda_bins), int(npix), int(npix)) if len(dirs) else None
+        self.peel_on = bool(peel) and len(dirs) > 0
+        if self.peel_on:
+            cap = int(peel_capacity)
+            if getattr(self, "_peel_q", None) is None or self._peel_q.numel() < cap * PEEL_REC_BYTES:
+                self._peel_q = torch.empty(cap * PEEL_REC_BYTES, dtype=torch.uint8, device=self.device)
+            self.peel_capacity = cap
 
     def new_tallies(self, tally_j=True):
         z = lambda n: torch.zeros(int(n), dtype=torch.int64, device=self.device)
@@ -226,11 +238,12 @@ class Engine:
                     sed=z(self.n_theta * self.n_phi * self.n_lambda),
                     jq=z(self.n_lambda * self.n_cells) if tally_j else None,
                     counters=z(16),
-                    image=z(np.prod(shape)) if shape else None)
+                    image=z(np.prod(shape)) if shape else None,
+                    peel=z(np.prod(shape)) if shape and getattr(self, "peel_on", False) else None)
 
     def counters_sync(self, tallies):
         """The run counters as numpy uint64, after the stream has drained."""
-        t = Tallies(None, None, None, _ptr(tallies["counters"]), None)
+        t = Tallies(None, None, None, _ptr(tallies["counters"]), None, None)
         out = np.zeros(16, np.uint64)
         rc = lib().mcrt_read_counters_sync(C.byref(t), out.ctypes.data, _stream())
         if rc != 0:
@@ -242,10 +255,13 @@ class Engine:
         if flags is None:
             flags = FLAG_TALLY_J if tallies.get("jq") is not None else 0
         t = Tallies(_ptr(tallies["nabs"]), _ptr(tallies["sed"]), _ptr(tallies.get("jq")),
-                    _ptr(tallies["counters"]), _ptr(tallies.get("image")))
+                    _ptr(tallies["counters"]), _ptr(tallies.get("image")), _ptr(tallies.get("peel")))
         o = RunOpts()
         o.n_total, o.seed, o.max_events = int(n_total), int(seed), int(max_events)
         o.flags, o.grid_blocks = int(flags), int(grid_blocks)
+        if getattr(self, "peel_on", False) and tallies.get("peel") is not None:
+            o.flags |= FLAG_PEEL
+            o.peel_queue, o.peel_capacity = _ptr(self._peel_q), self.peel_capacity
         keep = []
         if frozen_nabs is not None:
             if isinstance(frozen_nabs, torch.Tensor):

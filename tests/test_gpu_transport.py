@@ -117,12 +117,21 @@ def test_fp64_frozen_tallies_equal_oracle(law):
     base = oracle.Session(w).transport()["nabs"]
     e = engine(w)
     obs = disk_observers(w)
-    e.set_observers(**obs)
+    e.set_observers(**obs, peel=True)
     tal = e.new_tallies()
     e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T | extra)
     g = host(tal)
-    o = oracle.Session(w, frozen_nabs=base, observers=obs, flags=oracle.FLAG_TALLY_J | extra).transport()
+    o = oracle.Session(w, frozen_nabs=base, observers=obs,
+                       flags=oracle.FLAG_TALLY_J | oracle.FLAG_PEEL | extra).transport()
     assert np.array_equal(g["counters"], o["counters"])
+    assert int(o["counters"][oracle.CNT["peel"]]) > 1000
+    # next-event weights: the same events and lines of sight; the optical
+    # depths of the two sides differ in the last bits (cell-local against
+    # global coordinates), which can move a rounding to 2^-24 by one unit
+    gp, op = g["peel"].astype(np.int64), o["peel"].reshape(-1).astype(np.int64)
+    assert op.sum() > 1000 * oracle.PEEL_ONE
+    assert np.abs(gp - op).max() <= 2
+    assert abs(int(gp.sum()) - int(op.sum())) <= 1e-12 * op.sum() + 50
     assert np.array_equal(g["nabs"], o["nabs"].reshape(-1))
     assert np.array_equal(g["sed"], o["sed"].reshape(-1))
     assert np.array_equal(g["jq"], o["jq"].reshape(-1))
@@ -132,6 +141,40 @@ def test_fp64_frozen_tallies_equal_oracle(law):
     if extra:
         d = oracle.Session(w, frozen_nabs=base, flags=oracle.FLAG_TALLY_J).transport()
         assert not np.array_equal(d["sed"], o["sed"])
+
+
+def test_peel_fp32_and_queue_overflow():
+    # FP32 transport against the FP64 oracle with equal random numbers: the
+    # direct starlight (star pixel) agrees to FP32 rounding of the optical
+    # depth, every image's total to the few packets whose histories part;
+    # a queue too small for the run keeps what fits and counts the rest
+    w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
+    base = oracle.Session(w).transport()["nabs"]
+    obs = disk_observers(w)
+    e = engine(w)
+    e.set_observers(**obs, peel=True)
+    tal = e.new_tallies()
+    e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    g = host(tal)
+    o = oracle.Session(w, frozen_nabs=base, observers=obs, flags=oracle.FLAG_TALLY_J | oracle.FLAG_PEEL).transport()
+    gp = g["peel"].reshape(o["peel"].shape).astype(np.float64)
+    op = o["peel"].astype(np.float64)
+    c = obs["npix"] // 2
+    assert g["counters"][mcrt.CNT["peel_dropped"]] == 0
+    assert abs(int(g["counters"][mcrt.CNT["peel"]]) - int(o["counters"][oracle.CNT["peel"]])) <= 0.02 * o["counters"][oracle.CNT["peel"]]
+    for ob in range(op.shape[0]):
+        for l in range(op.shape[1]):
+            assert abs(gp[ob, l].sum() - op[ob, l].sum()) <= 0.03 * op[ob, l].sum() + oracle.PEEL_ONE
+    # the star's pixel: launches are identical on both sides
+    assert np.allclose(gp[:, :, c, c], op[:, :, c, c], rtol=0.03)
+    e.set_observers(**obs, peel=True, peel_capacity=50)
+    small = e.new_tallies()
+    e.run(small, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    s = host(small)
+    n_ev = int(s["counters"][mcrt.CNT["peel"]])
+    assert n_ev == int(g["counters"][mcrt.CNT["peel"]])
+    assert int(s["counters"][mcrt.CNT["peel_dropped"]]) == n_ev - 50
+    assert 0 < s["peel"].sum() < g["peel"].sum()
 
 
 def test_images_count_every_in_cone_escape():
