@@ -100,6 +100,7 @@ def c3_block(n_packets, micro, stream):
            "roofline": {"bound": "hbm", "achieved": alg / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": alg / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "k_transport<float>", "alg_bytes_per_launch": alg}}
+    res["images"] = images_block(w, eng, loop.rows, stream, dt)
     del tal, loop, eng
     if micro:
         rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
@@ -164,6 +165,68 @@ def reemission_block(w, stream, label):
             "packets_per_s": {"before": N / a["ms"] * 1e3, "exact_bw": N / b["ms"] * 1e3},
             "T_before_over_T_exact_bw_minus_1_by_n_abs": bins,
             "sed_total_variation": tv, "sed_total_variation_two_seeds": tv0}
+
+
+def images_block(w, eng, rows, stream, plain_s):
+    """The paper's Fig. 2 on the gap + spiral disk: next-event images at the
+    bins holding 10 and 11.3 um, face-on and inclined by 60 deg, 401 x 401
+    pixels over the 200 AU box, one full pass with the images on (its extra
+    time over the plain pass is the image cost); then the ELT point spread
+    function (50 mas FWHM at 50 pc, 2.5 AU) and the face-on 11.3 um radial
+    profile across the planet's gap at 20 AU, before and after the PSF."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1201_3588_amd import mcrt
+    AU, PC = synth.AU, 3.0856775814913673e18
+    lam = np.asarray(w.species.lam_um)
+    bins = [int(np.argmin(np.abs(np.log(lam / t)))) for t in (10.0, 11.3)]
+    npix, half = 401, 100.0 * AU
+    incl = np.radians(60.0)
+    eng.set_observers(dirs=[(0.0, 0.0, 1.0), (0.0, -np.sin(incl), np.cos(incl))], npix=npix, half_width=half,
+                      center=(0.0, 0.0, 0.0), cos_cone=float(np.cos(np.radians(10.0))), lambda_bins=bins,
+                      peel=True, peel_capacity=1 << 25)
+    tal = eng.new_tallies(tally_j=True)
+    N = w.n_packets
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    eng.run(tal, 0, N, N, w.seed, pah_rows=rows)
+    e1.record(stream)
+    c = eng.counters_sync(tal)
+    t_img = e0.elapsed_time(e1) / 1e3
+    pix_au = 2.0 * half / npix / AU
+    fwhm_pix = 2.5 / pix_au
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    eps = w.source.lum / N
+    D = 50.0 * PC
+    dnu = torch.as_tensor(eng.tables_numpy()["dnu"][bins], device="cuda")
+    p0.record(stream)
+    conv = mcrt.image_psf(tal["peel"], npix, eps / (4 * np.pi * D * D) / mcrt.PEEL_UNIT, fwhm_pix)
+    p1.record(stream)
+    raw = tal["peel"].double().reshape(2, 2, npix, npix) * (eps / (4 * np.pi * D * D) / mcrt.PEEL_UNIT)
+    conv = conv.reshape(2, 2, npix, npix)
+    torch.cuda.synchronize()
+    jy = 1e23 / dnu.reshape(1, 2, 1, 1)                 # erg s^-1 cm^-2 per bin -> Jy
+
+    def radial(img):
+        yy, xx = torch.meshgrid(torch.arange(npix, device="cuda"), torch.arange(npix, device="cuda"), indexing="ij")
+        rr = torch.sqrt(((xx - npix // 2) * pix_au) ** 2 + ((yy - npix // 2) * pix_au) ** 2)
+        prof = {}
+        for r_au in (15.0, 20.0, 25.0):
+            m = (rr >= r_au - 1.0) & (rr < r_au + 1.0)
+            prof[r_au] = float(img[m].mean().item())
+        return prof
+    pr, pc = radial(raw[0, 1] * jy[0, 1]), radial(conv[0, 1] * jy[0, 1])
+    return {"bins": bins, "lambda_um": [float(lam[b]) for b in bins], "npix": npix, "pixel_au": pix_au,
+            "pass_with_images_ms": t_img * 1e3, "pass_plain_ms": plain_s * 1e3,
+            "image_cost_fraction": t_img / plain_s - 1.0,
+            "next_event_records": int(c[mcrt.CNT["peel"]]), "dropped": int(c[mcrt.CNT["peel_dropped"]]),
+            "psf_fwhm_pix": fwhm_pix, "psf_ms_4_images": p0.elapsed_time(p1),
+            "total_flux_jy": (raw * jy).sum(dim=(2, 3)).tolist(),
+            "faceon_11um_gap_contrast_raw": {"I20_over_I15": pr[20.0] / pr[15.0], "I20_over_I25": pr[20.0] / pr[25.0]},
+            "faceon_11um_gap_contrast_psf": {"I20_over_I15": pc[20.0] / pc[15.0], "I20_over_I25": pc[20.0] / pc[25.0]}}
 
 
 def c5_block(n_packets, stream):

@@ -272,6 +272,24 @@ int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
  * side.  J_out: device float [n_cells * n_lambda]. */
 int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
 
+/* Images through a telescope (paper Sec. 4, Fig. 2: the instrument's point
+ * spread function, 50 mas at 10 um).  Each of the n_images [npix][npix]
+ * images in `image` (device, uint64 sums such as tallies->peel or
+ * tallies->image) is multiplied by `scale` and convolved with a Gaussian of
+ * full width at half maximum fwhm_pix pixels (sigma = fwhm / (2 sqrt(2 ln 2))),
+ * truncated to |dx|, |dy| <= r = mcrt_psf_radius(fwhm_pix) = ceil(3 sigma) and
+ * normalised to unit sum over that square (the 2-D weights are the outer
+ * product of the 1-D ones); pixels outside an image count as zero, so flux
+ * closer than r to the edge is partly lost.  fwhm_pix = 0 copies the scaled
+ * image.  weights: device double [2 r + 1] scratch, receives the 1-D weights.
+ * out: device double [n_images][npix][npix].  Returns MCRT_E_INVALID for
+ * null pointers, npix outside 1..4096 or fwhm_pix outside
+ * [0, MCRT_PSF_MAX_FWHM]; asynchronous on stream. */
+#define MCRT_PSF_MAX_FWHM 32.0
+int32_t mcrt_psf_radius(double fwhm_pix);
+int32_t mcrt_image_psf(const uint64_t *image, int32_t n_images, int32_t npix, double scale,
+                       double fwhm_pix, double *weights, double *out, hipStream_t stream);
+
 /* Copies the MCRT_N_COUNTERS counters of `tallies` to host memory and waits
  * for the stream (so for every launch queued on it before). */
 int32_t mcrt_read_counters_sync(const mcrt_tallies *tallies, uint64_t *host_out, hipStream_t stream);

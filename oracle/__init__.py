@@ -322,3 +322,28 @@ def pah_rows(lam_um, cband, out):
     rows = np.zeros((o.shape[0], lam.size))
     lib().orc_pah_rows(lam.size, cb.shape[0], _p(lam), _p(cb), _p(o), o.shape[0], _p(rows))
     return rows
+
+
+def psf_convolve(images, scale, fwhm_pix):
+    """Images [..., npix, npix] times scale, convolved with a Gaussian point
+    spread function of full width at half maximum fwhm_pix pixels (paper
+    Sec. 4, Fig. 2): sigma = fwhm / (2 sqrt(2 ln 2)), taps |dx|, |dy| <= r =
+    ceil(3 sigma), weights exp(-(dx^2 + dy^2) / (2 sigma^2)) normalised to unit
+    sum over that square, zero outside the image.  Plain sum over shifts."""
+    img = np.asarray(images, dtype=np.float64) * float(scale)
+    sigma = fwhm_pix / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    r = int(np.ceil(3.0 * sigma))
+    if sigma > 0:
+        d = np.arange(-r, r + 1, dtype=np.float64)
+        w1 = np.exp(-d * d / (2.0 * sigma * sigma))
+        w1 /= w1.sum()
+    else:
+        w1 = np.ones(1)
+    n = img.shape[-1]
+    pad = np.zeros(img.shape[:-2] + (n + 2 * r, n + 2 * r))
+    pad[..., r:r + n, r:r + n] = img
+    out = np.zeros_like(img)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            out += w1[dy + r] * w1[dx + r] * pad[..., r + dy:r + dy + n, r + dx:r + dx + n]
+    return out

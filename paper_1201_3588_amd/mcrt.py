@@ -102,6 +102,10 @@ def lib():
         L.mcrt_set_observers.restype = C.c_int32
         L.mcrt_read_counters_sync.argtypes = [C.POINTER(Tallies), P, P]
         L.mcrt_read_counters_sync.restype = C.c_int32
+        L.mcrt_psf_radius.argtypes = [C.c_double]
+        L.mcrt_psf_radius.restype = C.c_int32
+        L.mcrt_image_psf.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, P, P, P]
+        L.mcrt_image_psf.restype = C.c_int32
         for name in ("mcrt_tables_bytes", "mcrt_ctx_create", "mcrt_table_layout_get", "mcrt_build_tables",
                      "mcrt_run", "mcrt_temperatures", "mcrt_mean_intensity"):
             getattr(L, name).restype = C.c_int32
@@ -121,6 +125,24 @@ def _ptr(t):
 
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def image_psf(images: torch.Tensor, npix: int, scale: float, fwhm_pix: float) -> torch.Tensor:
+    """Images (device int64 tensor of uint64 sums, [..., npix, npix]) times
+    scale, convolved with a Gaussian PSF of FWHM fwhm_pix pixels
+    (mcrt_image_psf); returns float64 [n_images, npix, npix]."""
+    img = images.contiguous()
+    n_img = img.numel() // (npix * npix)
+    r = lib().mcrt_psf_radius(float(fwhm_pix))
+    if r < 0 or n_img * npix * npix != img.numel():
+        raise MCRTError(-1, "image_psf: fwhm out of range or shape mismatch")
+    w = torch.empty(2 * r + 1, dtype=torch.float64, device=img.device)
+    out = torch.empty((n_img, npix, npix), dtype=torch.float64, device=img.device)
+    rc = lib().mcrt_image_psf(_ptr(img), n_img, int(npix), float(scale), float(fwhm_pix), _ptr(w), _ptr(out),
+                              _stream())
+    if rc != 0:
+        raise MCRTError(rc, "mcrt_image_psf")
+    return out
 
 
 def u64_view(t: torch.Tensor) -> np.ndarray:
