@@ -325,6 +325,15 @@ def pah_model(n_c: int, lam_um) -> PahModel:
     y = lam_c / lam
     cut = np.arctan(1.0e3 * (y - 1.0) ** 3 / y) / np.pi + 0.5
     sig_uv = 1.0e-17 * (2.0 * drude + fuv + base) * cut
+    # beyond 17 eV (hard UV to X-rays) the per-atom photo-absorption falls as
+    # E^-2 from its 17 eV value, a smooth stand-in for the graphite-like
+    # scaling the paper uses up to 1 keV (grids that start at 0.1 um never
+    # reach it)
+    x17 = 17.0 / 1.2398419843320026           # 1/um at 17 eV
+    if np.any(x > x17):
+        drude17 = x17 ** 2 / ((x17 * x17 - 4.6 ** 2) ** 2 + x17 ** 2)
+        s17 = 2.0 * drude17 + 0.1 * (x17 - 5.9) ** 2 + 0.3 + 0.1 * x17
+        sig_uv = np.where(x > x17, 1.0e-17 * s17 * (x17 / x) ** 2, sig_uv)
     sig_ir = 2.0e-22 * (lam / 10.0) ** -1.0
     cband = np.empty((PAH_BANDS.shape[0], lam.size))
     for b, (l0, fw, S) in enumerate(PAH_BANDS):
@@ -334,6 +343,32 @@ def pah_model(n_c: int, lam_um) -> PahModel:
     cabs = ccont + cband.sum(axis=0)
     return PahModel(n_c=n_c, theta=800.0, lam_um=lam, cabs=cabs, cband=cband,
                     ccont=ccont, mass=n_c * 12.0 * AMU)
+
+
+def hard_photon_case(energies_ev=(3.8, 13.6, 50.0, 100.0, 300.0, 1000.0), flux=1.0e4, nl=241,
+                     M=1000, n_c=100):
+    """The paper's Fig. 3 set-up: a PAH with n_c C atoms in monochromatic
+    radiation of flux `flux` (erg s^-1 cm^-2) at each photon energy.
+    Wavelength grid 0.001-1000 um (down to 1.24 keV), M enthalpy bins on
+    T = 2.7 K .. 5e4 K (the top bin holds more than 1 keV).  Each field lights
+    the one bin nearest the energy: 4 pi J_j dnu_j = flux.  Returns a dict
+    with lam, the PAH model, T, U, the lit bins and the fields [n_e, nl]."""
+    lam = lambda_grid(nl, 0.001, 1000.0)
+    pm = pah_model(n_c, lam)
+    T = 2.7 * (5.0e4 / 2.7) ** (np.arange(M) / (M - 1))
+    U = pm.enthalpy(T)
+    ed = np.empty(nl + 1)
+    ed[1:-1] = np.sqrt(lam[:-1] * lam[1:])
+    ed[0] = lam[0] ** 2 / ed[1]
+    ed[-1] = lam[-1] ** 2 / ed[-2]
+    nu = _C / (lam * 1e-4)
+    dnu = _C / (ed[:-1] * 1e-4) - _C / (ed[1:] * 1e-4)
+    hnu_ev = _H * nu / 1.602176634e-12
+    bins = [int(np.argmin(np.abs(np.log(hnu_ev / e)))) for e in energies_ev]
+    J = np.zeros((len(bins), nl))
+    for k, j in enumerate(bins):
+        J[k, j] = flux / (4.0 * np.pi * dnu[j])
+    return dict(lam=lam, pm=pm, T=T, U=U, bins=bins, hnu_ev=hnu_ev[bins], J=J, flux=flux)
 
 
 def blackbody_field(lam_um, G0, T_h):

@@ -97,3 +97,20 @@ def test_reemission_rows_match_oracle(nl):
     ref = oracle.pah_rows(lam, pm.cband, out.cpu().numpy())
     assert np.all(rows[:, -1] == 1.0)
     assert np.max(np.abs(rows - ref)) < 1e-12
+
+
+def test_hard_photon_fields_match_oracle():
+    # the paper's Fig. 3 set-up (100 C atoms, 1000 enthalpy bins up to 5e4 K,
+    # 241 bins down to 1.24 keV, one lit bin per field): P(T) and emission
+    case = synth.hard_photon_case()
+    pm, T, U = case["pm"], case["T"], case["U"]
+    o_out, o_P, o_pabs = oracle.pah_solve(T, U, case["lam"], pm.cabs, pm.cband, pm.ccont, case["J"],
+                                          want_P=True, n_threads=8)
+    s = pah.PahSolver(T, U, case["lam"], pm.cabs, pm.cband, pm.ccont)
+    g_out, g_P, g_pabs = (a.cpu().numpy() for a in s.solve(torch.as_tensor(case["J"]).cuda(), want_P=True))
+    assert np.allclose(g_pabs, o_pabs, rtol=1e-13, atol=0)
+    for c in range(case["J"].shape[0]):
+        m = o_P[c] > 1e-12 * o_P[c].max()
+        assert np.max(np.abs(g_P[c][m] / o_P[c][m] - 1)) < 1e-10, c
+        mo = o_out[c] > 1e-12 * o_out[c].max()
+        assert np.max(np.abs(g_out[c][mo] / o_out[c][mo] - 1)) < 1e-10, c

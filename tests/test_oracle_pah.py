@@ -193,3 +193,28 @@ def test_reemission_rows():
     others = sum(out[:, k] * (pm.cband[k] * dnu / (pm.cband[k] * dnu).sum())[near].sum()
                  for k in range(17) if k != b)
     assert np.allclose(excess, out[:, b] * w[near].sum() + others, rtol=1e-9)
+
+
+def test_hard_photons_broaden_the_temperature_distribution():
+    # the paper's Fig. 3: a 100 C atom PAH in monochromatic radiation of fixed
+    # flux 1e4 erg s^-1 cm^-2 at 3.8 eV .. 1 keV.  Absorbed power is C F
+    # (one lit bin); the molecule emits it; at fixed flux harder photons come
+    # more rarely and each lifts the molecule further, so P(T) moves to low
+    # temperatures (median falls) while its hot tail stays (the spread from
+    # the median to the 99.99 % point widens)
+    case = synth.hard_photon_case()
+    pm, T, U = case["pm"], case["T"], case["U"]
+    out, P, pabs = oracle.pah_solve(T, U, case["lam"], pm.cabs, pm.cband, pm.ccont, case["J"],
+                                    want_P=True, n_threads=4)
+    C = pm.cabs[case["bins"]]
+    assert np.allclose(pabs, C * case["flux"], rtol=1e-12)
+    assert np.allclose(out.sum(1), pabs, rtol=1e-12)
+    med, spread = [], []
+    for p in P:
+        c = np.cumsum(p)
+        q = lambda v: T[np.searchsorted(c, v)]
+        med.append(q(0.5))
+        spread.append(q(0.9999) / q(0.5))
+    assert all(a > b for a, b in zip(med[1:], med[2:]))           # 13.6 eV onwards
+    assert all(a < b for a, b in zip(spread[:-1], spread[1:]))
+    assert spread[-1] > 5 * spread[0]
