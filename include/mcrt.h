@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MCRT_VERSION 103
+#define MCRT_VERSION 104
 
 #define MCRT_OK 0
 #define MCRT_E_INVALID (-1)     /* null pointer, bad size or range */
@@ -205,6 +205,9 @@ typedef struct {
   int32_t pad;
   void *peel_queue;            /* device, peel_capacity * MCRT_PEEL_REC_BYTES, for MCRT_FLAG_PEEL */
   uint64_t peel_capacity;      /* records */
+  void *jrec_ws;               /* device workspace of mcrt_jrec_ws_bytes(jrec_capacity) bytes for the
+                                  deferred path tally, or NULL for direct atomic adds */
+  uint64_t jrec_capacity;      /* path-segment records the workspace holds */
 } mcrt_run_opts;
 
 /* Byte offsets of the tables inside the tables buffer (for inspection). */
@@ -271,6 +274,17 @@ int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
  * r_c the distance from the source to the leaf centre, at least half the leaf
  * side.  J_out: device float [n_cells * n_lambda]. */
 int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
+
+/* Deferred path-length tally (TALLY_J with mcrt_run_opts.jrec_ws): instead of
+ * one 64-bit atomic add per path segment into the [n_lambda][n_cells] tally,
+ * the transport appends a record per segment to the workspace and mcrt_run
+ * then adds them with streaming partition passes and LDS sums, on the same
+ * stream; the tally is identical to the one of the atomic path (integer sums).
+ * Segments beyond jrec_capacity records are added directly (still exact).
+ * Workspace bytes for a capacity: *bytes; MCRT_E_INVALID for capacity outside
+ * [4096, 2^31], MCRT_E_UNSUPPORTED when the grid is deeper than 7 levels or
+ * the tally has more than 8192 * 40704 words.  No device work. */
+int32_t mcrt_jrec_ws_bytes(const mcrt_ctx *ctx, uint64_t capacity, uint64_t *bytes);
 
 /* Images through a telescope (paper Sec. 4, Fig. 2: the instrument's point
  * spread function, 50 mas at 10 um).  Each of the n_images [npix][npix]

@@ -219,6 +219,13 @@ int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcr
     return fail(ctx, MCRT_E_INVALID, "PAH species need pah_rows");
   if (ctx->img.n_obs > 0 && !tallies->image)
     return fail(ctx, MCRT_E_INVALID, "observers are set: tallies->image needed");
+  if (opts->jrec_ws) {
+    if (!(opts->flags & MCRT_FLAG_TALLY_J) || !tallies->jq)
+      return fail(ctx, MCRT_E_INVALID, "jrec_ws needs TALLY_J and tallies->jq");
+    uint64_t need = 0;
+    const int32_t rc = mcrt_jrec_ws_bytes(ctx, opts->jrec_capacity, &need);
+    if (rc != MCRT_OK) return fail(ctx, rc, "jrec_capacity out of range or grid unsupported for the deferred tally");
+  }
   if (n_packets == 0) return MCRT_OK;
   const hipError_t e = launch_transport(ctx, first_id, n_packets, *opts, *tallies, stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "transport launch");

@@ -62,6 +62,21 @@ struct RunScratch {
 
 Layout make_layout(const mcrt_desc& d);
 
+// Deferred path-length tally: the transport appends one 64-bit record per
+// path segment, (tally index << 24) | fixed-point length, in chunks of
+// kRecChunk claimed per wave; a partition by tally range and an LDS sum then
+// add them to the tally (mcrt_jdefer.hip).
+constexpr uint64_t kRecChunk = 4096;
+constexpr int kRecValBits = 24;
+constexpr uint64_t kBucketSlots = 40704;        // tally words per LDS bucket (u32 partial sums)
+constexpr uint64_t kTile1 = 1ull << 18;         // records per partition tile
+constexpr int kMaxBuckets = 8192;
+struct JrecLayout {
+  uint64_t n_buckets, n_tiles, capacity;
+  uint64_t hdr, counts, prefix, parts, recA, recB, total;   // byte offsets
+};
+JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity);
+
 }  // namespace mcrt
 
 namespace mcrt {
@@ -94,6 +109,7 @@ hipError_t launch_checks(mcrt_ctx* c, hipStream_t s);
 hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s);
 hipError_t launch_transport(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_opts& o,
                             const mcrt_tallies& t, hipStream_t s);
+hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t* jq, hipStream_t s);
 hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
                                hipStream_t s);
 hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s);

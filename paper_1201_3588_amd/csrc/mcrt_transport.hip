@@ -60,6 +60,10 @@ struct TP {
   const int8_t* level;
   const int4* leaf_lo;
   unsigned long long* peel;
+  // deferred path tally: record buffer, its capacity and fill counter
+  unsigned long long* jrec;
+  uint64_t jrec_cap;
+  unsigned long long* jrec_count;
 };
 
 // One queued next-event: where (base-cube units, inside leaf `cell`), in which
@@ -222,8 +226,10 @@ constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the share
 // lev) and the position u* relative to that corner in base-cube units, so that
 // rounding scales with the cell, not with the distance from the grid origin;
 // crossing into a neighbour re-bases u by an exact integer offset.
-template <typename R, bool TRACE, bool IMG>
-__global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
+// With the deferred path tally (DEFER) the record logic needs more registers:
+// six waves per SIMD without spills beat seven with them.
+template <typename R, bool TRACE, bool IMG, bool DEFER>
+__global__ void __launch_bounds__(256, DEFER ? 6 : 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
   __shared__ unsigned int s_cnt[12];
   double* s_alb = smem;
@@ -260,9 +266,54 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
   // frequent counters in registers, rare ones in LDS
   uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
   auto bump = [&](int k) { atomicAdd(&s_cnt[k], 1u); };
+  // deferred path tally: this lane's pending record, and the wave's current
+  // chunk of the record buffer [rcur, rcur + rleft) (wave-uniform); once the
+  // buffer is exhausted (rfull) the wave adds to the tally directly
+  unsigned long long prec = 0;
+  bool hrec = false, rfull = false;
+  uint64_t rcur = 0, rleft = 0;
   auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
   for (;;) {
+    if (DEFER) {
+      // every lane is here (loop head): store the pending records of the wave
+      // contiguously, claiming a new chunk when the current one runs out
+      const unsigned long long rm = __ballot(hrec);
+      if (rm) {
+        const uint64_t cnt = (uint64_t)__popcll(rm);
+        const uint64_t rank = (uint64_t)__popcll(rm & lt_mask);
+        uint64_t pos = ~0ull;
+        if (!rfull) {
+          if (rank < rleft) pos = rcur + rank;
+          if (cnt > rleft) {
+            unsigned long long base = 0;
+            const int leader = __ffsll((long long)rm) - 1;
+            if (lane == leader) base = atomicAdd(P.jrec_count, (unsigned long long)kRecChunk);
+            base = __shfl(base, leader);
+            if (base + kRecChunk <= P.jrec_cap) {
+              if (rank >= rleft) pos = base + (rank - rleft);
+              rcur = base + (cnt - rleft);
+              rleft = kRecChunk - (cnt - rleft);
+            } else {
+              // buffer exhausted: neutral records (slot 0, length 0) over the
+              // part of this chunk inside the buffer; direct adds from now on
+              for (uint64_t q = base + (uint64_t)lane; q < P.jrec_cap && q < base + kRecChunk; q += 64)
+                P.jrec[q] = 0ull;
+              rfull = true;
+              rleft = 0;
+            }
+          } else {
+            rcur += cnt;
+            rleft -= cnt;
+          }
+        }
+        if (hrec) {
+          if (pos != ~0ull) P.jrec[pos] = prec;
+          else atomicAdd(&P.jq[prec >> kRecValBits], prec & ((1ull << kRecValBits) - 1ull));
+          hrec = false;
+        }
+      }
+    }
     if (!exhausted || q_next < q_end) {
       const unsigned long long dead = __ballot(!alive);
       if (dead) {
@@ -363,7 +414,13 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
       const R s = tau / alpha;
       u0 += s * d0; u1 += s * d1; u2 += s * d2;
       if (tally_j && dusty) {
-        atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], (unsigned long long)rrint(s * P.qscale));
+        const unsigned long long q = (unsigned long long)rrint(s * P.qscale);
+        if (DEFER) {
+          prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+          hrec = true;
+        } else {
+          atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+        }
         c_jseg++;
       }
       events += 1;
@@ -454,7 +511,13 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
     // ---- cross the face into the neighbour
     if (alpha > R(0)) tau -= alpha * tex;
     if (tally_j && dusty) {
-      atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], (unsigned long long)rrint(tex * P.qscale));
+      const unsigned long long q = (unsigned long long)rrint(tex * P.qscale);
+      if (DEFER) {
+        prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+        hrec = true;
+      } else {
+        atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+      }
       c_jseg++;
     }
     c_cross++;
@@ -494,6 +557,10 @@ __global__ void __launch_bounds__(256, 7) k_transport(const TP<R> P) {
       if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
     }
   }
+
+  // the unused tail of the wave's last chunk holds neutral records
+  if (DEFER && !rfull)
+    for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) P.jrec[rcur + q] = 0ull;
 
   // ---- counters: registers reduced per wave, LDS per block
   {
@@ -685,8 +752,18 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   const uint64_t want = (n + 255) / 256;
   const size_t lds = (size_t)d.n_lambda * (2 * sizeof(double) + sizeof(R));
   // persistent grid: as many blocks as can be resident at once
-  auto kern = o.trace ? (img ? k_transport<R, true, true> : k_transport<R, true, false>)
-                      : (img ? k_transport<R, false, true> : k_transport<R, false, false>);
+  const bool defer = o.jrec_ws != nullptr && (o.flags & MCRT_FLAG_TALLY_J) && t.jq != nullptr;
+  if (defer) {
+    const JrecLayout J = jrec_layout((uint64_t)d.n_lambda * (uint64_t)d.n_cells, o.jrec_capacity);
+    unsigned char* ws = static_cast<unsigned char*>(o.jrec_ws);
+    P.jrec = reinterpret_cast<unsigned long long*>(ws + J.recA);
+    P.jrec_cap = J.capacity;
+    P.jrec_count = reinterpret_cast<unsigned long long*>(ws + J.hdr);
+    k_zero_u64<<<1, 64, 0, s>>>(P.jrec_count, 8);
+  }
+  auto kern = o.trace ? (img ? k_transport<R, true, true, false> : k_transport<R, true, false, false>)
+              : defer ? (img ? k_transport<R, false, true, true> : k_transport<R, false, false, true>)
+                      : (img ? k_transport<R, false, true, false> : k_transport<R, false, false, false>);
   int per_cu = 0;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
   if (per_cu < 1) per_cu = 1;
@@ -695,6 +772,10 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   if (blocks < 1) blocks = 1;
   kern<<<(unsigned)blocks, 256, lds, s>>>(P);
   if (peel) k_peel<R><<<(unsigned)(c->n_cu * 4), 256, 0, s>>>(P);
+  if (defer) {
+    const hipError_t e = launch_jrec_accumulate(c, o, t.jq, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ class RunOpts(C.Structure):
                 ("flags", C.c_int32), ("grid_blocks", C.c_int32),
                 ("frozen_nabs", _dp), ("pah_rows", _dp), ("trace", _dp), ("trace_len", _dp),
                 ("trace_cap", C.c_int32), ("pad", C.c_int32),
-                ("peel_queue", _dp), ("peel_capacity", C.c_uint64)]
+                ("peel_queue", _dp), ("peel_capacity", C.c_uint64),
+                ("jrec_ws", _dp), ("jrec_capacity", C.c_uint64)]
 
 
 class TableLayout(C.Structure):
@@ -102,6 +103,8 @@ def lib():
         L.mcrt_set_observers.restype = C.c_int32
         L.mcrt_read_counters_sync.argtypes = [C.POINTER(Tallies), P, P]
         L.mcrt_read_counters_sync.restype = C.c_int32
+        L.mcrt_jrec_ws_bytes.argtypes = [P, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.mcrt_jrec_ws_bytes.restype = C.c_int32
         L.mcrt_psf_radius.argtypes = [C.c_double]
         L.mcrt_psf_radius.restype = C.c_int32
         L.mcrt_image_psf.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, P, P, P]
@@ -272,6 +275,22 @@ class Engine:
             raise MCRTError(rc, "mcrt_read_counters_sync")
         return out
 
+    def set_deferred_tally(self, capacity):
+        """Path-length tally through a record workspace of `capacity` segment
+        records (mcrt_jrec_ws_bytes) instead of per-segment atomics; 0 turns
+        it off.  Returns False when the grid does not support it."""
+        if not capacity:
+            self._jrec = None
+            return True
+        nbytes = C.c_uint64(0)
+        rc = lib().mcrt_jrec_ws_bytes(self.ctx, int(capacity), C.byref(nbytes))
+        if rc == -6:
+            self._jrec = None
+            return False
+        self._check(rc, "mcrt_jrec_ws_bytes")
+        self._jrec = (torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device), int(capacity))
+        return True
+
     def run(self, tallies, first_id, n, n_total, seed, max_events=1_000_000, flags=None,
             frozen_nabs=None, pah_rows=None, trace_cap=0, grid_blocks=0):
         if flags is None:
@@ -284,6 +303,9 @@ class Engine:
         if getattr(self, "peel_on", False) and tallies.get("peel") is not None:
             o.flags |= FLAG_PEEL
             o.peel_queue, o.peel_capacity = _ptr(self._peel_q), self.peel_capacity
+        jrec = getattr(self, "_jrec", None)
+        if jrec is not None and (o.flags & FLAG_TALLY_J) and tallies.get("jq") is not None:
+            o.jrec_ws, o.jrec_capacity = _ptr(jrec[0]), jrec[1]
         keep = []
         if frozen_nabs is not None:
             if isinstance(frozen_nabs, torch.Tensor):

@@ -25,7 +25,7 @@ def test_every_declared_symbol_is_exported():
     assert "mcrt_run" in names and "mcrt_build_tables" in names
     for n in names:
         assert hasattr(L, n), n
-    assert L.mcrt_version() == 103
+    assert L.mcrt_version() == 104
 
 
 def good_desc():

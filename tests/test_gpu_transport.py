@@ -433,3 +433,28 @@ def test_exact_bw_correction_vanishes_with_many_absorptions():
     assert tv[100_000] > 4 * noise[100_000], (tv, noise)
     assert tv[10_000_000] < 0.05 * tv[100_000], (tv, noise)
     assert tv[10_000_000] < 3 * noise[10_000_000], (tv, noise)
+
+
+@pytest.mark.parametrize("precision,capacity", [("f64", 1 << 22), ("f32", 1 << 22), ("f32", 4096 * 3)])
+def test_deferred_tally_equals_atomic(precision, capacity):
+    # the path-length tally through segment records, partition and LDS sums
+    # is the tally of per-segment atomics, bit for bit (frozen temperatures
+    # make every packet's path independent of the others); a workspace far
+    # too small sends the overflow to direct adds, still exact
+    w = synth.small_disk(n_packets=20000, nl=32, n_sizes=2, nb=16)
+    w.precision = precision
+    base = oracle.Session(w, n_threads=8).transport(n=4000)["nabs"]
+    e = engine(w)
+    ref = e.new_tallies()
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    e.run(ref, 0, 20000, 20000, w.seed, frozen_nabs=base, flags=flags)
+    assert e.set_deferred_tally(capacity)
+    tal = e.new_tallies()
+    e.run(tal, 0, 12000, 20000, w.seed, frozen_nabs=base, flags=flags)
+    e.run(tal, 12000, 8000, 20000, w.seed, frozen_nabs=base, flags=flags)
+    a, b = host(ref), host(tal)
+    n_seg = int(a["counters"][mcrt.CNT["jseg"]])
+    assert n_seg > 8 * capacity if capacity < 1 << 20 else n_seg < capacity
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
+    e.set_deferred_tally(0)
