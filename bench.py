@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
                     help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
     ap.add_argument("--c3-packets", type=int, default=100_000_000)
+    ap.add_argument("--atomic-tally", action="store_true",
+                    help="path-length tally by per-segment atomics instead of the deferred records")
     ap.add_argument("--reemission", action=argparse.BooleanOptionalAction, default=True,
                     help="compare the paper's re-emission law with the Bjorkman-Wood one")
     ap.add_argument("--c5", action="store_true",
@@ -397,6 +399,9 @@ def main():
     w = synth.c2_disk(n_packets=args.packets)
     N = w.n_packets
     eng = mcrt.Engine.from_workload(w)
+    # path-length tally through segment records (about 64 per packet here)
+    # instead of one atomic per segment
+    deferred = (not args.atomic_tally) and eng.set_deferred_tally(min(1 << 31, max(1 << 20, 100 * N)))
     tal = eng.new_tallies(tally_j=True)
     stream = torch.cuda.current_stream()
     ev = []
@@ -516,9 +521,11 @@ def main():
     cnt = {k: int(c[v]) for k, v in mcrt.CNT.items()}
     assert cnt["launched"] == N and cnt["launched"] == cnt["escaped"] + cnt["killed"] + cnt["terminated"]
 
-    # algorithmic bytes of one transport launch: per crossing the density (4 B)
+    # algorithmic bytes of one transport pass: per crossing the density (4 B)
     # and base-map entry (4 B); per path-tally segment one 8 B read-modify-write
-    # (16 B); per absorption and per escape one 8 B atomic (16 B)
+    # (16 B); per absorption and per escape one 8 B atomic (16 B).  With the
+    # deferred tally the pass is the transport kernel plus the record passes
+    # (count, scan, scatter, sum), all inside the timed run.
     alg_bytes = 8 * cnt["crossings"] + 16 * cnt["jseg"] + 16 * cnt["absorptions"] + 16 * cnt["escaped"]
     achieved = alg_bytes / k_avg / 1e9
     # HBM bytes of one launch from the committed counter summary, if it was taken
@@ -526,8 +533,10 @@ def main():
     traffic = None
     try:
         import hashlib
-        src = os.path.join(ROOT, "paper_1201_3588_amd", "csrc", "mcrt_transport.hip")
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in ("mcrt_transport.hip", "mcrt_jdefer.hip"):
+            h.update(open(os.path.join(ROOT, "paper_1201_3588_amd", "csrc", f), "rb").read())
+        sha = h.hexdigest()
         kv = dict(l.split(": ", 1) for l in open(os.path.join(ROOT, "profiles", "transport_flared_disk_pmc.md"))
                   if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
         if kv.get("source_sha256", "").strip() == sha and N == 10_000_000:
@@ -559,16 +568,25 @@ def main():
         **info,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_transport<float>", "alg_bytes_per_launch": alg_bytes},
+                     "kernel": ("transport pass: k_transport<float,false,false,true> + k_jr_count, k_scan_*, "
+                                "k_jr_scatter, k_jr_items, k_jr_sum") if deferred else
+                               "k_transport<float,false,false,false>",
+                     "alg_bytes_per_launch": alg_bytes},
+        "path_tally": {"mode": "deferred records" if deferred else "atomic",
+                       "segments_per_s": cnt["jseg"] / k_avg},
     }
 
     if not args.no_micro:
         atom_rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
+        # the tally updates of the pass (path segments, absorptions, escapes)
+        # per second against the measured rate of random 64-bit atomics over a
+        # table of the path tally's size: above 1 once the path segments no
+        # longer go through atomics
         tr_atoms = (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg
         out["random_access_ceiling"] = {
             "atomics_per_s": atom_rate, "table_bytes": w.species.n_lambda * w.grid.n_cells * 8,
             "gbs_at_16B_per_op": atom_rate * 16 / 1e9,
-            "transport_atomics_per_s": tr_atoms, "frac_of_ceiling": tr_atoms / atom_rate}
+            "tally_updates_per_s": tr_atoms, "frac_of_ceiling": tr_atoms / atom_rate}
 
     if args.reemission:
         out["reemission_law"] = [
