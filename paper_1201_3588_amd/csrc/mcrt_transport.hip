@@ -221,6 +221,14 @@ __device__ __forceinline__ void peel_push(const TP<R>& P, double x0, double x1, 
 }
 
 constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the shared counter
+// Interactions and launches are long, divergent branches; run for the one or
+// two lanes that need them in a given step they would stall the other lanes
+// of the wave nearly every step.  A lane that reaches its interaction point
+// holds there until at least 1/kHoldFrac of the wave's live lanes hold, and
+// dead lanes are relaunched kRefillMin at a time (or when none is alive).
+// Histories do not change: random numbers are keyed by packet id and event.
+constexpr int kHoldFrac = 4;
+constexpr int kRefillMin = 16;
 
 // Packet state: current leaf (integer lower corner lo* in finest units, level
 // lev) and the position u* relative to that corner in base-cube units, so that
@@ -271,6 +279,7 @@ __global__ void __launch_bounds__(256, DEFER ? 6 : 7) k_transport(const TP<R> P)
   // buffer is exhausted (rfull) the wave adds to the tally directly
   unsigned long long prec = 0;
   bool hrec = false, rfull = false;
+  bool hold = false;          // at an interaction point, waiting for the wave's batch
   uint64_t rcur = 0, rleft = 0;
   auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
@@ -316,7 +325,7 @@ __global__ void __launch_bounds__(256, DEFER ? 6 : 7) k_transport(const TP<R> P)
     }
     if (!exhausted || q_next < q_end) {
       const unsigned long long dead = __ballot(!alive);
-      if (dead) {
+      if (dead && (__popcll(dead) >= kRefillMin || !__any(alive))) {
         const int nd = __popcll(dead);
         if (q_next >= q_end && !exhausted) {
           const int leader = __ffsll((long long)dead) - 1;
@@ -377,184 +386,194 @@ __global__ void __launch_bounds__(256, DEFER ? 6 : 7) k_transport(const TP<R> P)
       if (exhausted && q_next >= q_end) break;
       continue;
     }
-    if (!alive) continue;
+    if (alive && !hold) {
+      // ---- one segment: exit distance from the current leaf (lowest axis wins ties)
+      const int span = 1 << (L - lev);
+      const R side = (R)span * inv_nf;
+      R tex = (R)INFINITY;
+      int ax = -1;
+      {
+        // FP32: multiply by the direction's reciprocals (one rounding more than
+        // a division, well inside FP32 geometry tolerance); FP64: divide, as the
+        // definition does
+        R t;
+        if (d0 != R(0)) {
+          t = sizeof(R) == 4 ? (d0 > R(0) ? side - u0 : -u0) * r0 : (d0 > R(0) ? side - u0 : -u0) / d0;
+          t = t < R(0) ? R(0) : t;
+          if (t < tex) { tex = t; ax = 0; }
+        }
+        if (d1 != R(0)) {
+          t = sizeof(R) == 4 ? (d1 > R(0) ? side - u1 : -u1) * r1 : (d1 > R(0) ? side - u1 : -u1) / d1;
+          t = t < R(0) ? R(0) : t;
+          if (t < tex) { tex = t; ax = 1; }
+        }
+        if (d2 != R(0)) {
+          t = sizeof(R) == 4 ? (d2 > R(0) ? side - u2 : -u2) * r2 : (d2 > R(0) ? side - u2 : -u2) / d2;
+          t = t < R(0) ? R(0) : t;
+          if (t < tex) { tex = t; ax = 2; }
+        }
+      }
+      const bool dusty = dens > R(0);
+      const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)s_kext[j] * P.h)
+                                     : (R)(dens * s_kext[j]);
 
-    // ---- one segment: exit distance from the current leaf (lowest axis wins ties)
-    const int span = 1 << (L - lev);
-    const R side = (R)span * inv_nf;
-    R tex = (R)INFINITY;
-    int ax = -1;
-    {
-      // FP32: multiply by the direction's reciprocals (one rounding more than
-      // a division, well inside FP32 geometry tolerance); FP64: divide, as the
-      // definition does
-      R t;
-      if (d0 != R(0)) {
-        t = sizeof(R) == 4 ? (d0 > R(0) ? side - u0 : -u0) * r0 : (d0 > R(0) ? side - u0 : -u0) / d0;
-        t = t < R(0) ? R(0) : t;
-        if (t < tex) { tex = t; ax = 0; }
-      }
-      if (d1 != R(0)) {
-        t = sizeof(R) == 4 ? (d1 > R(0) ? side - u1 : -u1) * r1 : (d1 > R(0) ? side - u1 : -u1) / d1;
-        t = t < R(0) ? R(0) : t;
-        if (t < tex) { tex = t; ax = 1; }
-      }
-      if (d2 != R(0)) {
-        t = sizeof(R) == 4 ? (d2 > R(0) ? side - u2 : -u2) * r2 : (d2 > R(0) ? side - u2 : -u2) / d2;
-        t = t < R(0) ? R(0) : t;
-        if (t < tex) { tex = t; ax = 2; }
-      }
-    }
-    const bool dusty = dens > R(0);
-    const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)s_kext[j] * P.h)
-                                   : (R)(dens * s_kext[j]);
-
-    if (alpha > R(0) && tau < alpha * tex) {
-      // ---- interaction inside this cell
-      const R s = tau / alpha;
-      u0 += s * d0; u1 += s * d1; u2 += s * d2;
-      if (tally_j && dusty) {
-        const unsigned long long q = (unsigned long long)rrint(s * P.qscale);
-        if (DEFER) {
-          prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
-          hrec = true;
-        } else {
-          atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
-        }
-        c_jseg++;
-      }
-      events += 1;
-      if ((uint64_t)events > P.max_events) {
-        bump(2);
-        alive = false;
-        if (TRACE) record(P, kidx, 5, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
-        continue;
-      }
-      uint32_t w[4];
-      philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 0u, key0, key1, w);
-      R sp, cp;
-      sincos_rev(u24(w[2]), &sp, &cp);
-      if (u24(w[0]) <= s_alb[j]) {
-        // scattering: new direction from the phase function
-        if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 1, d0, d1, d2);
-        const R mu = (R)hg_mu(P.gpar[j], u24(w[1]));
-        const R st = rsqrt0(R(1) - mu * mu);
-        if (d2 > R(0.99999) || d2 < R(-0.99999)) {
-          d0 = st * cp; d1 = st * sp; d2 = d2 >= R(0) ? mu : -mu;
-        } else {
-          const R tmp = rsqrt0(R(1) - d2 * d2);
-          const R n0 = st * (d0 * d2 * cp - d1 * sp) / tmp + d0 * mu;
-          const R n1 = st * (d1 * d2 * cp + d0 * sp) / tmp + d1 * mu;
-          const R n2 = -st * cp * tmp + d2 * mu;
-          d0 = n0; d1 = n1; d2 = n2;
-        }
-        bump(4);
-        set_recip();
-        tau = -rlog((R)u24(w[3]));
-        if (TRACE) record(P, kidx, 2, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
-      } else {
-        // absorption: species, tally, new frequency, isotropic re-emission
-        uint32_t v[4];
-        philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 1u, key0, key1, v);
-        const int sp_i = cdf_search(P.sp_cdf + (int64_t)j * P.S, P.S, u24(w[1]));
-        unsigned long long before = atomicAdd(&P.nabs[(int64_t)cell * P.S + sp_i], 1ull);
-        bump(5);
-        if (P.flags & MCRT_FLAG_FROZEN_T) before = P.frozen[(int64_t)cell * P.S + sp_i];
-        if (P.flags & MCRT_FLAG_KILL_ON_ABSORB) {
-          bump(3);
-          alive = false;
-          if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
-          continue;
-        }
-        if (P.kind[sp_i] == 0) {
-          // Bracket of the absorbed energy; with the exact Bjorkman-Wood form
-          // a point uniform between the energies before and after this
-          // absorption, which picks the rows spanning T_before..T_after in
-          // proportion to the energy each covers.
-          const double vol = ldexp(P.h3, -3 * lev);
-          double nb = (double)before;
-          if (P.flags & MCRT_FLAG_EXACT_BW) nb += u24(v[2]);
-          const double pw = nb * P.eps / (P.rho[cell] * vol);
-          const double* E = P.E + (int64_t)sp_i * P.K;
-          int kb;
-          if (pw < E[0]) {
-            kb = 0;
-            bump(7);
+      if (alpha > R(0) && tau < alpha * tex) {
+        // ---- interaction inside this cell
+        const R s = tau / alpha;
+        u0 += s * d0; u1 += s * d1; u2 += s * d2;
+        if (tally_j && dusty) {
+          const unsigned long long q = (unsigned long long)rrint(s * P.qscale);
+          if (DEFER) {
+            prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+            hrec = true;
           } else {
-            int a = 0, b = P.K - 1;
-            if (E[P.K - 1] <= pw) a = P.K - 1;
-            else
-              while (b - a > 1) {
-                const int m = (a + b) >> 1;
-                if (E[m] <= pw) a = m; else b = m;
-              }
-            kb = a;
-            if (kb > P.K - 2) { kb = P.K - 2; bump(8); }
+            atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
           }
-          j = cdf_search(P.Rrows + ((int64_t)sp_i * (P.K - 1) + kb) * P.nl, P.nl, u24(v[0]));
-        } else {
-          const double* row = P.pah_rows + ((int64_t)P.pah_slot[sp_i] * P.n_cells + cell) * P.nl;
-          j = cdf_search(row, P.nl, u24(v[0]));
-          bump(9);
+          c_jseg++;
         }
-        const R mu = (R)(2.0 * u24(v[1]) - 1.0);
-        const R st = rsqrt0(R(1) - mu * mu);
-        d0 = st * cp; d1 = st * sp; d2 = mu;
-        set_recip();
-        tau = -rlog((R)u24(w[3]));
-        if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 0, d0, d1, d2);
-        if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+        hold = true;
+      } else {
+        // ---- cross the face into the neighbour
+        if (alpha > R(0)) tau -= alpha * tex;
+        if (tally_j && dusty) {
+          const unsigned long long q = (unsigned long long)rrint(tex * P.qscale);
+          if (DEFER) {
+            prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+            hrec = true;
+          } else {
+            atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+          }
+          c_jseg++;
+        }
+        c_cross++;
+        if (tex == R(0)) c_zero++;
+        u0 += tex * d0; u1 += tex * d1; u2 += tex * d2;
+        const R nf = (R)(1 << L);
+        int G0, G1, G2;
+        {
+          const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
+          G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
+          G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
+          G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
+        }
+        if (ax == 0) {
+          u0 = d0 > R(0) ? side : R(0);
+          G0 = d0 > R(0) ? lo0 + span : lo0 - 1;
+        } else if (ax == 1) {
+          u1 = d1 > R(0) ? side : R(0);
+          G1 = d1 > R(0) ? lo1 + span : lo1 - 1;
+        } else {
+          u2 = d2 > R(0) ? side : R(0);
+          G2 = d2 > R(0) ? lo2 + span : lo2 - 1;
+        }
+        const int o0 = lo0, o1 = lo1, o2 = lo2;
+        cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
+        if (cell < 0) {
+          bump(1);
+          alive = false;
+          escape_tally(P, d0, d1, d2, j);
+          if (IMG) image_tally(P, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
+          if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
+        } else {
+          // re-base the local position on the new leaf (exact integer offsets)
+          u0 += (R)(o0 - lo0) * inv_nf;
+          u1 += (R)(o1 - lo1) * inv_nf;
+          u2 += (R)(o2 - lo2) * inv_nf;
+          if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+        }
       }
-      continue;
     }
 
-    // ---- cross the face into the neighbour
-    if (alpha > R(0)) tau -= alpha * tex;
-    if (tally_j && dusty) {
-      const unsigned long long q = (unsigned long long)rrint(tex * P.qscale);
-      if (DEFER) {
-        prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
-        hrec = true;
-      } else {
-        atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
-      }
-      c_jseg++;
-    }
-    c_cross++;
-    if (tex == R(0)) c_zero++;
-    u0 += tex * d0; u1 += tex * d1; u2 += tex * d2;
-    const R nf = (R)(1 << L);
-    int G0, G1, G2;
+    // ---- the wave's held interactions, once enough lanes hold
     {
-      const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
-      G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
-      G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
-      G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
-    }
-    if (ax == 0) {
-      u0 = d0 > R(0) ? side : R(0);
-      G0 = d0 > R(0) ? lo0 + span : lo0 - 1;
-    } else if (ax == 1) {
-      u1 = d1 > R(0) ? side : R(0);
-      G1 = d1 > R(0) ? lo1 + span : lo1 - 1;
-    } else {
-      u2 = d2 > R(0) ? side : R(0);
-      G2 = d2 > R(0) ? lo2 + span : lo2 - 1;
-    }
-    const int o0 = lo0, o1 = lo1, o2 = lo2;
-    cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
-    if (cell < 0) {
-      bump(1);
-      alive = false;
-      escape_tally(P, d0, d1, d2, j);
-      if (IMG) image_tally(P, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
-      if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
-    } else {
-      // re-base the local position on the new leaf (exact integer offsets)
-      u0 += (R)(o0 - lo0) * inv_nf;
-      u1 += (R)(o1 - lo1) * inv_nf;
-      u2 += (R)(o2 - lo2) * inv_nf;
-      if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+      const unsigned long long hm = __ballot(hold);
+      if (hm && __popcll(hm) * kHoldFrac >= __popcll(__ballot(alive))) {
+        if (hold) {
+          hold = false;
+          events += 1;
+          if ((uint64_t)events > P.max_events) {
+            bump(2);
+            alive = false;
+            if (TRACE) record(P, kidx, 5, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+            continue;
+          }
+          uint32_t w[4];
+          philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 0u, key0, key1, w);
+          R sp, cp;
+          sincos_rev(u24(w[2]), &sp, &cp);
+          if (u24(w[0]) <= s_alb[j]) {
+            // scattering: new direction from the phase function
+            if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 1, d0, d1, d2);
+            const R mu = (R)hg_mu(P.gpar[j], u24(w[1]));
+            const R st = rsqrt0(R(1) - mu * mu);
+            if (d2 > R(0.99999) || d2 < R(-0.99999)) {
+              d0 = st * cp; d1 = st * sp; d2 = d2 >= R(0) ? mu : -mu;
+            } else {
+              const R tmp = rsqrt0(R(1) - d2 * d2);
+              const R n0 = st * (d0 * d2 * cp - d1 * sp) / tmp + d0 * mu;
+              const R n1 = st * (d1 * d2 * cp + d0 * sp) / tmp + d1 * mu;
+              const R n2 = -st * cp * tmp + d2 * mu;
+              d0 = n0; d1 = n1; d2 = n2;
+            }
+            bump(4);
+            set_recip();
+            tau = -rlog((R)u24(w[3]));
+            if (TRACE) record(P, kidx, 2, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+          } else {
+            // absorption: species, tally, new frequency, isotropic re-emission
+            uint32_t v[4];
+            philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 1u, key0, key1, v);
+            const int sp_i = cdf_search(P.sp_cdf + (int64_t)j * P.S, P.S, u24(w[1]));
+            unsigned long long before = atomicAdd(&P.nabs[(int64_t)cell * P.S + sp_i], 1ull);
+            bump(5);
+            if (P.flags & MCRT_FLAG_FROZEN_T) before = P.frozen[(int64_t)cell * P.S + sp_i];
+            if (P.flags & MCRT_FLAG_KILL_ON_ABSORB) {
+              bump(3);
+              alive = false;
+              if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+              continue;
+            }
+            if (P.kind[sp_i] == 0) {
+              // Bracket of the absorbed energy; with the exact Bjorkman-Wood form
+              // a point uniform between the energies before and after this
+              // absorption, which picks the rows spanning T_before..T_after in
+              // proportion to the energy each covers.
+              const double vol = ldexp(P.h3, -3 * lev);
+              double nb = (double)before;
+              if (P.flags & MCRT_FLAG_EXACT_BW) nb += u24(v[2]);
+              const double pw = nb * P.eps / (P.rho[cell] * vol);
+              const double* E = P.E + (int64_t)sp_i * P.K;
+              int kb;
+              if (pw < E[0]) {
+                kb = 0;
+                bump(7);
+              } else {
+                int a = 0, b = P.K - 1;
+                if (E[P.K - 1] <= pw) a = P.K - 1;
+                else
+                  while (b - a > 1) {
+                    const int m = (a + b) >> 1;
+                    if (E[m] <= pw) a = m; else b = m;
+                  }
+                kb = a;
+                if (kb > P.K - 2) { kb = P.K - 2; bump(8); }
+              }
+              j = cdf_search(P.Rrows + ((int64_t)sp_i * (P.K - 1) + kb) * P.nl, P.nl, u24(v[0]));
+            } else {
+              const double* row = P.pah_rows + ((int64_t)P.pah_slot[sp_i] * P.n_cells + cell) * P.nl;
+              j = cdf_search(row, P.nl, u24(v[0]));
+              bump(9);
+            }
+            const R mu = (R)(2.0 * u24(v[1]) - 1.0);
+            const R st = rsqrt0(R(1) - mu * mu);
+            d0 = st * cp; d1 = st * sp; d2 = mu;
+            set_recip();
+            tau = -rlog((R)u24(w[3]));
+            if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 0, d0, d1, d2);
+            if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+          }
+        }
+      }
     }
   }
 
