@@ -235,9 +235,9 @@ constexpr int kRefillMin = 16;
 // rounding scales with the cell, not with the distance from the grid origin;
 // crossing into a neighbour re-bases u by an exact integer offset.
 // With the deferred path tally (DEFER) the record logic needs more registers:
-// six waves per SIMD without spills beat seven with them.
+// five waves per SIMD without spills beat six or seven with them.
 template <typename R, bool TRACE, bool IMG, bool DEFER>
-__global__ void __launch_bounds__(256, DEFER ? 6 : 7) k_transport(const TP<R> P) {
+__global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
   __shared__ unsigned int s_cnt[12];
   double* s_alb = smem;
