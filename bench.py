@@ -69,6 +69,10 @@ def c3_block(n_packets, micro, stream):
     loop = PahLoop(w)
     eng = loop.eng
     N = w.n_packets
+    # deferred path tally: about 140 segment records per packet here, so the
+    # pass runs in id ranges of 12 M packets against a 2^31-record workspace
+    deferred = eng.set_deferred_tally(1 << 31)
+    batch = 12_000_000 if deferred else N
     J = eng.thin_field()
     torch.cuda.synchronize()
     p0 = torch.cuda.Event(enable_timing=True)
@@ -84,7 +88,7 @@ def c3_block(n_packets, micro, stream):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    eng.run(tal, 0, N, N, w.seed, pah_rows=loop.rows)
+    eng.run_batched(tal, 0, N, N, w.seed, batch, pah_rows=loop.rows)
     e1.record(stream)
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) / 1e3
@@ -94,19 +98,22 @@ def c3_block(n_packets, micro, stream):
     alg = 8 * cnt["crossings"] + 16 * (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"])
     res = {"workload": "gap_spiral_disk_128cube_depth3_2098552leaves_26species_200lambda_1e8packets_pah",
            "leaves": w.grid.n_cells, "packets": N, "transport_kernel_ms": dt * 1e3,
+           "path_tally": f"deferred records, id ranges of {batch} packets" if deferred else "atomic",
            "packets_per_s": N / dt, "crossings_per_s": cnt["crossings"] / dt, "per_pass_counts": cnt,
            "pah_rows_from_thin_field_ms": p0.elapsed_time(p1),
            "pah_cells_solved": 2 * w.grid.n_cells, "synth_build_s": t_synth,
            "roofline": {"bound": "hbm", "achieved": alg / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": alg / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_transport<float>", "alg_bytes_per_launch": alg}}
-    res["images"] = images_block(w, eng, loop.rows, stream, dt)
+                        "kernel": "transport pass (k_transport + record passes per id range)" if deferred
+                                  else "k_transport<float,false,false,false>",
+                        "alg_bytes_per_launch": alg}}
+    res["images"] = images_block(w, eng, loop.rows, stream, dt, batch)
     del tal, loop, eng
     if micro:
         rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
         tr = (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / dt
         res["random_access_ceiling"] = {"atomics_per_s": rate, "table_bytes": w.species.n_lambda * w.grid.n_cells * 8,
-                                        "transport_atomics_per_s": tr, "frac_of_ceiling": tr / rate}
+                                        "tally_updates_per_s": tr, "frac_of_ceiling": tr / rate}
     return res
 
 
@@ -167,7 +174,7 @@ def reemission_block(w, stream, label):
             "sed_total_variation": tv, "sed_total_variation_two_seeds": tv0}
 
 
-def images_block(w, eng, rows, stream, plain_s):
+def images_block(w, eng, rows, stream, plain_s, batch):
     """The paper's Fig. 2 on the gap + spiral disk: next-event images at the
     bins holding 10 and 11.3 um, face-on and inclined by 60 deg, 401 x 401
     pixels over the 200 AU box, one full pass with the images on (its extra
@@ -191,7 +198,7 @@ def images_block(w, eng, rows, stream, plain_s):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    eng.run(tal, 0, N, N, w.seed, pah_rows=rows)
+    eng.run_batched(tal, 0, N, N, w.seed, batch, pah_rows=rows)
     e1.record(stream)
     c = eng.counters_sync(tal)
     t_img = e0.elapsed_time(e1) / 1e3

@@ -278,12 +278,13 @@ int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
 /* Deferred path-length tally (TALLY_J with mcrt_run_opts.jrec_ws): instead of
  * one 64-bit atomic add per path segment into the [n_lambda][n_cells] tally,
  * the transport appends a record per segment to the workspace and mcrt_run
- * then adds them with streaming partition passes and LDS sums, on the same
- * stream; the tally is identical to the one of the atomic path (integer sums).
- * Segments beyond jrec_capacity records are added directly (still exact).
- * Workspace bytes for a capacity: *bytes; MCRT_E_INVALID for capacity outside
- * [4096, 2^31], MCRT_E_UNSUPPORTED when the grid is deeper than 7 levels or
- * the tally has more than 8192 * 40704 words.  No device work. */
+ * then adds them with streaming partition passes (two levels for tallies of
+ * more than 1536 * 40704 words) and LDS sums, on the same stream; the tally
+ * is identical to the one of the atomic path (integer sums).  Segments beyond
+ * jrec_capacity records are added directly (still exact).  Workspace bytes
+ * for a capacity: *bytes; MCRT_E_INVALID for capacity outside [4096, 2^31],
+ * MCRT_E_UNSUPPORTED when the grid is deeper than 7 levels or the tally has
+ * more than 2^20 * 40704 words.  No device work. */
 int32_t mcrt_jrec_ws_bytes(const mcrt_ctx *ctx, uint64_t capacity, uint64_t *bytes);
 
 /* Images through a telescope (paper Sec. 4, Fig. 2: the instrument's point

@@ -70,10 +70,13 @@ constexpr uint64_t kRecChunk = 4096;
 constexpr int kRecValBits = 24;
 constexpr uint64_t kBucketSlots = 40704;        // tally words per LDS bucket (u32 partial sums)
 constexpr uint64_t kTile1 = 1ull << 18;         // records per partition tile
-constexpr int kMaxBuckets = 8192;
+constexpr uint64_t kOneLevelMax = 1536;         // more buckets: two partition levels
+constexpr uint64_t kMaxBuckets = 1ull << 20;
 struct JrecLayout {
   uint64_t n_buckets, n_tiles, capacity;
-  uint64_t hdr, counts, prefix, parts, recA, recB, total;   // byte offsets
+  bool two_level;
+  uint64_t fpc, nc;                               // two levels: buckets per coarse range, coarse ranges
+  uint64_t hdr, counts, tb, counts2, prefix, parts, recA, recB, total;   // byte offsets
 };
 JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity);
 

@@ -4,15 +4,18 @@
 // table size, so the transport instead appends one record per path segment,
 // (tally index << 24) | fixed-point length, contiguously per wave.  Here the
 // records are added to the tally with streaming passes and LDS sums:
-//   count    histogram of records per (bucket of kBucketSlots tally words, tile)
+//   count    histogram of records per (bucket, tile)
 //   scan     exclusive scan of the counts, bucket-major: each bucket's records
 //            become one contiguous range, ordered by tile
-//   scatter  records to their bucket ranges
+//   scatter  records to their bucket ranges (sub-tiles sorted in LDS first)
 //   items    work items of at most kPart records per bucket
-//   sum      per item, u32 partial sums of its bucket in LDS (a carry past
-//            2^32 goes straight to the tally), then one add per tally word:
-//            plain for a bucket of one item, atomic for a bucket shared by
-//            several items.
+//   sum      per item, u32 partial sums of its bucket (kBucketSlots tally
+//            words) in LDS (a carry past 2^32 goes straight to the tally),
+//            then one add per tally word: plain for a bucket of one item,
+//            atomic for a bucket shared by several items.
+// A tally of many buckets is partitioned in two levels, so that every
+// scatter writes long runs: first into coarse ranges of fpc buckets, then
+// each coarse range, tile by tile, into its buckets.
 // Integer sums do not depend on order, so the tally equals the one the
 // atomic path gives, bit for bit.
 #include "mcrt_internal.h"
@@ -25,9 +28,46 @@ constexpr int kScanBlocks = 256;
 constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
 
-__device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint32_t nb) {
-  const uint64_t b = (r >> kRecValBits) / kBucketSlots;
+// bucket of a record among nb buckets of `span` tally words from slot0
+__device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint64_t slot0, uint64_t span, uint32_t nb) {
+  const uint64_t slot = r >> kRecValBits;
+  const uint64_t d = slot >= slot0 ? slot - slot0 : 0;
+  // 32-bit division when the offset fits (every tally below 2^32 words)
+  const uint64_t b = d < (1ull << 32) ? (uint64_t)((uint32_t)d / (uint32_t)span) : d / span;
   return b < nb ? (uint32_t)b : nb - 1;
+}
+
+// Where the buckets' records are after the last partition pass.  One level:
+// bucket b starts at offs[b nt].  Two levels: bucket b = c fpc + f starts at
+// entry (c, f, 0) of the level-2 counts, laid out [c][f][tile of c] with
+// tb[c] tiles before coarse range c.
+struct BucketMap {
+  const uint32_t* offs;
+  const uint32_t* tb;       // null for one level
+  uint64_t nt;
+  uint32_t fpc, nc, nb;     // nb: buckets
+};
+
+__device__ __forceinline__ uint64_t bucket_start(const BucketMap& M, uint32_t b, uint64_t n) {
+  if (b >= M.nb) return n;
+  if (!M.tb) return M.offs[(uint64_t)b * M.nt];
+  const uint32_t c = b / M.fpc, f = b - c * M.fpc;
+  const uint32_t t0 = M.tb[c], ntc = M.tb[c + 1] - t0;
+  const uint64_t idx = (uint64_t)t0 * M.fpc + (uint64_t)f * ntc;
+  return idx < (uint64_t)M.tb[M.nc] * M.fpc ? M.offs[idx] : n;
+}
+
+// level-2 tile g: its coarse range c (largest c with tb[c] <= g) and index k
+__device__ __forceinline__ bool tile2(const uint32_t* tb, uint32_t nc, uint32_t g, uint32_t& c, uint32_t& k) {
+  if (g >= tb[nc]) return false;
+  uint32_t lo = 0, hi = nc;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tb[mid] <= g) lo = mid; else hi = mid;
+  }
+  c = lo;
+  k = g - tb[lo];
+  return true;
 }
 
 __device__ __forceinline__ uint64_t n_records(const unsigned long long* hdr, uint64_t cap) {
@@ -35,15 +75,9 @@ __device__ __forceinline__ uint64_t n_records(const unsigned long long* hdr, uin
   return n < cap ? n : cap;
 }
 
-__global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __restrict__ rec,
-                                                 const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                 uint64_t nt, uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t h[];
-  const uint64_t n = n_records(hdr, cap);
-  const uint64_t t = blockIdx.x;
-  for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
-  __syncthreads();
-  const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
+// histogram of the records [a, e) over nb buckets of `span` words from slot0
+__device__ __forceinline__ void count_range(const unsigned long long* __restrict__ rec, uint64_t a, uint64_t e,
+                                            uint64_t slot0, uint64_t span, uint32_t nb, uint32_t* h) {
   for (uint64_t k = a + threadIdx.x; k < e; k += 8 * 256) {
     unsigned long long r[8];
 #pragma unroll
@@ -53,10 +87,72 @@ __global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __re
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (r[q] != ~0ull) atomicAdd(&h[bucket_of(r[q], nb)], 1u);
+      if (r[q] != ~0ull) atomicAdd(&h[bucket_of(r[q], slot0, span, nb)], 1u);
   }
+}
+
+// level 1: tile t of the record array; counts [bucket][tile]
+__global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __restrict__ rec,
+                                                 const unsigned long long* hdr, uint64_t cap, uint32_t nb,
+                                                 uint64_t span, uint64_t nt, uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t h[];
+  const uint64_t n = n_records(hdr, cap);
+  const uint64_t t = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
+  count_range(rec, a, e, 0, span, nb, h);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + t] = h[i];
+}
+
+// tiles of each coarse range for level 2: tb[c] = tiles before range c
+// (ranges from the level-1 offsets), tb[nc] = all tiles
+__global__ void __launch_bounds__(1024) k_jr_dir(const uint32_t* __restrict__ offs1, const unsigned long long* hdr,
+                                                uint64_t cap, uint32_t nc, uint64_t nt, uint32_t* __restrict__ tb) {
+  __shared__ uint32_t s[1024];
+  const uint64_t n = n_records(hdr, cap);
+  const uint32_t per = (nc + 1023) / 1024, c0 = threadIdx.x * per;
+  uint32_t loc = 0;
+  for (uint32_t c = c0; c < c0 + per && c < nc; ++c) {
+    const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
+    loc += (uint32_t)((hi - lo + kTile1 - 1) / kTile1);
+  }
+  s[threadIdx.x] = loc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - loc;
+  for (uint32_t c = c0; c < c0 + per && c < nc; ++c) {
+    tb[c] = run;
+    const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
+    run += (uint32_t)((hi - lo + kTile1 - 1) / kTile1);
+  }
+  if (threadIdx.x == 1023) tb[nc] = s[1023];
+}
+
+// level 2: tile g is tile k of coarse range c; counts at [c][f][k]
+__global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __restrict__ rec,
+                                                  const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
+                                                  uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
+                                                  const uint32_t* __restrict__ tb, uint32_t* __restrict__ counts2) {
+  extern __shared__ uint32_t h[];
+  uint32_t c, k;
+  if (!tile2(tb, nc, blockIdx.x, c, k)) return;
+  const uint64_t n = n_records(hdr, cap);
+  const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
+  for (uint32_t i = threadIdx.x; i < fpc; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
+  count_range(rec, a, e, (uint64_t)c * fpc * kBucketSlots, kBucketSlots, fpc, h);
+  __syncthreads();
+  const uint32_t t0 = tb[c], ntc = tb[c + 1] - t0;
+  for (uint32_t f = threadIdx.x; f < fpc; f += 256)
+    counts2[(uint64_t)t0 * fpc + (uint64_t)f * ntc + k] = h[f];
 }
 
 // exclusive scan of v[0, n) in place: block sums, their scan, then each block
@@ -138,14 +234,58 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part
   return total;
 }
 
-// Per tile, sub-tiles of `sub` records are sorted by bucket in LDS and then
-// written as contiguous runs to their buckets' ranges (consecutive threads,
-// consecutive addresses).
+// The records [a, e) of src, sub-tile by sub-tile sorted by bucket in LDS
+// and written as contiguous runs (consecutive threads, consecutive
+// addresses) from run[b], the next free position of bucket b in dst.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ recA,
+__device__ void scatter_range(const unsigned long long* __restrict__ src, uint64_t a, uint64_t e, uint64_t slot0,
+                              uint64_t span, uint32_t nb, uint32_t* run, uint32_t* pre, unsigned long long* srt,
+                              uint32_t* part, unsigned long long* __restrict__ dst, uint64_t n, uint32_t sub) {
+  constexpr int kMaxPer = 16;                                         // sub <= 16 NT
+  for (uint64_t s0 = a; s0 < e; s0 += sub) {
+    const uint32_t m = (uint32_t)(e - s0 < sub ? e - s0 : sub);
+    unsigned long long r[kMaxPer];
+    uint32_t bk[kMaxPer], rk[kMaxPer];
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
+      if (k < m) {
+        r[q] = src[s0 + k];
+        bk[q] = bucket_of(r[q], slot0, span, nb);
+        rk[q] = atomicAdd(&pre[bk[q]], 1u);
+      }
+    }
+    __syncthreads();
+    block_exclusive_scan<NT>(pre, nb, part);
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
+      if (k < m) srt[pre[bk[q]] + rk[q]] = r[q];
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += NT) {
+      const unsigned long long x = srt[k];
+      const uint32_t b = bucket_of(x, slot0, span, nb);
+      const uint64_t d = (uint64_t)run[b] + (k - pre[b]);
+      if (d < n) dst[d] = x;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += NT) {
+      const uint32_t next = i + 1 < nb ? pre[i + 1] : m;
+      run[i] += next - pre[i];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += NT) pre[i] = 0u;
+    __syncthreads();
+  }
+}
+
+// level 1: tile t of src into the bucket ranges of dst
+template <int NT>
+__global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src,
                                                     const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                    uint64_t nt, const uint32_t* __restrict__ offs,
-                                                    unsigned long long* __restrict__ recB, uint32_t sub) {
+                                                    uint64_t span, uint64_t nt, const uint32_t* __restrict__ offs,
+                                                    unsigned long long* __restrict__ dst, uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;                                   // [sub] records by bucket
   uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);          // [nb] next position per bucket
@@ -161,58 +301,49 @@ __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __r
     pre[i] = 0u;
   }
   __syncthreads();
-  constexpr int kMaxPer = 16;                                         // sub <= 16 NT
-  for (uint64_t s0 = a; s0 < e; s0 += sub) {
-    const uint32_t m = (uint32_t)(e - s0 < sub ? e - s0 : sub);
-    unsigned long long r[kMaxPer];
-    uint32_t bk[kMaxPer], rk[kMaxPer];
-#pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
-      if (k < m) {
-        r[q] = recA[s0 + k];
-        bk[q] = bucket_of(r[q], nb);
-        rk[q] = atomicAdd(&pre[bk[q]], 1u);
-      }
-    }
-    __syncthreads();
-    block_exclusive_scan<NT>(pre, nb, part);
-#pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
-      if (k < m) srt[pre[bk[q]] + rk[q]] = r[q];
-    }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < m; k += NT) {
-      const unsigned long long x = srt[k];
-      const uint32_t b = bucket_of(x, nb);
-      const uint64_t dst = (uint64_t)run[b] + (k - pre[b]);
-      if (dst < n) recB[dst] = x;
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t next = i + 1 < nb ? pre[i + 1] : m;
-      run[i] += next - pre[i];
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += NT) pre[i] = 0u;
-    __syncthreads();
-  }
+  scatter_range<NT>(src, a, e, 0, span, nb, run, pre, srt, part, dst, n, sub);
 }
 
-// bucket b's records: [offs[b nt], offs[(b+1) nt]) (the last ends at n);
+// level 2: tile k of coarse range c into its fpc buckets
+template <int NT>
+__global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __restrict__ src,
+                                                     const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
+                                                     uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
+                                                     const uint32_t* __restrict__ tb,
+                                                     const uint32_t* __restrict__ offs2,
+                                                     unsigned long long* __restrict__ dst, uint32_t sub) {
+  extern __shared__ unsigned long long smem64[];
+  unsigned long long* srt = smem64;
+  uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);
+  uint32_t* pre = run + fpc;
+  __shared__ uint32_t part[NT];
+  uint32_t c, k;
+  if (!tile2(tb, nc, blockIdx.x, c, k)) return;
+  const uint64_t n = n_records(hdr, cap);
+  const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
+  const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
+  const uint32_t t0 = tb[c], ntc = tb[c + 1] - t0;
+  for (uint32_t f = threadIdx.x; f < fpc; f += NT) {
+    run[f] = offs2[(uint64_t)t0 * fpc + (uint64_t)f * ntc + k];
+    pre[f] = 0u;
+  }
+  __syncthreads();
+  scatter_range<NT>(src, a, e, (uint64_t)c * fpc * kBucketSlots, kBucketSlots, fpc, run, pre, srt, part, dst, n,
+                    sub);
+}
+
 // parts[b] = exclusive prefix of ceil(len_b / kPart) over buckets
-__global__ void __launch_bounds__(1024) k_jr_items(const uint32_t* __restrict__ offs,
-                                                  unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                  uint64_t nt, uint32_t* __restrict__ parts) {
+__global__ void __launch_bounds__(1024) k_jr_items(const BucketMap M, unsigned long long* hdr, uint64_t cap,
+                                                  uint32_t* __restrict__ parts) {
   __shared__ uint32_t s[1024];
   const uint64_t n = n_records(hdr, cap);
+  const uint32_t nb = M.nb;
   const uint32_t per = (nb + 1023) / 1024;
   const uint32_t b0 = threadIdx.x * per;
   uint32_t loc = 0;
   for (uint32_t b = b0; b < b0 + per && b < nb; ++b) {
-    const uint64_t lo = offs[(uint64_t)b * nt];
-    const uint64_t hi = b + 1 < nb ? offs[(uint64_t)(b + 1) * nt] : n;
+    const uint64_t lo = bucket_start(M, b, n);
+    const uint64_t hi = bucket_start(M, b + 1, n);
     loc += (uint32_t)((hi - lo + kPart - 1) / kPart);
   }
   s[threadIdx.x] = loc;
@@ -226,8 +357,8 @@ __global__ void __launch_bounds__(1024) k_jr_items(const uint32_t* __restrict__ 
   uint32_t run = s[threadIdx.x] - loc;
   for (uint32_t b = b0; b < b0 + per && b < nb; ++b) {
     parts[b] = run;
-    const uint64_t lo = offs[(uint64_t)b * nt];
-    const uint64_t hi = b + 1 < nb ? offs[(uint64_t)(b + 1) * nt] : n;
+    const uint64_t lo = bucket_start(M, b, n);
+    const uint64_t hi = bucket_start(M, b + 1, n);
     run += (uint32_t)((hi - lo + kPart - 1) / kPart);
   }
   if (threadIdx.x == 1023) {
@@ -237,13 +368,13 @@ __global__ void __launch_bounds__(1024) k_jr_items(const uint32_t* __restrict__ 
 }
 
 __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __restrict__ recB,
-                                                unsigned long long* hdr, uint64_t cap, uint32_t nb, uint64_t nt,
-                                                const uint32_t* __restrict__ offs,
+                                                unsigned long long* hdr, uint64_t cap, const BucketMap M,
                                                 const uint32_t* __restrict__ parts, uint64_t n_slots,
                                                 unsigned long long* __restrict__ jq) {
   extern __shared__ uint32_t acc[];
   __shared__ uint32_t s_item;
   const uint64_t n = n_records(hdr, cap);
+  const uint32_t nb = M.nb;
   const uint32_t total = parts[nb];
   for (;;) {
     if (threadIdx.x == 0) s_item = (uint32_t)atomicAdd(&hdr[1], 1ull);
@@ -257,8 +388,8 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
       if (parts[mid] <= item) lo = mid; else hi = mid;
     }
     const uint32_t b = lo;
-    const uint64_t start = offs[(uint64_t)b * nt];
-    const uint64_t end = b + 1 < nb ? offs[(uint64_t)(b + 1) * nt] : n;
+    const uint64_t start = bucket_start(M, b, n);
+    const uint64_t end = bucket_start(M, b + 1, n);
     const uint64_t r0 = start + (uint64_t)(item - parts[b]) * kPart;
     const uint64_t r1 = r0 + kPart < end ? r0 + kPart : end;
     const bool shared_bucket = parts[b + 1] - parts[b] > 1;
@@ -285,7 +416,7 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
     }
     __threadfence();
     __syncthreads();
-    const uint64_t ns = n_slots - base < kBucketSlots ? n_slots - base : kBucketSlots;
+    const uint64_t ns = base >= n_slots ? 0 : (n_slots - base < kBucketSlots ? n_slots - base : kBucketSlots);
     for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
       const uint32_t v = acc[i];
       if (v) {
@@ -304,6 +435,16 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
   J.capacity = capacity;
   J.n_buckets = (n_slots + kBucketSlots - 1) / kBucketSlots;
   J.n_tiles = (capacity + kTile1 - 1) / kTile1;
+  J.two_level = J.n_buckets > kOneLevelMax;
+  J.fpc = J.nc = 0;
+  if (J.two_level) {
+    uint64_t f = 1;
+    while (f * f < J.n_buckets) ++f;
+    J.fpc = f;
+    J.nc = (J.n_buckets + f - 1) / f;
+  }
+  const uint64_t nb1 = J.two_level ? J.nc : J.n_buckets;
+  const uint64_t nb_all = J.two_level ? J.nc * J.fpc : J.n_buckets;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -311,14 +452,47 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
     return o;
   };
   J.hdr = take(64);
-  J.counts = take(4 * J.n_buckets * J.n_tiles);
+  J.counts = take(4 * nb1 * J.n_tiles);
+  J.tb = take(4 * (J.nc + 1));
+  J.counts2 = take(J.two_level ? 4 * (J.n_tiles + J.nc + 1) * J.fpc : 0);
   J.prefix = take(8 * (kScanBlocks + 1));
-  J.parts = take(4 * (J.n_buckets + 1));
+  J.parts = take(4 * (nb_all + 1));
   J.recA = take(8 * capacity);
   J.recB = take(8 * capacity);
   J.total = off;
   return J;
 }
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void scan_u32(uint32_t* v, uint64_t n, unsigned long long* bsum, hipStream_t s) {
+  k_scan_sums<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
+  k_scan_top<<<1, 64, 0, s>>>(bsum);
+  k_scan_apply<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
+}
+
+// one scatter launch: few buckets -> 512-thread blocks on 8192-record
+// sub-tiles, two per CU, so one block's loads overlap the other's sort;
+// otherwise one 1024-thread block per CU with the largest power-of-two
+// sub-tile (<= 16384 records) whose sort buffer fits beside the two bucket
+// arrays in 160 KB of LDS
+template <typename L512, typename L1024>
+void scatter_launch(uint64_t nb, L512 l512, L1024 l1024) {
+  if (8 * nb <= 12 * 1024) {
+    l512(8192u, (size_t)8192 * 8 + 8 * nb);
+  } else {
+    uint32_t sub = 16384;
+    while (sub > 1024 && (size_t)sub * 8 + 8 * nb + 4096 + 256 > 160 * 1024) sub >>= 1;
+    l1024(sub, (size_t)sub * 8 + 8 * nb);
+  }
+}
+
+}  // namespace
 
 hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t* jq, hipStream_t s) {
   const uint64_t n_slots = (uint64_t)c->d.n_lambda * (uint64_t)c->d.n_cells;
@@ -326,33 +500,53 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
   unsigned char* ws = static_cast<unsigned char*>(o.jrec_ws);
   auto* hdr = reinterpret_cast<unsigned long long*>(ws + J.hdr);
   auto* counts = reinterpret_cast<uint32_t*>(ws + J.counts);
+  auto* tb = reinterpret_cast<uint32_t*>(ws + J.tb);
+  auto* counts2 = reinterpret_cast<uint32_t*>(ws + J.counts2);
   auto* bsum = reinterpret_cast<unsigned long long*>(ws + J.prefix);
   auto* parts = reinterpret_cast<uint32_t*>(ws + J.parts);
   auto* recA = reinterpret_cast<unsigned long long*>(ws + J.recA);
   auto* recB = reinterpret_cast<unsigned long long*>(ws + J.recB);
   auto* tally = reinterpret_cast<unsigned long long*>(jq);
-  const uint32_t nb = (uint32_t)J.n_buckets;
-  const uint64_t nt = J.n_tiles, cap = J.capacity, nc = (uint64_t)nb * nt;
-  k_jr_count<<<(unsigned)nt, 256, 4 * (size_t)nb, s>>>(recA, hdr, cap, nb, nt, counts);
-  k_scan_sums<<<kScanBlocks, 256, 0, s>>>(counts, nc, bsum);
-  k_scan_top<<<1, 64, 0, s>>>(bsum);
-  k_scan_apply<<<kScanBlocks, 256, 0, s>>>(counts, nc, bsum);
-  // few buckets: 512-thread blocks on 8192-record sub-tiles, two per CU, so
-  // one block's loads overlap the other's sort; otherwise one 1024-thread
-  // block per CU with the largest power-of-two sub-tile (<= 16384 records)
-  // whose sort buffer fits beside the two bucket arrays in 160 KB of LDS
-  if (8 * (size_t)nb <= 12 * 1024) {
-    const uint32_t sub = 8192;
-    k_jr_scatter<512><<<(unsigned)nt, 512, (size_t)sub * 8 + 8 * (size_t)nb, s>>>(recA, hdr, cap, nb, nt,
-                                                                                 counts, recB, sub);
+  const uint64_t nt = J.n_tiles, cap = J.capacity;
+  const uint32_t nb1 = (uint32_t)(J.two_level ? J.nc : J.n_buckets);
+  const uint64_t span1 = J.two_level ? J.fpc * kBucketSlots : kBucketSlots;
+  // level 1 (the whole partition for one level): recA -> recB
+  k_jr_count<<<(unsigned)nt, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
+  scan_u32(counts, (uint64_t)nb1 * nt, bsum, s);
+  scatter_launch(
+      nb1,
+      [&](uint32_t sub, size_t lds) {
+        k_jr_scatter<512><<<(unsigned)nt, 512, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
+      },
+      [&](uint32_t sub, size_t lds) {
+        k_jr_scatter<1024><<<(unsigned)nt, 1024, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
+      });
+  BucketMap M{};
+  const unsigned long long* sorted = recB;
+  if (!J.two_level) {
+    M.offs = counts; M.tb = nullptr; M.nt = nt; M.nb = nb1;
   } else {
-    uint32_t sub = 16384;
-    while (sub > 1024 && (size_t)sub * 8 + 8 * (size_t)nb + 4096 + 256 > 160 * 1024) sub >>= 1;
-    k_jr_scatter<1024><<<(unsigned)nt, 1024, (size_t)sub * 8 + 8 * (size_t)nb, s>>>(recA, hdr, cap, nb, nt,
-                                                                                   counts, recB, sub);
+    // level 2: each coarse range of recB, tile by tile, into its buckets -> recA
+    const uint32_t fpc = (uint32_t)J.fpc, nc = (uint32_t)J.nc;
+    const uint64_t n2 = (nt + nc + 1) * fpc;
+    const unsigned grid2 = (unsigned)(nt + nc);
+    k_jr_dir<<<1, 1024, 0, s>>>(counts, hdr, cap, nc, nt, tb);
+    k_fill_u32<<<256, 256, 0, s>>>(counts2, n2);
+    k_jr_count2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2);
+    scan_u32(counts2, n2, bsum, s);
+    scatter_launch(
+        fpc,
+        [&](uint32_t sub, size_t lds) {
+          k_jr_scatter2<512><<<grid2, 512, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, recA, sub);
+        },
+        [&](uint32_t sub, size_t lds) {
+          k_jr_scatter2<1024><<<grid2, 1024, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, recA, sub);
+        });
+    M.offs = counts2; M.tb = tb; M.nt = nt; M.fpc = fpc; M.nc = nc; M.nb = nc * fpc;
+    sorted = recA;
   }
-  k_jr_items<<<1, 1024, 0, s>>>(counts, hdr, cap, nb, nt, parts);
-  k_jr_sum<<<(unsigned)c->n_cu, 1024, 4 * kBucketSlots, s>>>(recB, hdr, cap, nb, nt, counts, parts, n_slots, tally);
+  k_jr_items<<<1, 1024, 0, s>>>(M, hdr, cap, parts);
+  k_jr_sum<<<(unsigned)c->n_cu, 1024, 4 * kBucketSlots, s>>>(sorted, hdr, cap, M, parts, n_slots, tally);
   return hipGetLastError();
 }
 
@@ -364,7 +558,9 @@ extern "C" int32_t mcrt_jrec_ws_bytes(const mcrt_ctx* ctx, uint64_t capacity, ui
   if (capacity < mcrt::kRecChunk || capacity > (1ull << 31)) return MCRT_E_INVALID;
   if (ctx->d.max_level > 7 || n_slots >= (1ull << 40)) return MCRT_E_UNSUPPORTED;
   const mcrt::JrecLayout J = mcrt::jrec_layout(n_slots, capacity);
-  if (J.n_buckets > (uint64_t)mcrt::kMaxBuckets || J.n_buckets * J.n_tiles > (1ull << 26))
+  const uint64_t nb1 = J.two_level ? J.nc : J.n_buckets;
+  if (J.n_buckets > mcrt::kMaxBuckets || nb1 * J.n_tiles > (1ull << 26) ||
+      (J.two_level && (J.n_tiles + J.nc + 1) * J.fpc > (1ull << 26)))
     return MCRT_E_UNSUPPORTED;
   *bytes = J.total;
   return MCRT_OK;

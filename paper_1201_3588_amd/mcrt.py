@@ -334,6 +334,14 @@ class Engine:
             return [recs[k * trace_cap:k * trace_cap + lens[k]] for k in range(int(n))]
         return keep
 
+    def run_batched(self, tallies, first_id, n, n_total, seed, batch, **kw):
+        """run() over consecutive id ranges of at most `batch` packets (so that
+        the deferred tally's records of each range fit its workspace)."""
+        keep = []
+        for a in range(0, int(n), int(batch)):
+            keep += self.run(tallies, int(first_id) + a, min(int(batch), int(n) - a), n_total, seed, **kw) or []
+        return keep
+
     def temperatures(self, nabs, n_total):
         T = torch.empty(self.n_cells * self.n_species, dtype=torch.float64, device=self.device)
         self._check(lib().mcrt_temperatures(self.ctx, _ptr(nabs), int(n_total), _ptr(T), _stream()),

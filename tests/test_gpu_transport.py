@@ -435,13 +435,15 @@ def test_exact_bw_correction_vanishes_with_many_absorptions():
     assert tv[10_000_000] < 3 * noise[10_000_000], (tv, noise)
 
 
-@pytest.mark.parametrize("precision,capacity", [("f64", 1 << 22), ("f32", 1 << 22), ("f32", 4096 * 3)])
-def test_deferred_tally_equals_atomic(precision, capacity):
+@pytest.mark.parametrize("precision,capacity,nb,nl", [("f64", 1 << 22, 16, 32), ("f32", 1 << 22, 16, 32),
+                                                      ("f32", 4096 * 3, 16, 32), ("f32", 1 << 22, 72, 200)])
+def test_deferred_tally_equals_atomic(precision, capacity, nb, nl):
     # the path-length tally through segment records, partition and LDS sums
     # is the tally of per-segment atomics, bit for bit (frozen temperatures
     # make every packet's path independent of the others); a workspace far
-    # too small sends the overflow to direct adds, still exact
-    w = synth.small_disk(n_packets=20000, nl=32, n_sizes=2, nb=16)
+    # too small sends the overflow to direct adds, still exact.  The 72^3 grid
+    # with 200 bins has 1834 buckets of tally words: two partition levels.
+    w = synth.small_disk(n_packets=20000, nl=nl, n_sizes=2, nb=nb)
     w.precision = precision
     base = oracle.Session(w, n_threads=8).transport(n=4000)["nabs"]
     e = engine(w)
