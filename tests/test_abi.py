@@ -142,3 +142,35 @@ def test_observer_validation_codes():
     finally:
         L.mcrt_ctx_destroy(ctx)
     assert L.mcrt_read_counters_sync(None, None, None) == -1
+
+
+def test_deferred_tally_workspace_codes():
+    L = mcrt.lib()
+    nbytes = C.c_uint64()
+    ctx = C.c_void_p()
+    assert L.mcrt_ctx_create(C.byref(good_desc()), C.byref(ctx)) == 0
+    try:
+        assert L.mcrt_jrec_ws_bytes(ctx, 100, C.byref(nbytes)) == -1           # below one chunk
+        assert L.mcrt_jrec_ws_bytes(ctx, (1 << 31) + 1, C.byref(nbytes)) == -1
+        assert L.mcrt_jrec_ws_bytes(ctx, 1 << 20, None) == -1
+        assert L.mcrt_jrec_ws_bytes(ctx, 1 << 20, C.byref(nbytes)) == 0
+        small = nbytes.value
+        assert small >= 2 * 8 * (1 << 20) and small % 256 == 0                # two record buffers
+        assert L.mcrt_jrec_ws_bytes(ctx, 1 << 22, C.byref(nbytes)) == 0
+        assert nbytes.value - small >= 2 * 8 * ((1 << 22) - (1 << 20))
+        # the workspace needs the path tally: TALLY_J off is rejected
+        opts = mcrt.RunOpts()
+        opts.n_total, opts.jrec_ws, opts.jrec_capacity = 10, C.c_void_p(0x1000), 1 << 20
+        t = mcrt.Tallies(C.c_void_p(0x1000), C.c_void_p(0x1000), None, C.c_void_p(0x1000))
+        assert L.mcrt_run(ctx, 0, 10, C.byref(opts), C.byref(t), None) == -2       # tables not built yet
+    finally:
+        L.mcrt_ctx_destroy(ctx)
+    d = good_desc()
+    d.max_level = 8                                                              # records hold 24-bit lengths
+    d.n_nodes = 0
+    ctx = C.c_void_p()
+    assert L.mcrt_ctx_create(C.byref(d), C.byref(ctx)) == 0
+    try:
+        assert L.mcrt_jrec_ws_bytes(ctx, 1 << 20, C.byref(nbytes)) == -6
+    finally:
+        L.mcrt_ctx_destroy(ctx)
