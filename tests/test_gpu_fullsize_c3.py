@@ -2,7 +2,9 @@
 2,098,552 leaves, 26 species of which two PAHs, 200 wavelengths, 1e8 packets),
 in the launch configuration the benchmark times: PAH re-emission rows from the
 optically thin field (first pass of the PAH iteration, exact solver), then one
-transport pass.  The oracle checks sampled outputs one by one:
+transport pass with the path-length tally deferred to records (two partition
+levels, id ranges of 12 M packets).  The oracle checks sampled outputs one by
+one:
   * exact integer bookkeeping of the full pass;
   * the exact PAH solution and re-emission rows of sampled cells;
   * with the pass's own absorption field frozen, sampled packet ids anywhere in
@@ -10,7 +12,9 @@ transport pass.  The oracle checks sampled outputs one by one:
     2 % of them, rays meeting a face at grazing incidence, may carry FP32
     position errors up to 1e-3 instead of 1e-5);
   * temperatures of sampled cells and the mean intensity of every cell,
-    recomputed by the oracle from the GPU's tallies.
+    recomputed by the oracle from the GPU's tallies;
+  * with a frozen field, the deferred tally of 3 M packets equals the
+    per-segment atomic one bit for bit.
 """
 import numpy as np
 import pytest
@@ -32,8 +36,9 @@ def c3_pass():
     loop = PahLoop(w)
     J0 = loop.eng.thin_field()
     outs = loop.emission(J0)
+    assert loop.eng.set_deferred_tally(1 << 31)
     tal = loop.eng.new_tallies(tally_j=True)
-    loop.eng.run(tal, 0, w.n_packets, w.n_packets, w.seed, pah_rows=loop.rows)
+    loop.eng.run_batched(tal, 0, w.n_packets, w.n_packets, w.seed, 12_000_000, pah_rows=loop.rows)
     T = loop.eng.temperatures(tal["nabs"], w.n_packets)
     torch.cuda.synchronize()
     return dict(w=w, loop=loop, J0=J0, outs=outs, r=host(tal), T=T.cpu().numpy(),
@@ -103,3 +108,25 @@ def test_c3_sampled_temperatures_and_intensities(c3_pass):
     J = loop.eng.mean_intensity(torch.as_tensor(r["jq"].view(np.int64)).cuda(), w.n_packets).cpu().numpy()
     Jo = s.mean_intensity(r["jq"])
     assert np.allclose(J, Jo, rtol=2e-7, atol=1e-30 * Jo.max())
+
+
+def test_c3_deferred_tally_equals_atomic(c3_pass):
+    # the same 3 M packets with the pass's absorption field frozen, once with
+    # per-segment atomics and once through records (two partition levels):
+    # identical tallies
+    w, loop = c3_pass["w"], c3_pass["loop"]
+    eng = loop.eng
+    frozen = torch.as_tensor(c3_pass["r"]["nabs"].view(np.int64)).cuda()
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    out = {}
+    for mode in ("atomic", "deferred"):
+        eng.set_deferred_tally(1 << 31 if mode == "deferred" else 0)
+        tal = eng.new_tallies(tally_j=True)
+        eng.run(tal, 40_000_000, 3_000_000, w.n_packets, w.seed, frozen_nabs=frozen, pah_rows=loop.rows,
+                flags=flags)
+        out[mode] = host(tal)
+        del tal
+    a, b = out["atomic"], out["deferred"]
+    assert int(a["counters"][mcrt.CNT["jseg"]]) > 3e8
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
