@@ -6,9 +6,10 @@ workload (64^3 base cubes refined 2x2x2 to depth 3 inside 1 AU = 262,480
 leaves, 3 materials x 8 grain sizes, 200 wavelengths, Henyey-Greenstein
 scattering, 1e7 packets from a 5800 K, 1 L_sun star, FP32 geometry, FP64
 tables and temperatures, path-length J tally on):
-  table build -> transport of all packets -> temperatures -> mean intensity
-  -> PAH (30 C) emission of every dusty cell from its field: surrogate network
-     with exact fallback on flagged cells -> PAH re-emission rows.
+  table build -> transport of all packets (path-length tally through per-segment
+  records and LDS sums; --atomic-tally for per-segment atomics) -> temperatures
+  -> mean intensity -> PAH (30 C) emission of every dusty cell from its field:
+  surrogate network with exact fallback on flagged cells -> PAH re-emission rows.
 The exact PAH solver is timed on the same cells beside the step.  The
 surrogate is trained before the timed region on exactly solved cells (the
 disk's fields plus synthetic fields).  Inputs are resident in device memory

@@ -8,7 +8,9 @@ outputs one by one and properties that hold at any size:
   * temperatures of sampled cells and the mean intensity of every cell,
     recomputed by the oracle from the GPU's tallies;
   * the exact PAH solver on sampled cells' fields;
-  * 3 sigma agreement of SED and shell absorptions at 2e6 packets (frozen field).
+  * 3 sigma agreement of SED and shell absorptions at 2e6 packets (frozen field);
+  * with a frozen field, the full pass's path-length tally through records (the
+    benchmark's path) equals the per-segment atomic one bit for bit.
 """
 import numpy as np
 import pytest
@@ -28,6 +30,7 @@ def full_pass():
     w = synth.c2_disk()
     e = mcrt.Engine.from_workload(w)
     e.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    assert e.set_deferred_tally(min(1 << 31, 100 * w.n_packets))        # as bench.py
     tal = e.new_tallies(tally_j=True)
     e.run(tal, 0, w.n_packets, w.n_packets, w.seed)
     T = e.temperatures(tal["nabs"], w.n_packets)
@@ -101,3 +104,19 @@ def test_full_grid_statistics_frozen(full_pass):
     for k in ("sed", "shells"):
         frac, zmax, chi2, n = res[k]
         assert n >= 5 and frac <= 0.02 and zmax < 6.0, (k, res[k])
+
+
+def test_full_pass_deferred_tally_equals_atomic(full_pass):
+    w, e, r, T, J = full_pass
+    frozen = torch.as_tensor(r["nabs"].view(np.int64)).cuda()
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    out = {}
+    for mode in ("deferred", "atomic"):
+        if mode == "atomic":
+            e.set_deferred_tally(0)
+        tal = e.new_tallies(tally_j=True)
+        e.run(tal, 0, w.n_packets, w.n_packets, w.seed, frozen_nabs=frozen, flags=flags)
+        out[mode] = host(tal)
+        del tal
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(out["atomic"][k], out["deferred"][k]), k
