@@ -55,7 +55,7 @@ def random_atomic_rate(n_slots, stream):
     return issued / (e0.elapsed_time(e1) / 1e3)
 
 
-def c3_block(n_packets, micro, stream):
+def c3_block(n_packets, micro, stream, iterate=True):
     """The gap + spiral disk with PAHs (128^3 base, depth 3, 2,098,552 leaves,
     26 species, 200 bins): PAH re-emission rows from the optically thin field
     (first pass of the PAH iteration, exact solver), then one timed transport
@@ -109,6 +109,18 @@ def c3_block(n_packets, micro, stream):
                                   else "k_transport<float,false,false,false>",
                         "alg_bytes_per_launch": alg}}
     res["images"] = images_block(w, eng, loop.rows, stream, dt, batch)
+    if iterate:
+        # the PAH iteration to convergence (emitted band power of both PAH
+        # species changing by less than 1 % between passes), from the thin field
+        t_it = time.perf_counter()
+        it = loop.run(n_iter=6, tol=0.01, batch=batch)
+        torch.cuda.synchronize()
+        hist = it["history"]
+        res["pah_iteration"] = {"passes": len(hist), "wall_s": time.perf_counter() - t_it,
+                                "converged": hist[-1]["change"] is not None and hist[-1]["change"] < 0.01,
+                                "band_power_change_per_pass": [h["change"] for h in hist],
+                                "pah_absorptions_per_pass": [h["pah_abs"] for h in hist]}
+        del it
     del tal, loop, eng
     if micro:
         rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
@@ -374,6 +386,8 @@ def main():
     ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
                     help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
     ap.add_argument("--c3-packets", type=int, default=100_000_000)
+    ap.add_argument("--c3-iterate", action=argparse.BooleanOptionalAction, default=True,
+                    help="also iterate the gap + spiral disk's PAH emission to convergence")
     ap.add_argument("--atomic-tally", action="store_true",
                     help="path-length tally by per-segment atomics instead of the deferred records")
     ap.add_argument("--reemission", action=argparse.BooleanOptionalAction, default=True,
@@ -606,7 +620,7 @@ def main():
     if not args.no_pah:
         out["pah_hard_photons"] = hard_photon_block(stream)
     if args.c3:
-        out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream)
+        out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream, iterate=args.c3_iterate)
     if args.c5:
         out["c5"] = c5_block(args.c5_packets, stream)
 

@@ -48,7 +48,9 @@ class PahLoop:
             outs.append(out)
         return outs
 
-    def run(self, n_iter=4, n_packets=None, seed=None, tol=0.01, log=None):
+    def run(self, n_iter=4, n_packets=None, seed=None, tol=0.01, log=None, batch=None):
+        """batch: packets per transport call (id ranges that fit the deferred
+        tally's workspace, when one is set on the engine); None = one call."""
         w = self.w
         N = int(n_packets or w.n_packets)
         seed = w.seed if seed is None else seed
@@ -59,7 +61,7 @@ class PahLoop:
         for it in range(n_iter):
             outs = self.emission(J)
             tal = self.eng.new_tallies(tally_j=True)
-            self.eng.run(tal, 0, N, N, seed + 7919 * it, pah_rows=self.rows)
+            self.eng.run_batched(tal, 0, N, N, seed + 7919 * it, batch or N, pah_rows=self.rows)
             T = self.eng.temperatures(tal["nabs"], N)
             J = self.eng.mean_intensity(tal["jq"], N)
             bp = torch.stack([band_power(o, self.rho, self.vol) for o in outs])
