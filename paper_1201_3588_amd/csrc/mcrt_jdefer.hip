@@ -26,14 +26,38 @@ namespace {
 
 constexpr int kScanBlocks = 256;
 constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
+constexpr int kLoads = 16;                  // record loads per thread in flight (count, sum)
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
 
-// bucket of a record among nb buckets of `span` tally words from slot0
-__device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint64_t slot0, uint64_t span, uint32_t nb) {
+// Unsigned 32-bit division by an invariant divisor as a multiply-high, two
+// shifts and an add (Granlund & Montgomery, "Division by invariant integers
+// using multiplication", PLDI 1994, Sec. 4): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1 (< 2^32), t = mulhi(m, n) gives
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) exactly for every
+// 32-bit n.  The emulated division it replaces costs about twenty VALU
+// instructions per record.
+struct UDiv {
+  uint32_t d, m, s1, s2;
+};
+
+UDiv make_udiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return UDiv{d, (uint32_t)m, l < 1 ? l : 1u, l > 0 ? l - 1 : 0u};
+}
+
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv& D) {
+  const uint32_t t = __umulhi(D.m, n);
+  return (t + ((n - t) >> D.s1)) >> D.s2;
+}
+
+// bucket of a record among nb buckets of D.d tally words from slot0
+__device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint64_t slot0, const UDiv& D, uint32_t nb) {
   const uint64_t slot = r >> kRecValBits;
   const uint64_t d = slot >= slot0 ? slot - slot0 : 0;
   // 32-bit division when the offset fits (every tally below 2^32 words)
-  const uint64_t b = d < (1ull << 32) ? (uint64_t)((uint32_t)d / (uint32_t)span) : d / span;
+  const uint64_t b = d < (1ull << 32) ? (uint64_t)udiv((uint32_t)d, D) : d / D.d;
   return b < nb ? (uint32_t)b : nb - 1;
 }
 
@@ -75,26 +99,28 @@ __device__ __forceinline__ uint64_t n_records(const unsigned long long* hdr, uin
   return n < cap ? n : cap;
 }
 
-// histogram of the records [a, e) over nb buckets of `span` words from slot0
+// histogram of the records [a, e) over nb buckets of D.d words from slot0
 __device__ __forceinline__ void count_range(const unsigned long long* __restrict__ rec, uint64_t a, uint64_t e,
-                                            uint64_t slot0, uint64_t span, uint32_t nb, uint32_t* h) {
-  for (uint64_t k = a + threadIdx.x; k < e; k += 8 * 256) {
-    unsigned long long r[8];
+                                            uint64_t slot0, const UDiv& D, uint32_t nb, uint32_t* h) {
+  // kLoads records per thread in flight: the passes over the records are
+  // bound by the bytes a CU keeps in flight
+  for (uint64_t k = a + threadIdx.x; k < e; k += kLoads * 256) {
+    unsigned long long r[kLoads];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < kLoads; ++q) {
       const uint64_t kk = k + (uint64_t)q * 256;
       r[q] = kk < e ? rec[kk] : ~0ull;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (r[q] != ~0ull) atomicAdd(&h[bucket_of(r[q], slot0, span, nb)], 1u);
+    for (int q = 0; q < kLoads; ++q)
+      if (r[q] != ~0ull) atomicAdd(&h[bucket_of(r[q], slot0, D, nb)], 1u);
   }
 }
 
 // level 1: tile t of the record array; counts [bucket][tile]
 __global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __restrict__ rec,
                                                  const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                 uint64_t span, uint64_t nt, uint32_t* __restrict__ counts) {
+                                                 UDiv span, uint64_t nt, uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t h[];
   const uint64_t n = n_records(hdr, cap);
   const uint64_t t = blockIdx.x;
@@ -139,7 +165,8 @@ __global__ void __launch_bounds__(1024) k_jr_dir(const uint32_t* __restrict__ of
 __global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __restrict__ rec,
                                                   const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
                                                   uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
-                                                  const uint32_t* __restrict__ tb, uint32_t* __restrict__ counts2) {
+                                                  const uint32_t* __restrict__ tb, UDiv span,
+                                                  uint32_t* __restrict__ counts2) {
   extern __shared__ uint32_t h[];
   uint32_t c, k;
   if (!tile2(tb, nc, blockIdx.x, c, k)) return;
@@ -148,7 +175,7 @@ __global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __r
   for (uint32_t i = threadIdx.x; i < fpc; i += 256) h[i] = 0u;
   __syncthreads();
   const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
-  count_range(rec, a, e, (uint64_t)c * fpc * kBucketSlots, kBucketSlots, fpc, h);
+  count_range(rec, a, e, (uint64_t)c * fpc * kBucketSlots, span, fpc, h);
   __syncthreads();
   const uint32_t t0 = tb[c], ntc = tb[c + 1] - t0;
   for (uint32_t f = threadIdx.x; f < fpc; f += 256)
@@ -239,21 +266,25 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part
 // addresses) from run[b], the next free position of bucket b in dst.
 template <int NT>
 __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64_t a, uint64_t e, uint64_t slot0,
-                              uint64_t span, uint32_t nb, uint32_t* run, uint32_t* pre, unsigned long long* srt,
+                              const UDiv& span, uint32_t nb, uint32_t* run, uint32_t* pre, unsigned long long* srt,
                               uint32_t* part, unsigned long long* __restrict__ dst, uint64_t n, uint32_t sub) {
   constexpr int kMaxPer = 16;                                         // sub <= 16 NT
   for (uint64_t s0 = a; s0 < e; s0 += sub) {
     const uint32_t m = (uint32_t)(e - s0 < sub ? e - s0 : sub);
     unsigned long long r[kMaxPer];
     uint32_t bk[kMaxPer], rk[kMaxPer];
+    // all loads first (positions past m re-read record s0 and are dropped),
+    // so that a wave has its whole share in flight at once
 #pragma unroll
     for (int q = 0; q < kMaxPer; ++q) {
       const uint32_t k = (uint32_t)q * NT + threadIdx.x;
-      if (k < m) {
-        r[q] = src[s0 + k];
-        bk[q] = bucket_of(r[q], slot0, span, nb);
-        rk[q] = atomicAdd(&pre[bk[q]], 1u);
-      }
+      r[q] = src[s0 + (k < m ? k : 0u)];
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
+      bk[q] = bucket_of(r[q], slot0, span, nb);
+      if (k < m) rk[q] = atomicAdd(&pre[bk[q]], 1u);
     }
     __syncthreads();
     block_exclusive_scan<NT>(pre, nb, part);
@@ -263,11 +294,14 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
       if (k < m) srt[pre[bk[q]] + rk[q]] = r[q];
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < m; k += NT) {
-      const unsigned long long x = srt[k];
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const uint32_t k = (uint32_t)q * NT + threadIdx.x;
+      const uint32_t kk = k < m ? k : 0u;
+      const unsigned long long x = srt[kk];
       const uint32_t b = bucket_of(x, slot0, span, nb);
-      const uint64_t d = (uint64_t)run[b] + (k - pre[b]);
-      if (d < n) dst[d] = x;
+      const uint64_t d = (uint64_t)run[b] + (kk - pre[b]);
+      if (k < m && d < n) dst[d] = x;
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += NT) {
@@ -284,7 +318,7 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
 template <int NT>
 __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src,
                                                     const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                    uint64_t span, uint64_t nt, const uint32_t* __restrict__ offs,
+                                                    UDiv span, uint64_t nt, const uint32_t* __restrict__ offs,
                                                     unsigned long long* __restrict__ dst, uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;                                   // [sub] records by bucket
@@ -310,7 +344,7 @@ __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __
                                                      const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
                                                      uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
                                                      const uint32_t* __restrict__ tb,
-                                                     const uint32_t* __restrict__ offs2,
+                                                     const uint32_t* __restrict__ offs2, UDiv span,
                                                      unsigned long long* __restrict__ dst, uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;
@@ -328,8 +362,7 @@ __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __
     pre[f] = 0u;
   }
   __syncthreads();
-  scatter_range<NT>(src, a, e, (uint64_t)c * fpc * kBucketSlots, kBucketSlots, fpc, run, pre, srt, part, dst, n,
-                    sub);
+  scatter_range<NT>(src, a, e, (uint64_t)c * fpc * kBucketSlots, span, fpc, run, pre, srt, part, dst, n, sub);
 }
 
 // parts[b] = exclusive prefix of ceil(len_b / kPart) over buckets
@@ -396,15 +429,19 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
     const uint64_t base = (uint64_t)b * kBucketSlots;
     for (uint32_t i = threadIdx.x; i < kBucketSlots; i += 1024) acc[i] = 0u;
     __syncthreads();
-    for (uint64_t k = r0 + threadIdx.x; k < r1; k += 8 * 1024) {
-      unsigned long long r[8];
+    for (uint64_t k = r0 + threadIdx.x; k < r1; k += kLoads * 1024) {
+      unsigned long long r[kLoads];
+      // unconditional loads (past r1: record r0 again, dropped below): a
+      // load under a branch makes the compiler wait for the earlier ones
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < kLoads; ++q) {
         const uint64_t kk = k + (uint64_t)q * 1024;
-        r[q] = kk < r1 ? recB[kk] : 0ull;
+        r[q] = recB[kk < r1 ? kk : r0];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < kLoads; ++q) r[q] = k + (uint64_t)q * 1024 < r1 ? r[q] : 0ull;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
         const uint64_t slot = r[q] >> kRecValBits;
         const uint32_t val = (uint32_t)(r[q] & kValMask);
         const uint64_t i = slot - base;
@@ -414,14 +451,41 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
         }
       }
     }
-    __threadfence();
+    // this block's carry atomics complete before any of its threads reads the
+    // words back below (no other block touches a single-item bucket, and a
+    // shared bucket is written back by atomics only): a workgroup-scope fence
+    // and the barrier, with each wave first waiting for its own memory
+    // operations (vmcnt counts an atomic until the L2 acknowledges it).  An
+    // agent-scope fence would also write back and invalidate the whole L2 of
+    // the XCD, once per item.
+    __threadfence_block();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const uint64_t ns = base >= n_slots ? 0 : (n_slots - base < kBucketSlots ? n_slots - base : kBucketSlots);
-    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
-      const uint32_t v = acc[i];
-      if (v) {
-        if (shared_bucket) atomicAdd(&jq[base + i], (unsigned long long)v);
-        else jq[base + i] += v;
+    for (uint32_t i0 = threadIdx.x; i0 < ns; i0 += 8 * 1024) {
+      uint32_t v[8];
+      unsigned long long old[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t i = i0 + q * 1024;
+        v[q] = i < ns ? acc[i] : 0u;
+      }
+      if (shared_bucket) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (v[q]) atomicAdd(&jq[base + i0 + q * 1024], (unsigned long long)v[q]);
+      } else {
+        // the tally words' loads all in flight before the first store:
+        // unconditional (past ns: word i0 again), since loads under a branch
+        // make every store wait for all earlier memory operations
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t i = i0 + q * 1024;
+          old[q] = jq[base + (i < ns ? i : i0)];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (v[q]) jq[base + i0 + q * 1024] = old[q] + v[q];
       }
     }
     __syncthreads();
@@ -509,7 +573,7 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
   auto* tally = reinterpret_cast<unsigned long long*>(jq);
   const uint64_t nt = J.n_tiles, cap = J.capacity;
   const uint32_t nb1 = (uint32_t)(J.two_level ? J.nc : J.n_buckets);
-  const uint64_t span1 = J.two_level ? J.fpc * kBucketSlots : kBucketSlots;
+  const UDiv span1 = make_udiv((uint32_t)(J.two_level ? J.fpc * kBucketSlots : kBucketSlots));
   // level 1 (the whole partition for one level): recA -> recB
   k_jr_count<<<(unsigned)nt, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
   scan_u32(counts, (uint64_t)nb1 * nt, bsum, s);
@@ -532,15 +596,18 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
     const unsigned grid2 = (unsigned)(nt + nc);
     k_jr_dir<<<1, 1024, 0, s>>>(counts, hdr, cap, nc, nt, tb);
     k_fill_u32<<<256, 256, 0, s>>>(counts2, n2);
-    k_jr_count2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2);
+    const UDiv span2 = make_udiv((uint32_t)kBucketSlots);
+    k_jr_count2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, span2, counts2);
     scan_u32(counts2, n2, bsum, s);
     scatter_launch(
         fpc,
         [&](uint32_t sub, size_t lds) {
-          k_jr_scatter2<512><<<grid2, 512, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, recA, sub);
+          k_jr_scatter2<512><<<grid2, 512, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, span2, recA,
+                                                    sub);
         },
         [&](uint32_t sub, size_t lds) {
-          k_jr_scatter2<1024><<<grid2, 1024, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, recA, sub);
+          k_jr_scatter2<1024><<<grid2, 1024, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, span2, recA,
+                                                      sub);
         });
     M.offs = counts2; M.tb = tb; M.nt = nt; M.fpc = fpc; M.nc = nc; M.nb = nc * fpc;
     sorted = recA;
