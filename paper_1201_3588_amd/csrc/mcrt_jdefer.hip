@@ -236,27 +236,36 @@ __global__ void __launch_bounds__(256) k_scan_apply(uint32_t* __restrict__ v, ui
 }
 
 // Block-wide exclusive scan of v[0, n) in LDS with NT threads; returns the
-// total.  part: LDS scratch of NT words.
+// total.  Each thread sums its run of entries, the runs are scanned within
+// each wave by shuffles and across the NT / 64 waves through part (LDS
+// scratch of NT / 64 words): two barriers in all.
 template <int NT>
 __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part) {
   const uint32_t per = (n + NT - 1) / NT, a = threadIdx.x * per;
   uint32_t loc = 0;
   for (uint32_t i = a; i < a + per && i < n; ++i) loc += v[i];
-  part[threadIdx.x] = loc;
-  __syncthreads();
-  for (int off = 1; off < NT; off <<= 1) {
-    const uint32_t y = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += y;
-    __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint32_t inc = loc;                                  // inclusive within the wave
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
   }
-  uint32_t run = part[threadIdx.x] - loc;
+  if (lane == 63u) part[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NT / 64; ++w) {
+    const uint32_t t = part[w];
+    before += w < wave ? t : 0u;
+    total += t;
+  }
+  uint32_t run = before + inc - loc;
   for (uint32_t i = a; i < a + per && i < n; ++i) {
     const uint32_t x = v[i];
     v[i] = run;
     run += x;
   }
-  const uint32_t total = part[NT - 1];
   __syncthreads();
   return total;
 }
@@ -324,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __r
   unsigned long long* srt = smem64;                                   // [sub] records by bucket
   uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);          // [nb] next position per bucket
   uint32_t* pre = run + nb;                                           // [nb] counts, then prefix
-  __shared__ uint32_t part[NT];
+  __shared__ uint32_t part[NT / 64];
   const uint64_t n = n_records(hdr, cap);
   const uint64_t t = blockIdx.x;
   const uint64_t a = t * kTile1;
@@ -350,7 +359,7 @@ __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __
   unsigned long long* srt = smem64;
   uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);
   uint32_t* pre = run + fpc;
-  __shared__ uint32_t part[NT];
+  __shared__ uint32_t part[NT / 64];
   uint32_t c, k;
   if (!tile2(tb, nc, blockIdx.x, c, k)) return;
   const uint64_t n = n_records(hdr, cap);
