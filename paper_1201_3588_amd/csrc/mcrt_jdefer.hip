@@ -310,6 +310,8 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
       const unsigned long long x = srt[kk];
       const uint32_t b = bucket_of(x, slot0, span, nb);
       const uint64_t d = (uint64_t)run[b] + (kk - pre[b]);
+      // plain store: a bucket's runs are completed across sub-tiles in the L2
+      // (non-temporal stores made this pass 23 % slower)
       if (k < m && d < n) dst[d] = x;
     }
     __syncthreads();

@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
               // buffer exhausted: neutral records (slot 0, length 0) over the
               // part of this chunk inside the buffer; direct adds from now on
               for (uint64_t q = base + (uint64_t)lane; q < P.jrec_cap && q < base + kRecChunk; q += 64)
-                P.jrec[q] = 0ull;
+                __builtin_nontemporal_store(0ull, &P.jrec[q]);
               rfull = true;
               rleft = 0;
             }
@@ -317,7 +317,10 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
           }
         }
         if (hrec) {
-          if (pos != ~0ull) P.jrec[pos] = prec;
+          // records are written once and read back by the next kernels:
+          // non-temporal, so they stream past the L2 lines of the grid and
+          // tables that the march gathers from
+          if (pos != ~0ull) __builtin_nontemporal_store(prec, &P.jrec[pos]);
           else atomicAdd(&P.jq[prec >> kRecValBits], prec & ((1ull << kRecValBits) - 1ull));
           hrec = false;
         }
@@ -579,7 +582,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
 
   // the unused tail of the wave's last chunk holds neutral records
   if (DEFER && !rfull)
-    for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) P.jrec[rcur + q] = 0ull;
+    for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) __builtin_nontemporal_store(0ull, &P.jrec[rcur + q]);
 
   // ---- counters: registers reduced per wave, LDS per block
   {
