@@ -94,6 +94,22 @@ __device__ __forceinline__ bool tile2(const uint32_t* tb, uint32_t nc, uint32_t 
   return true;
 }
 
+// Blocks are dealt to the chip's 8 XCDs round-robin (block b to XCD b mod 8).
+// The tile of block b among `used` tiles, chosen so that each XCD takes one
+// contiguous range of tiles: the runs of a bucket in neighbouring tiles meet
+// in one cache line, which is then completed in one L2 instead of two (the
+// same holds for neighbouring words of the per-tile counts).  The grid needs
+// at least 8 ceil(used / 8) blocks; false for a block without a tile.
+constexpr uint64_t kXcds = 8;
+
+__device__ __forceinline__ bool xcd_tile(uint64_t b, uint64_t used, uint64_t& t) {
+  const uint64_t q = (used + kXcds - 1) / kXcds;
+  const uint64_t i = b / kXcds;
+  if (i >= q) return false;
+  t = (b % kXcds) * q + i;
+  return t < used;
+}
+
 __device__ __forceinline__ uint64_t n_records(const unsigned long long* hdr, uint64_t cap) {
   const uint64_t n = hdr[0];
   return n < cap ? n : cap;
@@ -123,13 +139,19 @@ __global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __re
                                                  UDiv span, uint64_t nt, uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t h[];
   const uint64_t n = n_records(hdr, cap);
-  const uint64_t t = blockIdx.x;
-  for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
-  __syncthreads();
-  const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
-  count_range(rec, a, e, 0, span, nb, h);
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + t] = h[i];
+  const uint64_t used = (n + kTile1 - 1) / kTile1;
+  uint64_t t;
+  if (xcd_tile(blockIdx.x, used, t)) {
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
+    __syncthreads();
+    const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
+    count_range(rec, a, e, 0, span, nb, h);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + t] = h[i];
+  }
+  // the tiles past the last record: block t writes their zero counts
+  if (blockIdx.x >= used && blockIdx.x < nt)
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + blockIdx.x] = 0u;
 }
 
 // tiles of each coarse range for level 2: tb[c] = tiles before range c
@@ -168,8 +190,9 @@ __global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __r
                                                   const uint32_t* __restrict__ tb, UDiv span,
                                                   uint32_t* __restrict__ counts2) {
   extern __shared__ uint32_t h[];
+  uint64_t g;
   uint32_t c, k;
-  if (!tile2(tb, nc, blockIdx.x, c, k)) return;
+  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2(tb, nc, (uint32_t)g, c, k)) return;
   const uint64_t n = n_records(hdr, cap);
   const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
   for (uint32_t i = threadIdx.x; i < fpc; i += 256) h[i] = 0u;
@@ -337,9 +360,9 @@ __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __r
   uint32_t* pre = run + nb;                                           // [nb] counts, then prefix
   __shared__ uint32_t part[NT / 64];
   const uint64_t n = n_records(hdr, cap);
-  const uint64_t t = blockIdx.x;
+  uint64_t t;
+  if (!xcd_tile(blockIdx.x, (n + kTile1 - 1) / kTile1, t)) return;
   const uint64_t a = t * kTile1;
-  if (a >= n) return;
   const uint64_t e = a + kTile1 < n ? a + kTile1 : n;
   for (uint32_t i = threadIdx.x; i < nb; i += NT) {
     run[i] = offs[(uint64_t)i * nt + t];
@@ -362,8 +385,9 @@ __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __
   uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);
   uint32_t* pre = run + fpc;
   __shared__ uint32_t part[NT / 64];
+  uint64_t g;
   uint32_t c, k;
-  if (!tile2(tb, nc, blockIdx.x, c, k)) return;
+  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2(tb, nc, (uint32_t)g, c, k)) return;
   const uint64_t n = n_records(hdr, cap);
   const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
   const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
@@ -582,10 +606,11 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
   const uint32_t nb1 = (uint32_t)(J.two_level ? J.nc : J.n_buckets);
   const UDiv span1 = make_udiv((uint32_t)(J.two_level ? J.fpc * kBucketSlots : kBucketSlots));
   // level 1 (the whole partition for one level): recA -> recB
-  k_jr_count<<<(unsigned)nt, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
+  const unsigned grid1 = (unsigned)((nt + kXcds - 1) / kXcds * kXcds);     // whole rounds over the XCDs
+  k_jr_count<<<grid1, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
   scan_u32(counts, (uint64_t)nb1 * nt, bsum, s);
   scatter_launch(nb1, [&](uint32_t sub, size_t lds) {
-    k_jr_scatter<1024><<<(unsigned)nt, 1024, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
+    k_jr_scatter<1024><<<grid1, 1024, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
   });
   BucketMap M{};
   const unsigned long long* sorted = recB;
@@ -595,7 +620,7 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
     // level 2: each coarse range of recB, tile by tile, into its buckets -> recA
     const uint32_t fpc = (uint32_t)J.fpc, nc = (uint32_t)J.nc;
     const uint64_t n2 = (nt + nc + 1) * fpc;
-    const unsigned grid2 = (unsigned)(nt + nc);
+    const unsigned grid2 = (unsigned)((nt + nc + kXcds - 1) / kXcds * kXcds);  // >= level-2 tiles
     k_jr_dir<<<1, 1024, 0, s>>>(counts, hdr, cap, nc, nt, tb);
     k_fill_u32<<<256, 256, 0, s>>>(counts2, n2);
     const UDiv span2 = make_udiv((uint32_t)kBucketSlots);
