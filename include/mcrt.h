@@ -227,7 +227,12 @@ void mcrt_ctx_destroy(mcrt_ctx *ctx);
 const char *mcrt_last_error(const mcrt_ctx *ctx);
 int32_t mcrt_table_layout_get(const mcrt_ctx *ctx, mcrt_table_layout *out);
 
-/* Builds, in FP64 on the device, every table of the method into `tables`
+/* Paper Sec. 2: an absorbed packet raises the energy of its cell by eps and
+ * with it the cell's temperature, and leaves again at a new frequency drawn
+ * from the emission of the cell at the temperature before the absorption
+ * (the difference spectrum, without the Bjorkman & Wood correction); the star
+ * emits the packets.  These tables carry that arithmetic for the transport.
+ * Builds, in FP64 on the device, every table of the method into `tables`
  * (caller-owned, >= mcrt_tables_bytes): bin frequencies and widths, the
  * source CDF over bins, extinction/albedo, the species choice CDF per bin,
  * E_s(T_k) = 4 pi sum_j kabs_s B_j(T_k) dnu_j on the log T grid and the
@@ -255,7 +260,10 @@ int32_t mcrt_run(mcrt_ctx *ctx, uint64_t first_id, uint64_t n_packets,
                  const mcrt_run_opts *opts, const mcrt_tallies *tallies,
                  hipStream_t stream);
 
-/* Equilibrium temperature of every (cell, equilibrium species): solves
+/* Paper Sec. 2: the energy eps of each packet absorbed in a cell raises the
+ * cell's energy, and accordingly its temperature: the temperature is the one
+ * at which the cell emits what it absorbed.
+ * Equilibrium temperature of every (cell, equilibrium species): solves
  * nabs * eps = rho V E_s(T) for T in [T_lo, T_hi] in FP64 (bracket from the
  * E table, safeguarded Newton on the exact bin sum).  nabs == 0 gives T_lo;
  * PAH species give 0.  T_out: device [n_cells * n_species] double. */
@@ -267,6 +275,12 @@ int32_t mcrt_temperatures(mcrt_ctx *ctx, const uint64_t *nabs, uint64_t n_total,
  * J_out: device [n_cells * n_lambda] float. */
 int32_t mcrt_mean_intensity(mcrt_ctx *ctx, const uint64_t *jq, uint64_t n_total,
                             float *J_out, hipStream_t stream);
+
+/* Dust mass of every leaf, rho_c V_c (g), V_c = base_size^3 2^(-3 level_c):
+ * the weight of a cell's per-gram emission in sums over the grid (the band
+ * powers of the PAH iteration, pah_band_power).  Requires mcrt_build_tables.
+ * mass_out: device double [n_cells]. */
+int32_t mcrt_cell_mass(mcrt_ctx *ctx, double *mass_out, hipStream_t stream);
 
 /* Optically thin field of the source at every leaf centre, the starting
  * field of the PAH iteration (no dust in the way):
@@ -304,7 +318,6 @@ int32_t mcrt_jrec_ws_bytes(const mcrt_ctx *ctx, uint64_t capacity, uint64_t *byt
 int32_t mcrt_psf_radius(double fwhm_pix);
 int32_t mcrt_image_psf(const uint64_t *image, int32_t n_images, int32_t npix, double scale,
                        double fwhm_pix, double *weights, double *out, hipStream_t stream);
-
 /* Copies the MCRT_N_COUNTERS counters of `tallies` to host memory and waits
  * for the stream (so for every launch queued on it before). */
 int32_t mcrt_read_counters_sync(const mcrt_tallies *tallies, uint64_t *host_out, hipStream_t stream);

@@ -86,6 +86,20 @@ int32_t pah_solve_exact(pah_ctx *ctx, const void *J, int32_t j_is_f32, int64_t n
  * one PAH species' slice of mcrt_run_opts.pah_rows. */
 int32_t pah_build_rows(pah_ctx *ctx, const double *out, int64_t n, double *rows, hipStream_t stream);
 
+/* Emitted band powers of the model, the quantity whose change between
+ * transport passes ends the PAH iteration (paper Sec. 2 with Sec. 1: PAH
+ * emission in the Monte Carlo loop; the field of one pass sets the emission
+ * the next pass re-emits from):
+ * bp_out[b] = sum_c weight[c] out[c][b] for the n_bands bands, FP64, summed
+ * in a fixed order (the same result on every call).  With weight the cell's
+ * dust mass (mcrt_cell_mass) and out per molecule, bp is the band power up to
+ * the constant number of molecules per gram.  out: device double
+ * [n][n_bands + n_lambda]; weight: device double [n]; bp_out: device double
+ * [n_bands].  Uses a 128 KiB region of the tables buffer for partial sums, so
+ * calls on one context must not overlap in time. */
+int32_t pah_band_power(pah_ctx *ctx, const double *out, int64_t n, const double *weight, double *bp_out,
+                       hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate of the exact step: a perceptron n_in -> n_h -> n_h -> n_out
  * with SiLU activations, z = W x + b per layer (W stored [out][in]).

@@ -314,6 +314,20 @@ def pah_solve(T, U, lam_um, cabs, cband, ccont, J, n_threads: int = 1, want_P: b
     return out, P, pabs
 
 
+def cell_mass(grid):
+    """Dust mass per leaf, rho_c V_c, with V_c = (base_size 2^-level_c)^3."""
+    side = grid.base_size * np.ldexp(1.0, -np.asarray(grid.leaf_level, np.int64))
+    return np.asarray(grid.rho, np.float64) * side ** 3
+
+
+def band_power(out, mass, n_bands):
+    """Emitted band powers summed over cells: sum_c mass_c out[c, b] for the
+    first n_bands outputs (the quantity whose change between passes ends the
+    PAH iteration)."""
+    out = np.asarray(out, np.float64)
+    return np.asarray(mass, np.float64) @ out[:, :n_bands]
+
+
 def pah_rows(lam_um, cband, out):
     """Re-emission CDF rows [n, nl] from solver outputs [n, n_bands + nl]."""
     lam = np.ascontiguousarray(lam_um, np.float64)

@@ -251,6 +251,15 @@ int32_t mcrt_thin_field(mcrt_ctx* ctx, float* J_out, hipStream_t stream) {
   return MCRT_OK;
 }
 
+int32_t mcrt_cell_mass(mcrt_ctx* ctx, double* mass_out, hipStream_t stream) {
+  if (!ctx) return MCRT_E_INVALID;
+  if (!ctx->tables_built) return fail(ctx, MCRT_E_STATE, "cell mass before mcrt_build_tables");
+  if (!mass_out) return fail(ctx, MCRT_E_INVALID, "null mass_out");
+  const hipError_t e = launch_cell_mass(ctx, mass_out, stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cell mass launch");
+  return MCRT_OK;
+}
+
 int32_t mcrt_mean_intensity(mcrt_ctx* ctx, const uint64_t* jq, uint64_t n_total, float* J_out,
                             hipStream_t stream) {
   if (!ctx) return MCRT_E_INVALID;

@@ -116,6 +116,7 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
 hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
                                hipStream_t s);
 hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s);
+hipError_t launch_cell_mass(mcrt_ctx* c, double* mass, hipStream_t s);
 hipError_t launch_mean_intensity(mcrt_ctx* c, const uint64_t* jq, uint64_t n_total, float* J,
                                  hipStream_t s);
 }  // namespace mcrt

@@ -143,7 +143,23 @@ __global__ void k_thin_field(int64_t n_cells, int nl, double h, int L, double bx
   J[i] = (float)(lum * w / (16.0 * kPi * kPi * r * r * dnu[j]));
 }
 
+// mass of dust per leaf: rho_c h^3 2^(-3 level_c)
+__global__ void k_cell_mass(int64_t n_cells, double h3, const double* __restrict__ rho,
+                            const int8_t* __restrict__ level, double* __restrict__ mass) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  mass[c] = rho[c] * ldexp(h3, -3 * (int)level[c]);
+}
+
 }  // namespace
+
+hipError_t launch_cell_mass(mcrt_ctx* c, double* mass, hipStream_t s) {
+  const mcrt_desc& d = c->d;
+  const double h3 = d.base_size * d.base_size * d.base_size;
+  k_cell_mass<<<(unsigned)((d.n_cells + 255) / 256), 256, 0, s>>>(
+      d.n_cells, h3, d.rho, reinterpret_cast<const int8_t*>(c->tables + c->lay.level), mass);
+  return hipGetLastError();
+}
 
 hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s) {
   const mcrt_desc& d = c->d;

@@ -3,6 +3,8 @@
 // difference-emissivity rows used to pick the re-emission frequency
 // (paper Sec. 2: the new frequency follows from the cell temperature before
 // the absorption).  Also leaf levels, FP32 copies and an input check.
+#include <float.h>
+
 #include "mcrt_internal.h"
 
 namespace mcrt {
@@ -188,11 +190,22 @@ __global__ void k_check_rho(int64_t n_cells, const double* __restrict__ rho,
   if (!(r >= 0.0) || isinf(r)) atomicOr(bad, 1ull);
 }
 
+// FP32 density term rho h of a leaf.  A leaf with dust keeps a positive term
+// even where rho h is below the smallest normal float (the far wings of a
+// disk's vertical profile, tens of scale heights up): rounding it to zero
+// would drop the leaf's path-length tally, which counts the path in every
+// leaf with dust whatever its density.  The smallest normal float there
+// changes no optical depth that FP32 can represent.
+__device__ __forceinline__ float rho_h_f32(double r, double h) {
+  const float v = (float)(r * h);
+  return (r > 0.0 && !(v >= FLT_MIN)) ? FLT_MIN : v;
+}
+
 __global__ void k_cells(int64_t n_cells, double h, const double* __restrict__ rho,
                         float* __restrict__ rho_h32) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
-  rho_h32[c] = (float)(rho[c] * h);
+  rho_h32[c] = rho_h_f32(rho[c], h);
 }
 
 // base-map entry packed with the FP32 density term of an unrefined base cube
@@ -201,7 +214,7 @@ __global__ void k_binfo(int64_t nbase, double h, const int32_t* __restrict__ bas
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbase) return;
   const int32_t e = base_map[b];
-  binfo[b] = make_int2(e, e >= 0 ? __float_as_int((float)(rho[e] * h)) : 0);
+  binfo[b] = make_int2(e, e >= 0 ? __float_as_int(rho_h_f32(rho[e], h)) : 0);
 }
 
 __global__ void k_check_species(int nl, int S, const double* __restrict__ lam_um,

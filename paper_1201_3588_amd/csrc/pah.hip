@@ -36,8 +36,10 @@ constexpr int kBk = 32;
 constexpr int kThreads = 256;
 constexpr int kNC = 4;             // cells per workgroup
 
+constexpr int kBpBlocks = 256;        // partial sums of the band-power reduction
+
 struct PahLayout {
-  uint64_t nu, dnu, ed, E, fac, invdu, mtab, adown, em, bandw, total;
+  uint64_t nu, dnu, ed, E, fac, invdu, mtab, adown, em, bandw, bp_part, total;
 };
 
 PahLayout pah_layout(const pah_desc& d) {
@@ -59,6 +61,7 @@ PahLayout pah_layout(const pah_desc& d) {
   L.adown = take(8 * M);
   L.em = take(8 * M * no);
   L.bandw = take(8 * (uint64_t)(d.n_bands > 0 ? d.n_bands : 1) * nl);
+  L.bp_part = take(8 * (uint64_t)kBpBlocks * 64);
   L.total = off;
   return L;
 }
@@ -504,6 +507,32 @@ __global__ void k_compact(const uint8_t* __restrict__ ood, int64_t n, int64_t* _
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
+// Band powers summed over cells, weighted: sum_c w_c out[c][b].  Lane b of a
+// wave accumulates band b over the cells of its wave (one row read per cell,
+// lanes on consecutive bands), the block's four waves are added in LDS, and
+// a second kernel adds the blocks' partial sums in block order: the result
+// does not depend on timing.
+__global__ void __launch_bounds__(256) k_band_power_part(int nbd, int no, int64_t n, const double* __restrict__ out,
+                                                        const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double s[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (lane < nbd)
+    for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < n; c += (int64_t)gridDim.x * 4)
+      acc += w[c] * out[c * no + lane];
+  s[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) part[blockIdx.x * 64 + lane] = s[0][lane] + s[1][lane] + s[2][lane] + s[3][lane];
+}
+
+__global__ void k_band_power_sum(int nbd, const double* __restrict__ part, double* __restrict__ bp) {
+  const int b = threadIdx.x;
+  if (b >= nbd) return;
+  double acc = 0.0;
+  for (int k = 0; k < kBpBlocks; ++k) acc += part[k * 64 + b];
+  bp[b] = acc;
+}
+
 size_t solve_lds(const pah_desc& d) {
   return sizeof(double) * (kNC * ((size_t)d.M + 3 * (size_t)d.n_lambda + 2 + kBk * kBk + kBk) +
                            2 * (size_t)d.M + d.n_lambda) +
@@ -657,6 +686,21 @@ int32_t pah_build_rows(pah_ctx* c, const double* out, int64_t n, double* rows, h
     k_pah_rows<false><<<(unsigned)blocks, 256, 0, s>>>(c->d.n_lambda, c->d.n_bands, n, out, wb, rows);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("rows launch: ") + hipGetErrorString(e));
+  return MCRT_OK;
+}
+
+int32_t pah_band_power(pah_ctx* c, const double* out, int64_t n, const double* weight, double* bp_out,
+                       hipStream_t s) {
+  if (!c) return MCRT_E_INVALID;
+  if (!c->built) return pfail(c, MCRT_E_STATE, "band power before pah_build_tables");
+  if (n < 0) return pfail(c, MCRT_E_INVALID, "n < 0");
+  if (!out || !weight || !bp_out) return pfail(c, MCRT_E_INVALID, "null argument");
+  if (c->d.n_bands == 0) return MCRT_OK;
+  double* part = reinterpret_cast<double*>(c->tables + c->lay.bp_part);
+  k_band_power_part<<<kBpBlocks, 256, 0, s>>>(c->d.n_bands, c->d.n_bands + c->d.n_lambda, n, out, weight, part);
+  k_band_power_sum<<<1, 64, 0, s>>>(c->d.n_bands, part, bp_out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(c, MCRT_E_HIP, std::string("band power launch: ") + hipGetErrorString(e));
   return MCRT_OK;
 }
 

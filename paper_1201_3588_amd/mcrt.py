@@ -99,6 +99,8 @@ def lib():
         L.mcrt_mean_intensity.argtypes = [P, P, C.c_uint64, P, P]
         L.mcrt_thin_field.argtypes = [P, P, P]
         L.mcrt_thin_field.restype = C.c_int32
+        L.mcrt_cell_mass.argtypes = [P, P, P]
+        L.mcrt_cell_mass.restype = C.c_int32
         L.mcrt_set_observers.argtypes = [P, C.POINTER(Observers)]
         L.mcrt_set_observers.restype = C.c_int32
         L.mcrt_read_counters_sync.argtypes = [C.POINTER(Tallies), P, P]
@@ -353,6 +355,12 @@ class Engine:
         self._check(lib().mcrt_mean_intensity(self.ctx, _ptr(jq), int(n_total), _ptr(J), _stream()),
                     "mcrt_mean_intensity")
         return J.view(self.n_cells, self.n_lambda)
+
+    def cell_mass(self):
+        """Dust mass per leaf, rho_c V_c (mcrt_cell_mass), float64 [n_cells]."""
+        m = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        self._check(lib().mcrt_cell_mass(self.ctx, _ptr(m), _stream()), "mcrt_cell_mass")
+        return m
 
     def thin_field(self):
         J = torch.empty(self.n_cells * self.n_lambda, dtype=torch.float32, device=self.device)

@@ -29,7 +29,8 @@ def lib():
         L.pah_build_tables.argtypes = [P, P, C.c_uint64, P]
         L.pah_solve_exact.argtypes = [P, P, C.c_int32, C.c_int64, P, P, P, P]
         L.pah_build_rows.argtypes = [P, P, C.c_int64, P, P]
-        for n in ("pah_build_rows", "pah_tables_bytes", "pah_ctx_create", "pah_build_tables",
+        L.pah_band_power.argtypes = [P, P, C.c_int64, P, P, P]
+        for n in ("pah_build_rows", "pah_band_power", "pah_tables_bytes", "pah_ctx_create", "pah_build_tables",
                   "pah_solve_exact"):
             getattr(L, n).restype = C.c_int32
         L._pah_ready = True
@@ -88,6 +89,15 @@ class PahSolver:
         r = rows if rows is not None else torch.empty((n, self.n_lambda), dtype=torch.float64, device=self.device)
         self._check(lib().pah_build_rows(self.ctx, _ptr(out.contiguous()), n, _ptr(r), _stream()), "pah_build_rows")
         return r
+
+    def band_power(self, out, weight):
+        """Band powers summed over cells, sum_c weight_c out[c, b] (pah_band_power),
+        float64 [n_bands] on the device."""
+        out, weight = out.contiguous(), weight.contiguous()
+        bp = torch.empty(self.n_bands, dtype=torch.float64, device=self.device)
+        self._check(lib().pah_band_power(self.ctx, _ptr(out), int(out.shape[0]), _ptr(weight), _ptr(bp),
+                                         _stream()), "pah_band_power")
+        return bp
 
     def solve(self, J: torch.Tensor, want_P=False, out=None):
         """J: [n, n_lambda] float32 or float64 device tensor -> (out [n, n_out],

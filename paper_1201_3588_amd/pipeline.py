@@ -11,16 +11,18 @@ Orchestration only; every numerical step is a libmcrt.so kernel.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from .mcrt import Engine, u64_view
 from .pah import PahSolver
 
 
-def band_power(out, rho, vol, n_bands=17):
-    """Emitted band power of a species summed over cells, up to the species'
-    constant number of molecules per gram: sum_c rho_c V_c F_b,c."""
-    return (out[:, :n_bands] * (rho * vol)[:, None]).sum(0)
+def relative_change(new, old):
+    """Largest relative change of the band powers between two passes (the
+    iteration's stop test; a few dozen numbers, on the host)."""
+    a, b = new.cpu().numpy(), old.cpu().numpy()
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
 
 
 class PahLoop:
@@ -33,9 +35,7 @@ class PahLoop:
         dev = self.eng.device
         self.rows = torch.empty((len(self.solvers), self.eng.n_cells, self.eng.n_lambda),
                                 dtype=torch.float64, device=dev)
-        lo, side = w.grid.leaf_boxes_cm()
-        self.rho = torch.as_tensor(w.grid.rho).to(dev)
-        self.vol = torch.as_tensor(side ** 3).to(dev)
+        self.mass = self.eng.cell_mass()
 
     def emission(self, J):
         outs = []
@@ -64,8 +64,8 @@ class PahLoop:
             self.eng.run_batched(tal, 0, N, N, seed + 7919 * it, batch or N, pah_rows=self.rows)
             T = self.eng.temperatures(tal["nabs"], N)
             J = self.eng.mean_intensity(tal["jq"], N)
-            bp = torch.stack([band_power(o, self.rho, self.vol) for o in outs])
-            change = None if prev is None else float(((bp - prev).abs() / prev.abs().clamp_min(1e-300)).max())
+            bp = torch.stack([s.band_power(o, self.mass) for s, o in zip(self.solvers, outs)])
+            change = None if prev is None else relative_change(bp, prev)
             prev = bp
             cnt = u64_view(tal["counters"])
             hist.append(dict(iteration=it, change=change, pah_abs=int(cnt[9]), escaped=int(cnt[1])))

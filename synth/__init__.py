@@ -404,6 +404,17 @@ def pah_fields(n: int, lam_um, seed: int = 4):
 # --------------------------------------------------------------------------
 # workloads
 # --------------------------------------------------------------------------
+def pah_test_rows(n_pah: int, n_cells: int, nl: int, seed: int = 3) -> np.ndarray:
+    """Seeded stand-in re-emission rows [n_pah][n_cells][nl] for transport
+    tests: per cell the running sum of uniform random weights over the bins,
+    divided by its total, last entry set to exactly 1 (a valid CDF)."""
+    rng = np.random.default_rng(seed)
+    rows = np.cumsum(rng.random((n_pah, n_cells, nl)), axis=2)
+    rows /= rows[:, :, -1:]
+    rows[:, :, -1] = 1.0
+    return rows
+
+
 def c1_sphere(n_packets: int = 100_000, seed: int = 1, nl: int = 100, nb: int = 32,
               tau_v: float = 1.0) -> Workload:
     """Uniform dust sphere R = 10 AU around a 4000 K, 1 L_sun star, 32^3 cells.

@@ -96,14 +96,20 @@ def test_pah_exact_on_sampled_disk_fields(full_pass):
         assert np.max(np.abs(g_out[c][m] / o_out[c][m] - 1)) < 1e-10
 
 
-def test_full_grid_statistics_frozen(full_pass):
-    w, e, r, T, J = full_pass
-    frozen = r["nabs"].reshape(w.grid.n_cells, w.species.n_species)
+def test_full_grid_statistics_frozen():
+    # the full 262,480-leaf grid, 2e6 packets per side with a frozen
+    # temperature field (from an oracle run of 2e5 packets), seeds differing:
+    # absorptions per cell (summed over the 24 species) and SED bins within
+    # 3 sigma (statparity's criteria)
     w2 = synth.c2_disk(n_packets=2_000_000)
-    res = statistical_check(w2, frozen=frozen)
-    for k in ("sed", "shells"):
-        frac, zmax, chi2, n = res[k]
-        assert n >= 5 and frac <= 0.02 and zmax < 6.0, (k, res[k])
+    frozen = oracle.Session(w2, n_threads=8).transport(n=200_000)["nabs"]
+
+    def per_cell(d, w):
+        return dict(sed=d["sed"].astype(np.float64),
+                    nabs=d["nabs"].reshape(w.grid.n_cells, -1).astype(np.float64).sum(1))
+    res = statistical_check(w2, frozen=frozen, summarize=per_cell)
+    for k, (ok, v) in res.items():
+        assert ok and v["n"] >= 300, (k, v)
 
 
 def test_full_pass_deferred_tally_equals_atomic(full_pass):

@@ -39,6 +39,33 @@ def test_exact_solver_matches_oracle(nc, M):
         assert np.all(np.abs(g_out[c][~mo]) <= 1e-11 * o_out[c].max())
 
 
+def test_band_power_and_cell_mass_match_oracle():
+    # the PAH iteration's stop quantity: band powers of the exact solution
+    # weighted by each leaf's dust mass, summed over the leaves of a nested
+    # disk grid (fields from the seeded generator, one per leaf)
+    from paper_1201_3588_amd import mcrt
+    w = synth.small_disk(n_packets=10, nl=200, n_sizes=1, nb=8, with_pah=True)
+    e = mcrt.Engine.from_workload(w)
+    e.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    mass = e.cell_mass()
+    o_mass = oracle.cell_mass(w.grid)
+    assert np.allclose(mass.cpu().numpy(), o_mass, rtol=1e-15, atol=0)
+    pm = w.pah[0]
+    J = synth.pah_fields(w.grid.n_cells, w.species.lam_um, seed=21)[0]
+    J[::7] = 0.0                                           # dark cells emit nothing
+    s = pah.PahSolver.from_model(pm)
+    g_out = s.solve(torch.as_tensor(J).cuda())[0]
+    bp = s.band_power(g_out, mass)
+    bp2 = s.band_power(g_out, mass)
+    T = 2.7 * (5000.0 / 2.7) ** (np.arange(500) / 499)
+    o_out = oracle.pah_solve(T, pm.enthalpy(T), w.species.lam_um, pm.cabs, pm.cband, pm.ccont, J, n_threads=8)[0]
+    o_bp = oracle.band_power(o_out, o_mass, s.n_bands)
+    g = bp.cpu().numpy()
+    assert g.shape == (17,) and np.all(o_bp > 0)
+    assert np.allclose(g, o_bp, rtol=1e-10, atol=0)
+    assert np.array_equal(g, bp2.cpu().numpy())           # fixed summation order
+
+
 def test_float_input_and_many_cells():
     pm = synth.pah_model(30, LAM)
     s = pah.PahSolver.from_model(pm)

@@ -218,3 +218,19 @@ def test_hard_photons_broaden_the_temperature_distribution():
     assert all(a > b for a, b in zip(med[1:], med[2:]))           # 13.6 eV onwards
     assert all(a < b for a, b in zip(spread[:-1], spread[1:]))
     assert spread[-1] > 5 * spread[0]
+
+
+def test_band_power_and_cell_mass_definitions():
+    # leaf masses add up to the grid's mass by brute force over a fine
+    # sampling (a density constant per leaf), and a single-cell, single-band
+    # case reduces to mass times that band's power
+    import oracle as O
+    w = synth.small_disk(n_packets=10, nl=16, n_sizes=1, nb=4)
+    m = O.cell_mass(w.grid)
+    lo, side = w.grid.leaf_boxes_cm()
+    assert np.allclose(m, w.grid.rho * side ** 3, rtol=1e-15)
+    vol = (side ** 3).sum()
+    assert abs(vol / (w.grid.nb * w.grid.base_size) ** 3 - 1) < 1e-12
+    out = np.zeros((3, 20))
+    out[1, 4] = 2.5
+    assert np.allclose(O.band_power(out, [1.0, 3.0, 5.0], 17), np.eye(17)[4] * 7.5)
