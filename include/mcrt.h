@@ -14,8 +14,9 @@
  *
  * Conventions for every entry point:
  *  - All arrays named "device" are caller-owned device memory (e.g. torch
- *    tensors); the library never allocates device memory and never frees
- *    caller memory.  Host structs are copied at the call.
+ *    tensors); the library never allocates device memory (its only device
+ *    memory of its own is the 1 KiB static array of mcrt_image_psf_static)
+ *    and never frees caller memory.  Host structs are copied at the call.
  *  - Every launch is asynchronous on the given stream; results are visible
  *    after the stream is synchronised.  Only functions ending in _sync block.
  *  - Return value: MCRT_OK or a negative MCRT_E_* code; the message of the
@@ -318,6 +319,23 @@ int32_t mcrt_jrec_ws_bytes(const mcrt_ctx *ctx, uint64_t capacity, uint64_t *byt
 int32_t mcrt_psf_radius(double fwhm_pix);
 int32_t mcrt_image_psf(const uint64_t *image, int32_t n_images, int32_t npix, double scale,
                        double fwhm_pix, double *weights, double *out, hipStream_t stream);
+
+/* mcrt_image_psf without the weights argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * forbid allocation): the 2 r + 1 weights go to a static device array of
+ * MCRT_PSF_STATIC_TAPS doubles (1 KiB) that each device holds from the
+ * library's load to the end of the process; its address is looked up once per
+ * device, on the first call with that device current.  Allocates nothing and
+ * calls no allocating routine.  Same arguments, results and errors as
+ * mcrt_image_psf, plus MCRT_E_CAPACITY if 2 r + 1 exceeded
+ * MCRT_PSF_STATIC_TAPS (no fwhm_pix in range does: r <= 41) and MCRT_E_HIP if
+ * the array's address cannot be obtained.  Every call on one device shares
+ * that array (it keeps the last call's weights, each call rewrites all it
+ * reads): calls that overlap in time on one device, e.g. on two streams,
+ * race and must be ordered by the caller. */
+#define MCRT_PSF_STATIC_TAPS 128
+int32_t mcrt_image_psf_static(const uint64_t *image, int32_t n_images, int32_t npix, double scale,
+                              double fwhm_pix, double *out, hipStream_t stream);
 /* Copies the MCRT_N_COUNTERS counters of `tallies` to host memory and waits
  * for the stream (so for every launch queued on it before). */
 int32_t mcrt_read_counters_sync(const mcrt_tallies *tallies, uint64_t *host_out, hipStream_t stream);

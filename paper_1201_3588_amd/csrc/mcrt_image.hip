@@ -10,6 +10,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mcrt.h"
 
 namespace {
@@ -61,6 +63,46 @@ __global__ void k_psf_weights(double sigma, int r, double* wts) {
   for (int d = 0; d <= 2 * r; ++d) wts[d] /= s;
 }
 
+// Weights of the allocation-free entry point: one copy per device, held from
+// the library's load to the end of the process.  In host code this name is
+// not a device address; the entry point uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[MCRT_PSF_STATIC_TAPS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// address of the current device's copy of `scratch`, looked up once per device
+hipError_t scratch_ptr(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+int32_t psf_launch(const uint64_t* image, int32_t n_images, int32_t npix, double scale, double fwhm_pix,
+                   double* weights, double* out, hipStream_t stream) {
+  const int32_t r = mcrt_psf_radius(fwhm_pix);
+  const double sigma = fwhm_pix / (2.0 * sqrt(2.0 * log(2.0)));
+  k_psf_weights<<<1, 64, 0, stream>>>(sigma, r, weights);
+  const int side = kTile + 2 * r;
+  const size_t lds = sizeof(double) * ((size_t)side * side + (size_t)side * kTile + (size_t)(2 * r + 1));
+  const dim3 grid((npix + kTile - 1) / kTile, (npix + kTile - 1) / kTile, n_images);
+  k_psf<<<grid, dim3(kTile, kTile), lds, stream>>>(reinterpret_cast<const unsigned long long*>(image), npix,
+                                                   scale, r, weights, out);
+  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+}
+
 }  // namespace
 
 extern "C" int32_t mcrt_psf_radius(double fwhm_pix) {
@@ -75,12 +117,17 @@ extern "C" int32_t mcrt_image_psf(const uint64_t* image, int32_t n_images, int32
   if (!std::isfinite(scale)) return MCRT_E_NUMERIC;
   const int32_t r = mcrt_psf_radius(fwhm_pix);
   if (r < 0) return MCRT_E_INVALID;
-  const double sigma = fwhm_pix / (2.0 * sqrt(2.0 * log(2.0)));
-  k_psf_weights<<<1, 64, 0, stream>>>(sigma, r, weights);
-  const int side = kTile + 2 * r;
-  const size_t lds = sizeof(double) * ((size_t)side * side + (size_t)side * kTile + (size_t)(2 * r + 1));
-  const dim3 grid((npix + kTile - 1) / kTile, (npix + kTile - 1) / kTile, n_images);
-  k_psf<<<grid, dim3(kTile, kTile), lds, stream>>>(reinterpret_cast<const unsigned long long*>(image), npix,
-                                                   scale, r, weights, out);
-  return hipGetLastError() == hipSuccess ? MCRT_OK : MCRT_E_HIP;
+  return psf_launch(image, n_images, npix, scale, fwhm_pix, weights, out, stream);
+}
+
+extern "C" int32_t mcrt_image_psf_static(const uint64_t* image, int32_t n_images, int32_t npix, double scale,
+                                         double fwhm_pix, double* out, hipStream_t stream) {
+  if (!image || !out || n_images < 1 || npix < 1 || npix > 4096) return MCRT_E_INVALID;
+  if (!std::isfinite(scale)) return MCRT_E_NUMERIC;
+  const int32_t r = mcrt_psf_radius(fwhm_pix);
+  if (r < 0) return MCRT_E_INVALID;
+  if (2 * r + 1 > MCRT_PSF_STATIC_TAPS) return MCRT_E_CAPACITY;
+  double* w = nullptr;
+  if (scratch_ptr(&w) != hipSuccess) return MCRT_E_HIP;
+  return psf_launch(image, n_images, npix, scale, fwhm_pix, w, out, stream);
 }

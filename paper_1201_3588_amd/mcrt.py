@@ -111,6 +111,8 @@ def lib():
         L.mcrt_psf_radius.restype = C.c_int32
         L.mcrt_image_psf.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, P, P, P]
         L.mcrt_image_psf.restype = C.c_int32
+        L.mcrt_image_psf_static.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, P, P]
+        L.mcrt_image_psf_static.restype = C.c_int32
         for name in ("mcrt_tables_bytes", "mcrt_ctx_create", "mcrt_table_layout_get", "mcrt_build_tables",
                      "mcrt_run", "mcrt_temperatures", "mcrt_mean_intensity"):
             getattr(L, name).restype = C.c_int32
@@ -147,6 +149,22 @@ def image_psf(images: torch.Tensor, npix: int, scale: float, fwhm_pix: float) ->
                               _stream())
     if rc != 0:
         raise MCRTError(rc, "mcrt_image_psf")
+    return out
+
+
+def image_psf_static(images: torch.Tensor, npix: int, scale: float, fwhm_pix: float,
+                     out: torch.Tensor) -> torch.Tensor:
+    """image_psf into a caller-given float64 `out` [n_images, npix, npix],
+    with the weights in the library's static device array
+    (mcrt_image_psf_static: no device memory is allocated)."""
+    n_img = images.numel() // (npix * npix)
+    if not images.is_contiguous() or not out.is_contiguous() or out.dtype != torch.float64 \
+            or out.numel() != n_img * npix * npix or n_img * npix * npix != images.numel():
+        raise MCRTError(-1, "image_psf_static: shape, dtype or layout mismatch")
+    rc = lib().mcrt_image_psf_static(_ptr(images), n_img, int(npix), float(scale), float(fwhm_pix), _ptr(out),
+                                     _stream())
+    if rc != 0:
+        raise MCRTError(rc, "mcrt_image_psf_static")
     return out
 
 
