@@ -1,20 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the Monte Carlo dust transfer hot path on one MI355X.
 
-One step = one pass of the hot path over the flared proto-planetary disk
-workload (64^3 base cubes refined 2x2x2 to depth 3 inside 1 AU = 262,480
-leaves, 3 materials x 8 grain sizes, 200 wavelengths, Henyey-Greenstein
-scattering, 1e7 packets from a 5800 K, 1 L_sun star, FP32 geometry, FP64
-tables and temperatures, path-length J tally on):
-  table build -> transport of all packets (path-length tally through per-segment
-  records and LDS sums; --atomic-tally for per-segment atomics) -> temperatures
-  -> mean intensity -> PAH (30 C) emission of every dusty cell from its field:
-  surrogate network with exact fallback on flagged cells -> PAH re-emission rows.
-The exact PAH solver is timed on the same cells beside the step.  The
-surrogate is trained before the timed region on exactly solved cells (the
-disk's fields plus synthetic fields).  Inputs are resident in device memory
-before the timed region.  Prints one JSON line.  The CPU oracle is timed on a
-bounded sample for reference.
+Headline workload (the largest configuration): the gap + spiral
+proto-planetary disk with PAHs on a 256^3 base grid refined 2x2x2 to depth 3
+inside 1 AU (16,784,776 leaves), 24 grain species (3 materials x 8 sizes) and
+2 PAH species (30 and 200 C atoms), 200 wavelengths, Henyey-Greenstein
+scattering, 1e9 packets per pass from a 5800 K, 1 L_sun star; FP32 geometry,
+FP64 tables and temperatures, integer tallies, path-length J tally on, the
+surrogate network in the loop for the PAH emission with the exact solver as
+fallback on flagged cells.
+
+One step = one pass of the PAH iteration through every step of the hot path:
+  table build -> PAH emission of both PAH species from the previous pass's
+  mean intensity (surrogate + exact fallback) and their re-emission rows ->
+  transport of all 1e9 packets (path-length tally through segment records,
+  id ranges that fit the record workspace) -> temperatures -> mean intensity
+  -> band powers (the iteration's stop quantity).
+Before the timed region (untimed): the grid, pass 0 (thin starlight field,
+exact PAH emission, one transport pass) and the surrogates' training on
+exactly solved cells of that pass's field plus synthetic fields.  Inputs are
+resident in device memory when the timed region starts.  Prints one JSON line;
+extra blocks time the smaller disks, the re-emission law comparison and the
+paper's Fig. 2 / Fig. 3 set-ups.  The CPU oracle is timed on a bounded sample
+of the same workload for reference.
 """
 from __future__ import annotations
 
@@ -29,6 +37,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photon packets/sec + cell-crossings/sec (1 GPU); PAH cells/sec surrogate vs exact"
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def random_atomic_rate(n_slots, stream):
@@ -281,124 +293,284 @@ def hard_photon_block(stream):
             "solve_ms_6_fields": e0.elapsed_time(e1), "P_of_T": rows}
 
 
-def c5_block(n_packets, stream):
-    """The gap + spiral disk with PAHs on a 256^3 base grid (depth 3,
-    16,784,776 leaves, 26 species, 200 bins, 1e9 packets), one pass timed end
-    to end in both forms from the same field: plain (exact PAH solver for both
-    PAH species) and with the surrogate in the loop (exact fallback on flagged
-    cells).  A pass = PAH emission and re-emission rows from the previous
-    field + transport + temperatures + mean intensity.  The surrogates are
-    trained on the disk's own first-pass fields."""
-    import numpy as np
+def random_load_rate(n_load, stream):
+    """Achievable rate of random 4-byte loads from a buffer of n_load floats
+    (the size of the transport's per-crossing gathers), HIP events."""
+    import ctypes as C
+    import torch
+    from paper_1201_3588_amd import mcrt
+    buf = torch.ones(n_load, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    n_ops = 1 << 30
+    L = mcrt.lib()
+    L.mcrt_bench_random.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_uint64,
+                                    C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p]
+    s = C.c_void_p(stream.cuda_stream)
+    L.mcrt_bench_random(None, 0, C.c_void_p(buf.data_ptr()), n_load, n_ops, 1, 1, C.c_void_p(sink.data_ptr()), s)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.mcrt_bench_random(None, 0, C.c_void_p(buf.data_ptr()), n_load, n_ops, 2, 1, C.c_void_p(sink.data_ptr()), s)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    q = 16 * 256 * ncu
+    issued = (n_ops + q - 1) // q * q
+    del buf, sink
+    return issued / (e0.elapsed_time(e1) / 1e3)
+
+
+def c2_block(steps, stream, micro):
+    """The flared disk (64^3 base, depth 3, 262,480 leaves, 24 species, 200
+    bins, 1e7 packets): one transport pass (deferred path tally) +
+    temperatures + mean intensity per step; its grid and tallies sit in the
+    L2 / Infinity Cache, so its random-access ceiling is measured at its own
+    sizes."""
     import torch
     import synth
     from paper_1201_3588_amd import mcrt
-    from paper_1201_3588_amd.pah import PahSolver
-    from paper_1201_3588_amd.surrogate import Surrogate, band_error
-    t0 = time.perf_counter()
-    w = synth.c5_full(n_packets=n_packets)
-    t_synth = time.perf_counter() - t0
+    w = synth.c2_disk()
+    N = w.n_packets
     eng = mcrt.Engine.from_workload(w)
     eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
-    N, nc, nl = w.n_packets, w.grid.n_cells, w.species.n_lambda
-    solvers = [PahSolver.from_model(pm) for pm in w.pah]
-    rows = torch.empty((len(solvers), nc, nl), dtype=torch.float64, device="cuda")
-    chunk = 1 << 22
+    deferred = eng.set_deferred_tally(min(1 << 31, max(1 << 20, 100 * N)))
+    tal = eng.new_tallies(tally_j=True)
+    ev = []
 
-    def pah_step(J, surs=None):
-        n_flag = 0
-        for p, s in enumerate(solvers):
-            for a in range(0, nc, chunk):
-                b = min(nc, a + chunk)
-                if surs is None:
+    def step():
+        for v in (t for t in tal.values() if t is not None):
+            v.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        eng.run(tal, 0, N, N, w.seed)
+        e1.record(stream)
+        ev.append((e0, e1))
+        eng.temperatures(tal["nabs"], N)
+        eng.mean_intensity(tal["jq"], N)
+
+    step()
+    torch.cuda.synchronize()
+    ev.clear()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = sum(a.elapsed_time(b) for a, b in ev) / len(ev) / 1e3
+    c = mcrt.u64_view(tal["counters"])
+    cnt = {kk: int(c[v]) for kk, v in mcrt.CNT.items()}
+    assert cnt["launched"] == N and cnt["launched"] == cnt["escaped"] + cnt["killed"] + cnt["terminated"]
+    alg = 8 * cnt["crossings"] + 16 * (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"])
+    res = {"workload": "flared_disk_64cube_depth3_262480leaves_24species_200lambda_1e7packets",
+           "packets_per_s": N * steps / wall, "ms_per_step": wall / steps * 1e3,
+           "transport_pass_ms": k * 1e3, "transport_packets_per_s": N / k,
+           "transport_crossings_per_s": cnt["crossings"] / k, "per_pass_counts": cnt,
+           "path_tally": "deferred records" if deferred else "atomic",
+           "pass_roofline": {"bound": "hbm", "achieved": alg / k / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": alg / k / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_pass": alg,
+                             "byte_model": "8 B per crossing, 16 B per tally read-modify-write "
+                                           "(path segment, absorption, escape)"}}
+    if micro:
+        loads = random_load_rate(w.grid.nb ** 3 * 2, stream)
+        atom = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
+        res["random_access_ceiling"] = {
+            "where": "grid (2 MB) and tallies (470 MB) resident in L2 / Infinity Cache",
+            "random_4B_loads_per_s": loads, "random_8B_atomics_per_s": atom,
+            "crossings_per_s_over_load_rate": cnt["crossings"] / k / loads,
+            "tally_updates_per_s_over_atomic_rate": (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k / atom}
+    del tal, eng
+    return res
+
+
+class C5Run:
+    """The headline workload and its pass (see the module docstring)."""
+
+    def __init__(self, args, stream):
+        import torch
+        import synth
+        from paper_1201_3588_amd import mcrt
+        from paper_1201_3588_amd.pah import PahSolver
+        self.args, self.stream = args, stream
+        t0 = time.perf_counter()
+        self.w = w = synth.c5_full(n_packets=args.packets)
+        self.synth_s = time.perf_counter() - t0
+        log(f"grid built in {self.synth_s:.1f} s ({w.grid.n_cells} leaves)")
+        self.eng = mcrt.Engine.from_workload(w)
+        self.eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
+        self.N, self.nc, self.nl = w.n_packets, w.grid.n_cells, w.species.n_lambda
+        self.solvers = [PahSolver.from_model(pm) for pm in w.pah]
+        self.rows = torch.empty((len(self.solvers), self.nc, self.nl), dtype=torch.float64, device="cuda")
+        self.mass = self.eng.cell_mass()
+        self.tal = self.eng.new_tallies(tally_j=True)
+        # deferred path tally: the record workspace takes the device memory
+        # left after the pass's own buffers (two fields, temperatures, a PAH
+        # output chunk, the surrogates and their training set: ~60 GB); the
+        # pass runs in id ranges whose records fit it (~250 records per packet)
+        free = torch.cuda.mem_get_info()[0]
+        cap = min(1 << 35, max(1 << 22, (free - (60 << 30)) // 16)) // 4096 * 4096
+        self.deferred = self.eng.set_deferred_tally(cap)
+        self.capacity = cap if self.deferred else 0
+        self.batch = (args.batch or cap // 300) if self.deferred else self.N
+        self.chunk = 1 << 22
+        self.surs = None
+        self.last = {}
+
+    def pah_step(self, J, exact=False):
+        """PAH emission of both species from J and their re-emission rows;
+        returns (band powers [n_pah, 17], flagged-cell count tensor)."""
+        import torch
+        bps, n_flag = [], torch.zeros((), dtype=torch.int64, device="cuda")
+        for p, s in enumerate(self.solvers):
+            bp = torch.zeros(s.n_bands, dtype=torch.float64, device="cuda")
+            for a in range(0, self.nc, self.chunk):
+                b = min(self.nc, a + self.chunk)
+                if exact or self.surs is None:
                     out = s.solve(J[a:b])[0]
                 else:
-                    out, ood = surs[p].solve(J[a:b])[:2]
-                    n_flag += int((ood != 0).sum().item())
-                s.rows(out, rows=rows[p, a:b])
-        return n_flag
+                    out, ood = self.surs[p].solve(J[a:b])[:2]
+                    n_flag += (ood != 0).sum()
+                s.rows(out, rows=self.rows[p, a:b])
+                bp += s.band_power(out, self.mass[a:b])
+                del out
+            bps.append(bp)
+        return torch.stack(bps), n_flag
 
-    def one_pass(J, seed, surs=None):
-        tal = eng.new_tallies(tally_j=True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        n_flag = pah_step(J, surs)
-        eng.run(tal, 0, N, N, seed, pah_rows=rows)
-        T = eng.temperatures(tal["nabs"], N)
-        Jn = eng.mean_intensity(tal["jq"], N)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        c = mcrt.u64_view(tal["counters"])
-        del tal, T
-        return Jn, dt, c, n_flag
+    def one_pass(self, J, seed, exact=False):
+        """One pass (the timed step).  Returns the new field; per-pass figures
+        in self.last (HIP events, read after the caller synchronises)."""
+        import torch
+        st = self.stream
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        e_start, e_pah, e_tr, e_end = ev(), ev(), ev(), ev()
+        e_start.record(st)
+        self.eng.build_tables(self.w.source.pos, self.w.source.lum, self.w.source.teff)
+        bp, n_flag = self.pah_step(J, exact)
+        e_pah.record(st)
+        for v in (t for t in self.tal.values() if t is not None):
+            v.zero_()
+        kev = []
+        for a in range(0, self.N, self.batch):
+            k0, k1 = ev(), ev()
+            k0.record(st)                 # creates the events; the library records them again
+            k1.record(st)                 # around the transport kernel of this id range
+            kev.append((k0, k1))
+            self.eng.run(self.tal, a, min(self.batch, self.N - a), self.N, seed, pah_rows=self.rows,
+                         kernel_events=(k0, k1))
+        e_tr.record(st)
+        T = self.eng.temperatures(self.tal["nabs"], self.N)
+        Jn = self.eng.mean_intensity(self.tal["jq"], self.N)
+        e_end.record(st)
+        self.last = dict(events=(e_start, e_pah, e_tr, e_end), kev=kev, bp=bp, n_flag=n_flag, T=T)
+        return Jn
 
-    J1, t_first, c1, _ = one_pass(eng.thin_field(), w.seed)
-    assert int(c1[0]) == N and int(c1[0]) == int(c1[1] + c1[2] + c1[3])
-    # surrogates trained on a sample of the first pass's lit cells plus synthetic fields
-    t_train = time.perf_counter()
-    lit = torch.nonzero(J1.sum(1) > 0).squeeze(1)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(5)
-    samp = lit[torch.randperm(lit.numel(), generator=g, device="cuda")[:1_000_000]]
-    Jtr = torch.cat([J1.index_select(0, samp),
-                     torch.as_tensor(synth.pah_fields(400_000, w.species.lam_um, seed=4)[0].astype(np.float32)).cuda()])
-    surs, errs = [], []
-    held = lit[torch.randperm(lit.numel(), generator=g, device="cuda")[:200_000]]
-    for s in solvers:
-        sur = Surrogate(s, batch=2048, seed=4)
-        out, pabs = sur.exact(Jtr)
-        sur.fit(Jtr, out, pabs, epochs=12, lr=2e-3)
-        Jh = J1.index_select(0, held)
-        pred, ood, _ = sur.predict(Jh)
-        ex, _ = sur.exact(Jh)
-        ok = (ood == 0) & (ex[:, :17].sum(1) > 0)
-        errs.append(float(torch.quantile(band_error(pred, ex)[ok], 0.95).item()))
-        surs.append(sur)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t_train
-    _, t_plain, c_plain, _ = one_pass(J1, w.seed + 1)
-    _, t_sur, c_sur, n_flag = one_pass(J1, w.seed + 1, surs)
-    for c in (c_plain, c_sur):
-        assert int(c[0]) == N and int(c[0]) == int(c[1] + c[2] + c[3])
-    return {"workload": "gap_spiral_disk_256cube_depth3_16784776leaves_26species_200lambda_1e9packets_pah",
-            "leaves": nc, "packets": N, "synth_build_s": t_synth,
-            "pass_plain_s": t_plain, "pass_surrogate_s": t_sur,
-            "packets_per_s_plain": N / t_plain, "packets_per_s_surrogate": N / t_sur,
-            "crossings_per_pass": int(c_plain[6]), "pah_absorptions_per_pass": int(c_plain[9]),
-            "pah_cells_per_pass": len(solvers) * nc, "surrogate_flagged_per_pass": n_flag,
-            "surrogate_band_error_p95": errs, "surrogate_training_s": t_train}
+    def pass_figures(self):
+        """Times and counts of the last pass (after a synchronise)."""
+        from paper_1201_3588_amd import mcrt
+        e_start, e_pah, e_tr, e_end = self.last["events"]
+        c = mcrt.u64_view(self.tal["counters"])
+        cnt = {k: int(c[v]) for k, v in mcrt.CNT.items()}
+        k_ms = [a.elapsed_time(b) for a, b in self.last["kev"]]
+        return dict(pass_ms=e_start.elapsed_time(e_end), pah_ms=e_start.elapsed_time(e_pah),
+                    transport_ms=e_pah.elapsed_time(e_tr), post_ms=e_tr.elapsed_time(e_end),
+                    k_transport_ms=k_ms, counts=cnt, n_flag=int(self.last["n_flag"].item()))
+
+    def train(self, J1):
+        """Surrogates for both PAH species, trained on exactly solved cells:
+        1e6 lit cells of the pass-1 field and 4e5 synthetic fields; held out:
+        2e5 other lit cells of that field (disjoint from the training cells)
+        and 5e4 synthetic fields of another seed."""
+        import numpy as np
+        import torch
+        import synth
+        from paper_1201_3588_amd.surrogate import Surrogate, band_error
+        t0 = time.perf_counter()
+        lit = torch.nonzero(J1.sum(1) > 0).squeeze(1)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        perm = lit[torch.randperm(lit.numel(), generator=g, device="cuda")]
+        n_tr = min(self.args.train_cells, perm.numel() // 2)
+        tr_idx, ho_idx = perm[:n_tr], perm[n_tr:n_tr + 200_000]
+        lam = self.w.species.lam_um
+        Jsyn = torch.as_tensor(synth.pah_fields(self.args.train_synthetic, lam, seed=4)[0].astype(np.float32)).cuda()
+        Jsyn_ho = torch.as_tensor(synth.pah_fields(50_000, lam, seed=14)[0].astype(np.float32)).cuda()
+        Jtr = torch.cat([J1.index_select(0, tr_idx), Jsyn])
+        Jho = J1.index_select(0, ho_idx)
+        surs, info = [], []
+
+        def err(sur, J):
+            pred, ood, _ = sur.predict(J)
+            ex, _ = sur.exact(J)
+            ok = (ood == 0) & (ex[:, :17].sum(1) > 0)
+            e = band_error(pred, ex)[ok]
+            return {"cells": int(J.shape[0]), "p95": float(torch.quantile(e, 0.95).item()),
+                    "median": float(e.median().item()), "flagged": float((ood != 0).float().mean().item())}
+        for s, pm in zip(self.solvers, self.w.pah):
+            sur = Surrogate(s, batch=2048, seed=4)
+            out, pabs = sur.exact(Jtr)
+            hist = sur.fit(Jtr, out, pabs, epochs=self.args.epochs, lr=2e-3)
+            sub = Jtr[:: max(1, Jtr.shape[0] // 100_000)][:100_000]
+            info.append({"n_c": pm.n_c, "train_cells": int(Jtr.shape[0]), "epochs": self.args.epochs,
+                         "loss_first": hist[0], "loss_last": hist[-1],
+                         "band_error_training_cells_in_distribution": err(sur, sub),
+                         "band_error_held_out_disk_cells": err(sur, Jho),
+                         "band_error_held_out_synthetic_fields": err(sur, Jsyn_ho)})
+            surs.append(sur)
+        torch.cuda.synchronize()
+        self.surs = surs
+        return {"species": info, "setup_s": time.perf_counter() - t0,
+                "held_out": "2e5 lit cells of the pass-1 field not among the training cells "
+                            "(disjoint slices of one permutation) and 5e4 synthetic fields of another seed"}
+
+
+def cpu_baseline_c5(w, n_s):
+    """The oracle (FP64 C, threaded over the host cores) on the first n_s
+    packet ids of the headline workload, path-length tally on, running
+    absorption counts.  Its PAH re-emission rows are seeded stand-in rows
+    (a table of 65,536 random CDF rows, cell c using row c mod 65,536), so it
+    does not need the 27 GB of per-cell rows."""
+    import numpy as np
+    import oracle
+    import synth
+    threads = min(16, len(os.sched_getaffinity(0)))
+    n_pah = int((w.species.kind == 1).sum())
+    table = synth.pah_test_rows(n_pah, 65536, w.species.n_lambda, seed=77).reshape(n_pah * 65536, -1)
+    rmap = (np.arange(w.grid.n_cells, dtype=np.int64) % 65536).astype(np.int32)
+    rmap = np.concatenate([rmap + 65536 * p for p in range(n_pah)]).astype(np.int32)
+    s = oracle.Session(w, n_threads=threads, pah_rows=table, pah_row_map=rmap)
+    acc = s.new_accumulator()
+    for v in acc.values():
+        if v is not None:
+            v.fill(0)                    # touch the pages before the clock starts
+    tc0 = time.perf_counter()
+    s.accumulate(acc, 0, n_s)
+    tc = time.perf_counter() - tc0
+    return {"value": n_s / tc, "unit": "packets/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_s} packet ids of the 256^3 gap + spiral disk (1e9-packet pass), transport "
+                      f"with path-length tally and running counts, PAH rows from a seeded stand-in table, "
+                      f"{tc:.1f} s wall"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--packets", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--packets", type=int, default=1_000_000_000)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="packets per transport call (0: sized so that the records of a range fit the "
+                         "workspace, from the records per packet of pass 0)")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
-    ap.add_argument("--no-pah", action="store_true")
+    ap.add_argument("--train-cells", type=int, default=1_000_000)
     ap.add_argument("--train-synthetic", type=int, default=400_000)
     ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--train-passes", type=int, default=3,
-                    help="transport passes (other seeds) whose disk fields join the training set")
-    ap.add_argument("--c3", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time one pass of the gap + spiral disk with PAHs (HBM-resident tallies)")
-    ap.add_argument("--c3-packets", type=int, default=100_000_000)
-    ap.add_argument("--c3-iterate", action=argparse.BooleanOptionalAction, default=True,
-                    help="also iterate the gap + spiral disk's PAH emission to convergence")
-    ap.add_argument("--atomic-tally", action="store_true",
-                    help="path-length tally by per-segment atomics instead of the deferred records")
-    ap.add_argument("--reemission", action=argparse.BooleanOptionalAction, default=True,
-                    help="compare the paper's re-emission law with the Bjorkman-Wood one")
-    ap.add_argument("--c5", action="store_true",
-                    help="also time the 256^3 gap + spiral disk (1e9 packets) end to end, plain and "
-                         "with the surrogate in the loop (minutes; needs ~150 GB of device memory)")
-    ap.add_argument("--c5-packets", type=int, default=1_000_000_000)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
-                         "the reference for scaling hardware byte counters")
+    ap.add_argument("--plain", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time one pass with the exact PAH solver instead of the surrogate")
+    ap.add_argument("--extra", action=argparse.BooleanOptionalAction, default=True,
+                    help="also run the smaller disks, the re-emission law comparison and the Fig. 3 set-up")
+    ap.add_argument("--c3-iterate", action=argparse.BooleanOptionalAction, default=True)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
@@ -409,162 +581,62 @@ def main():
     import torch
 
     import synth
-    from paper_1201_3588_amd import mcrt
-
     torch.cuda.set_device(0)
-    if args.copy_probe:
-        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.mul(a, 1.0, out=b)
-        torch.cuda.synchronize()
-        del a, b
-    w = synth.c2_disk(n_packets=args.packets)
-    N = w.n_packets
-    eng = mcrt.Engine.from_workload(w)
-    # path-length tally through segment records (about 64 per packet here)
-    # instead of one atomic per segment
-    deferred = (not args.atomic_tally) and eng.set_deferred_tally(min(1 << 31, max(1 << 20, 100 * N)))
-    tal = eng.new_tallies(tally_j=True)
     stream = torch.cuda.current_stream()
-    ev = []
-    dusty = torch.as_tensor(np.nonzero(w.grid.rho > 0)[0]).cuda()
-    sur = None
-    info = {}
-    if not args.no_pah:
-        from paper_1201_3588_amd import pah
-        from paper_1201_3588_amd.surrogate import Surrogate, band_error
-        pm = synth.pah_model(30, w.species.lam_um)
-        solver = pah.PahSolver.from_model(pm)
-        sur = Surrogate(solver, batch=2048, seed=4)
-        # training cells: the disk's own fields (one pass) plus synthetic fields
-        eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
-        t_prep = time.perf_counter()
-        Jd = []
-        for k in range(args.train_passes):
-            for v in (t for t in tal.values() if t is not None):
-                v.zero_()
-            eng.run(tal, 0, N, N, w.seed + 101 * (k + 1))
-            Jd.append(eng.mean_intensity(tal["jq"], N).index_select(0, dusty))
-        Js = torch.as_tensor(synth.pah_fields(args.train_synthetic, w.species.lam_um, seed=4)[0]
-                             .astype(np.float32)).cuda()
-        Jtr = torch.cat(Jd + [Js])
-        keep = Jtr.sum(1) > 0
-        Jtr = Jtr[keep].contiguous()
-        print(f"bench: exact solve of {Jtr.shape[0]} training cells", file=sys.stderr, flush=True)
-        out_tr, pabs_tr = sur.exact(Jtr)
-        torch.cuda.synchronize()
-        print(f"bench: solved in {time.perf_counter() - t_prep:.1f} s; training", file=sys.stderr, flush=True)
-        hist = sur.fit(Jtr, out_tr, pabs_tr, epochs=args.epochs, lr=2e-3,
-                       log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
-        torch.cuda.synchronize()
-        info["surrogate_training"] = {"cells": int(Jtr.shape[0]), "epochs": args.epochs,
-                                      "loss_first": hist[0], "loss_last": hist[-1],
-                                      "setup_s": time.perf_counter() - t_prep}
-        rows = torch.empty((dusty.numel(), w.species.n_lambda), dtype=torch.float64, device="cuda")
-    pah_t = []
-
-    def step():
-        for v in (t for t in tal.values() if t is not None):
-            v.zero_()
-        eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        eng.run(tal, 0, N, N, w.seed)
-        e1.record(stream)
-        ev.append((e0, e1))
-        T = eng.temperatures(tal["nabs"], N)
-        J = eng.mean_intensity(tal["jq"], N)
-        if sur is not None:
-            Jc = J.index_select(0, dusty)
-            p0 = torch.cuda.Event(enable_timing=True)
-            p1 = torch.cuda.Event(enable_timing=True)
-            p0.record(stream)
-            out, ood, pabs, idx = sur.solve(Jc)
-            sur.solver.rows(out, rows=rows)
-            p1.record(stream)
-            pah_t.append((p0, p1, ood))
-        return T, J
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev.clear()
-    pah_t.clear()
-    print("bench: timed steps", file=sys.stderr, flush=True)
+    R = C5Run(args, stream)
+    N = R.N
+    # pass 0 from the optically thin starlight field, exact PAH emission
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    J = R.one_pass(R.eng.thin_field(), R.w.seed + 1000, exact=True)
     torch.cuda.synchronize()
+    p0 = R.pass_figures()
+    if R.deferred and not args.batch:
+        # id ranges whose records fit the workspace with 8 % to spare
+        R.batch = int(R.capacity / (1.08 * p0["counts"]["jseg"] / N))
+    log(f"workspace {R.capacity} records, id ranges of {R.batch} packets")
+    log(f"pass 0 (exact PAH emission) in {time.perf_counter() - t0:.1f} s")
+    training = R.train(J)
+    log(f"surrogates trained in {training['setup_s']:.1f} s")
+    plain = None
+    if args.plain:
+        # one pass in the plain form (exact solver for every PAH cell), same field
+        Jp = R.one_pass(J, R.w.seed + 999, exact=True)
+        torch.cuda.synchronize()
+        plain = R.pass_figures()
+        del Jp
+    seed = R.w.seed
+    for k in range(args.warmup):
+        J = R.one_pass(J, seed + k)
+    torch.cuda.synchronize()
+    log("timed steps")
+    figs, bps = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        J = R.one_pass(J, seed + args.warmup + k)
+        torch.cuda.synchronize()
+        figs.append(R.pass_figures())
+        bps.append(R.last["bp"].cpu().numpy())
     t1 = time.perf_counter()
     wall = t1 - t0
-    k_ms = [a.elapsed_time(b) for a, b in ev]
-    k_avg = sum(k_ms) / len(k_ms) / 1e3
-    if sur is not None:
-        n_c = int(dusty.numel())
-        s_ms = [a.elapsed_time(b) for a, b, _ in pah_t]
-        s_avg = sum(s_ms) / len(s_ms) / 1e3
-        frac_ood = float((pah_t[-1][2] != 0).float().mean().item())
-        # exact solver on the same cells, and the surrogate's band error against it
-        Jc = eng.mean_intensity(tal["jq"], N).index_select(0, dusty)
-        torch.cuda.synchronize()
-        x0 = torch.cuda.Event(enable_timing=True)
-        x1 = torch.cuda.Event(enable_timing=True)
-        x0.record(stream)
-        ex, _pabs_ex = sur.exact(Jc)
-        x1.record(stream)
-        pred, ood, _ = sur.predict(Jc)
-        torch.cuda.synchronize()
-        t_ex = x0.elapsed_time(x1) / 1e3
-        err = band_error(pred, ex)
-        okm = (ood == 0) & (ex[:, :17].sum(1) > 0)
-        cpu_pah = None
-        if not args.no_cpu:
-            import oracle
-            threads = min(16, len(os.sched_getaffinity(0)))
-            sample = Jc[:: max(1, n_c // 4000)][:4000].double().cpu().numpy()
-            Tg = 2.7 * (5000.0 / 2.7) ** (np.arange(500) / 499)
-            tc0 = time.perf_counter()
-            oracle.pah_solve(Tg, pm.enthalpy(Tg), w.species.lam_um, pm.cabs, pm.cband, pm.ccont, sample,
-                             n_threads=threads)
-            cpu_pah = {"value": sample.shape[0] / (time.perf_counter() - tc0), "unit": "cells/s",
-                       "cores": threads, "kind": "oracle",
-                       "sample": f"{sample.shape[0]} of the disk's dusty cells, exact P(T) solver"}
-        info["pah"] = {"cells": n_c, "exact_cells_per_s": n_c / t_ex, "cpu_baseline_exact": cpu_pah,
-                       "surrogate_in_loop_cells_per_s": n_c / s_avg,
-                       "speedup": t_ex / s_avg, "ood_fraction": frac_ood,
-                       "ood_input_fraction": float(((ood & 1) != 0).float().mean().item()),
-                       "ood_balance_fraction": float(((ood & 2) != 0).float().mean().item()),
-                       "exact_balance_dev_p99": float(torch.quantile(
-                           (ex.sum(1) / _pabs_ex - 1).abs()[ex.sum(1) > 0], 0.99).item()),
-                       "band_error_p95": float(torch.quantile(err[okm], 0.95).item()),
-                       "band_error_median": float(err[okm].median().item())}
-    c = mcrt.u64_view(tal["counters"])
-    cnt = {k: int(c[v]) for k, v in mcrt.CNT.items()}
-    assert cnt["launched"] == N and cnt["launched"] == cnt["escaped"] + cnt["killed"] + cnt["terminated"]
-
-    # algorithmic bytes of one transport pass: per crossing the density (4 B)
-    # and base-map entry (4 B); per path-tally segment one 8 B read-modify-write
-    # (16 B); per absorption and per escape one 8 B atomic (16 B).  With the
-    # deferred tally the pass is the transport kernel plus the record passes
-    # (count, scan, scatter, sum), all inside the timed run.
-    alg_bytes = 8 * cnt["crossings"] + 16 * cnt["jseg"] + 16 * cnt["absorptions"] + 16 * cnt["escaped"]
-    achieved = alg_bytes / k_avg / 1e9
-    # HBM bytes of one launch from the committed counter summary, if it was taken
-    # on the current transport kernel source
-    traffic = None
-    try:
-        import hashlib
-        h = hashlib.sha256()
-        for f in ("mcrt_transport.hip", "mcrt_jdefer.hip"):
-            h.update(open(os.path.join(ROOT, "paper_1201_3588_amd", "csrc", f), "rb").read())
-        sha = h.hexdigest()
-        kv = dict(l.split(": ", 1) for l in open(os.path.join(ROOT, "profiles", "transport_flared_disk_pmc.md"))
-                  if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-        if kv.get("source_sha256", "").strip() == sha and N == 10_000_000:
-            traffic = int(kv["traffic_bytes_per_launch"])
-    except OSError:
-        pass
+    cnt = figs[-1]["counts"]
+    for f in figs:
+        c = f["counts"]
+        assert c["launched"] == N and c["launched"] == c["escaped"] + c["killed"] + c["terminated"]
+    changes = [None] + [float(np.max(np.abs(b - a) / np.maximum(np.abs(a), 1e-300))) for a, b in zip(bps[:-1], bps[1:])]
+    k_all = [t for f in figs for t in f["k_transport_ms"]]
+    k_avg = sum(k_all) / len(k_all) / 1e3
+    n_launch = len(figs[-1]["k_transport_ms"])
+    tr_ms = sum(f["transport_ms"] for f in figs) / len(figs)
+    pah_ms = sum(f["pah_ms"] for f in figs) / len(figs)
+    cr = sum(f["counts"]["crossings"] for f in figs) / len(figs)
+    # algorithmic bytes of the transport kernel per launch (one id range):
+    # per crossing the base-cube entry with the density term (8 B); per path
+    # segment its 8 B record; per absorption and per escape one 8 B atomic
+    # read-modify-write (16 B)
+    alg_pass = 8 * cnt["crossings"] + 8 * cnt["jseg"] + 16 * (cnt["absorptions"] + cnt["escaped"])
+    alg_launch = alg_pass / n_launch
+    achieved = alg_launch / k_avg / 1e9
+    n_pah_cells = len(R.solvers) * R.nc
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,
@@ -578,67 +650,64 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "flared_disk_64cube_depth3_262480leaves_24species_200lambda_1e7packets",
-                   "packets_per_step": N, "leaves": w.grid.n_cells, "n_lambda": w.species.n_lambda,
-                   "species": w.species.n_species, "transport": "f32 geometry, f64 tables/T",
-                   "tally_j": True},
-        "crossings_per_s": cnt["crossings"] * args.steps / wall,
-        "transport_kernel_ms": k_avg * 1e3,
-        "transport_packets_per_s": N / k_avg,
-        "transport_crossings_per_s": cnt["crossings"] / k_avg,
+        "config": {"workload": "gap_spiral_disk_256cube_depth3_16784776leaves_26species_200lambda_1e9packets_pah",
+                   "packets_per_step": N, "leaves": R.nc, "n_lambda": R.nl, "species": int(R.w.species.n_species),
+                   "pah_species": len(R.solvers), "transport": "f32 geometry, f64 tables/T",
+                   "tally_j": True, "pah_emission": "surrogate in the loop, exact fallback"},
+        "crossings_per_s": cr * args.steps / wall,
         "per_step_counts": cnt,
-        **info,
+        "step_breakdown_ms": {"pah_emission_and_rows": pah_ms, "transport_pass": tr_ms,
+                              "k_transport_sum": sum(k_all) / len(figs),
+                              "record_passes_and_launch_gaps": tr_ms - sum(k_all) / len(figs),
+                              "temperatures_and_mean_intensity": sum(f["post_ms"] for f in figs) / len(figs)},
+        "transport_packets_per_s": N / (tr_ms / 1e3),
+        "transport_crossings_per_s": cr / (tr_ms / 1e3),
+        "path_tally": {"mode": f"deferred records, id ranges of {R.batch} packets" if R.deferred else "atomic",
+                       "workspace_records": R.capacity, "segments_per_packet": cnt["jseg"] / N},
+        "pah": {"molecule_cells_per_pass": n_pah_cells,
+                "surrogate_in_loop_cells_per_s": n_pah_cells / (pah_ms / 1e3),
+                "exact_cells_per_s": n_pah_cells / (plain["pah_ms"] / 1e3) if plain else None,
+                "speedup": (plain["pah_ms"] / pah_ms) if plain else None,
+                "fallback_fraction": figs[-1]["n_flag"] / n_pah_cells,
+                "surrogate_training": training,
+                "iteration_band_power_change_per_step": changes,
+                "pass_plain_s": plain["pass_ms"] / 1e3 if plain else None,
+                "pass_surrogate_s": wall / args.steps},
+        "pass0": {"pass_ms": p0["pass_ms"], "pah_exact_ms": p0["pah_ms"], "transport_ms": p0["transport_ms"]},
+        "synth_build_s": R.synth_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("transport pass: k_transport<float,false,false,true> + k_jr_count, k_scan_*, "
-                                "k_jr_scatter, k_jr_items, k_jr_sum") if deferred else
-                               "k_transport<float,false,false,false>",
-                     "alg_bytes_per_launch": alg_bytes},
-        "path_tally": {"mode": "deferred records" if deferred else "atomic",
-                       "segments_per_s": cnt["jseg"] / k_avg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_transport<float,false,false,true>",
+                     "launches_per_step": n_launch, "avg_launch_ms": k_avg * 1e3,
+                     "alg_bytes_per_launch": alg_launch,
+                     "byte_model": "8 B per crossing (base-cube entry + density), 8 B per path-segment record, "
+                                   "16 B per absorption and per escape (8 B atomic read-modify-write)"},
     }
-
+    del J
+    R.tal = None
     if not args.no_micro:
-        atom_rate = random_atomic_rate(w.species.n_lambda * w.grid.n_cells, stream)
-        # the tally updates of the pass (path segments, absorptions, escapes)
-        # per second against the measured rate of random 64-bit atomics over a
-        # table of the path tally's size: above 1 once the path segments no
-        # longer go through atomics
-        tr_atoms = (cnt["jseg"] + cnt["absorptions"] + cnt["escaped"]) / k_avg
+        loads = random_load_rate(R.w.grid.nb ** 3 * 2, stream)
         out["random_access_ceiling"] = {
-            "atomics_per_s": atom_rate, "table_bytes": w.species.n_lambda * w.grid.n_cells * 8,
-            "gbs_at_16B_per_op": atom_rate * 16 / 1e9,
-            "tally_updates_per_s": tr_atoms, "frac_of_ceiling": tr_atoms / atom_rate}
-
-    if args.reemission:
+            "random_4B_loads_per_s": loads,
+            "buffer_bytes": R.w.grid.nb ** 3 * 8,
+            "crossings_per_s_in_k_transport": cnt["crossings"] / n_launch / k_avg,
+            "frac_of_load_rate": cnt["crossings"] / n_launch / k_avg / loads,
+            "note": "one dependent 8 B gather per crossing against random 4 B loads over the grid's size"}
+    w5 = R.w
+    del R
+    torch.cuda.empty_cache()
+    if args.extra:
+        out["c2"] = c2_block(5, stream, not args.no_micro)
         out["reemission_law"] = [
             reemission_block(synth.c1_sphere(n_packets=n), stream,
                              f"uniform_sphere_32cube_100lambda_{n:.0e}packets_f64".replace("+0", ""))
             for n in (100_000, 1_000_000, 10_000_000)]
-        out["reemission_law"].append(reemission_block(synth.c2_disk(n_packets=N), stream,
-                                                      out["config"]["workload"]))
-    if not args.no_pah:
+        out["reemission_law"].append(reemission_block(synth.c2_disk(), stream,
+                                                      "flared_disk_64cube_depth3_262480leaves_1e7packets"))
         out["pah_hard_photons"] = hard_photon_block(stream)
-    if args.c3:
-        out["c3"] = c3_block(args.c3_packets, not args.no_micro, stream, iterate=args.c3_iterate)
-    if args.c5:
-        out["c5"] = c5_block(args.c5_packets, stream)
-
+        out["c3"] = c3_block(100_000_000, not args.no_micro, stream, iterate=args.c3_iterate)
     if not args.no_cpu:
-        import oracle
-        try:
-            threads = min(16, len(os.sched_getaffinity(0)))
-        except AttributeError:
-            threads = min(16, os.cpu_count() or 1)
-        n_s = min(args.cpu_sample, N)
-        s = oracle.Session(w, n_threads=threads)
-        acc = s.new_accumulator()
-        tc0 = time.perf_counter()
-        s.accumulate(acc, 0, n_s)
-        tc = time.perf_counter() - tc0
-        out["cpu_baseline"] = {"value": n_s / tc, "unit": "packets/s", "cores": threads, "kind": "oracle",
-                               "sample": f"first {n_s} packet ids of the same workload, transport only, "
-                                         f"{tc:.1f} s wall"}
+        out["cpu_baseline"] = cpu_baseline_c5(w5, args.cpu_sample)
     print(json.dumps(out))
 
 

@@ -209,6 +209,8 @@ typedef struct {
   void *jrec_ws;               /* device workspace of mcrt_jrec_ws_bytes(jrec_capacity) bytes for the
                                   deferred path tally, or NULL for direct atomic adds */
   uint64_t jrec_capacity;      /* path-segment records the workspace holds */
+  hipEvent_t kernel_begin;     /* optional (NULL): events recorded on the stream right before and */
+  hipEvent_t kernel_end;       /* right after the transport kernel itself, to time it alone */
 } mcrt_run_opts;
 
 /* Byte offsets of the tables inside the tables buffer (for inspection). */
@@ -297,7 +299,8 @@ int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
  * more than 1536 * 40704 words) and LDS sums, on the same stream; the tally
  * is identical to the one of the atomic path (integer sums).  Segments beyond
  * jrec_capacity records are added directly (still exact).  Workspace bytes
- * for a capacity: *bytes; MCRT_E_INVALID for capacity outside [4096, 2^31],
+ * for a capacity (16 bytes per record plus small tables): *bytes;
+ * MCRT_E_INVALID for capacity outside [4096, 2^35],
  * MCRT_E_UNSUPPORTED when the grid is deeper than 7 levels or the tally has
  * more than 2^20 * 40704 words.  No device work. */
 int32_t mcrt_jrec_ws_bytes(const mcrt_ctx *ctx, uint64_t capacity, uint64_t *bytes);
@@ -336,6 +339,7 @@ int32_t mcrt_image_psf(const uint64_t *image, int32_t n_images, int32_t npix, do
 #define MCRT_PSF_STATIC_TAPS 128
 int32_t mcrt_image_psf_static(const uint64_t *image, int32_t n_images, int32_t npix, double scale,
                               double fwhm_pix, double *out, hipStream_t stream);
+
 /* Copies the MCRT_N_COUNTERS counters of `tallies` to host memory and waits
  * for the stream (so for every launch queued on it before). */
 int32_t mcrt_read_counters_sync(const mcrt_tallies *tallies, uint64_t *host_out, hipStream_t stream);

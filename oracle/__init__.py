@@ -66,7 +66,8 @@ class Problem(C.Structure):
                 ("n_threads", C.c_int32), ("frozen_nabs", _u64p), ("pah_rows", _dp),
                 ("n_obs", C.c_int32), ("npix", C.c_int32), ("n_img_lambda", C.c_int32), ("pad_img", C.c_int32),
                 ("img_lambda", C.c_int32 * 8), ("img_center", C.c_double * 3), ("img_half_width", C.c_double),
-                ("img_cos_cone", C.c_double), ("obs_dir", (C.c_double * 3) * 8)]
+                ("img_cos_cone", C.c_double), ("obs_dir", (C.c_double * 3) * 8),
+                ("pah_row_map", _i32p)]
 
 
 class Tables(C.Structure):
@@ -139,7 +140,9 @@ class Session:
 
     def __init__(self, w, n_threads: int = 1, n_total: int | None = None, seed: int | None = None,
                  flags: int | None = None, frozen_nabs=None, pah_rows=None, max_events=None,
-                 observers=None):
+                 observers=None, pah_row_map=None):
+        """pah_rows: dense [n_pah][n_cells][nl] CDF rows, or with pah_row_map
+        (int32 [n_pah * n_cells]) a compact table [n_rows][nl] indexed by it."""
         g, sp, src = w.grid, w.species, w.source
         self.w = w
         self._keep = []
@@ -179,6 +182,12 @@ class Session:
             p.flags |= FLAG_FROZEN_T
         if pah_rows is not None:
             p.pah_rows = _p(keep(pah_rows, np.float64))
+        if pah_row_map is not None:
+            rm = keep(pah_row_map, np.int32)
+            n_pah = int((np.asarray(sp.kind) == 1).sum())
+            n_rows = np.asarray(pah_rows).reshape(-1, sp.n_lambda).shape[0]
+            assert rm.size == n_pah * g.n_cells and rm.min() >= 0 and rm.max() < n_rows
+            p.pah_row_map = _p(rm, _i32p)
         if observers is not None:
             ob = observers
             p.n_obs, p.npix = len(ob["dirs"]), int(ob["npix"])

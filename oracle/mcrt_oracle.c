@@ -476,7 +476,8 @@ static void run_packet(const orc_problem *p, const orc_tables *t, uint64_t pid, 
           }
           j = cdf_search(t->R + ((int64_t)sp * (K - 1) + kb) * nl, nl, u[4]);
         } else {
-          const double *row = p->pah_rows + ((int64_t)pah_slot[sp] * p->n_cells + cell) * nl;
+          const int64_t slot = (int64_t)pah_slot[sp] * p->n_cells + cell;
+          const double *row = p->pah_rows + (p->pah_row_map ? (int64_t)p->pah_row_map[slot] : slot) * nl;
           j = cdf_search(row, nl, u[4]);
           add_u64(&cnt[ORC_CNT_PAH_ABS], 1, thr);
         }

@@ -74,6 +74,9 @@ typedef struct {
   double img_half_width;           /* cm */
   double img_cos_cone;             /* in (0, 1] */
   double obs_dir[8][3];            /* towards the observers (normalised here) */
+  /* optional: row of (PAH slot p, cell c) is pah_rows + pah_row_map[p n_cells + c] nl,
+     so many cells can share a row of a compact table; NULL = the dense layout */
+  const int32_t *pah_row_map;      /* [n_pah][n_cells] or NULL */
 } orc_problem;
 
 typedef struct {

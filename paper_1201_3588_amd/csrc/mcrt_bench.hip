@@ -32,9 +32,12 @@ __global__ void __launch_bounds__(256) k_rand_loads(const float* __restrict__ t,
   const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long s = mix64(seed ^ (tid * 0x9E3779B97F4A7C15ull));
   float acc = 0.0f;
+  // a power-of-two size takes a mask instead of the 64-bit remainder, whose
+  // emulation would make the loop bound by arithmetic rather than by memory
+  const unsigned long long mask = (n_load & (n_load - 1)) == 0 ? n_load - 1 : 0;
   for (unsigned long long i = 0; i < ops_per_thread; ++i) {
     s = mix64(s + 0x9E3779B97F4A7C15ull);
-    acc += t[s % n_load];
+    acc += t[mask ? (s & mask) : s % n_load];
   }
   if (acc == -1.0f) sink[0] = acc;   // keeps the loads alive
 }

@@ -72,6 +72,7 @@ constexpr uint64_t kBucketSlots = 40704;        // tally words per LDS bucket (u
 constexpr uint64_t kTile1 = 1ull << 18;         // records per partition tile
 constexpr uint64_t kOneLevelMax = 1536;         // more buckets: two partition levels
 constexpr uint64_t kMaxBuckets = 1ull << 20;
+constexpr uint64_t kMaxRecords = 1ull << 35;     // workspace capacity limit (64-bit offsets)
 struct JrecLayout {
   uint64_t n_buckets, n_tiles, capacity;
   bool two_level;

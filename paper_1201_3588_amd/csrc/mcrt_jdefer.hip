@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint64_t slo
 // entry (c, f, 0) of the level-2 counts, laid out [c][f][tile of c] with
 // tb[c] tiles before coarse range c.
 struct BucketMap {
-  const uint32_t* offs;
+  const uint64_t* offs;
   const uint32_t* tb;       // null for one level
   uint64_t nt;
   uint32_t fpc, nc, nb;     // nb: buckets
@@ -136,7 +136,7 @@ __device__ __forceinline__ void count_range(const unsigned long long* __restrict
 // level 1: tile t of the record array; counts [bucket][tile]
 __global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __restrict__ rec,
                                                  const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                 UDiv span, uint64_t nt, uint32_t* __restrict__ counts) {
+                                                 UDiv span, uint64_t nt, uint64_t* __restrict__ counts) {
   extern __shared__ uint32_t h[];
   const uint64_t n = n_records(hdr, cap);
   const uint64_t used = (n + kTile1 - 1) / kTile1;
@@ -151,12 +151,12 @@ __global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __re
   }
   // the tiles past the last record: block t writes their zero counts
   if (blockIdx.x >= used && blockIdx.x < nt)
-    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + blockIdx.x] = 0u;
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + blockIdx.x] = 0ull;
 }
 
 // tiles of each coarse range for level 2: tb[c] = tiles before range c
 // (ranges from the level-1 offsets), tb[nc] = all tiles
-__global__ void __launch_bounds__(1024) k_jr_dir(const uint32_t* __restrict__ offs1, const unsigned long long* hdr,
+__global__ void __launch_bounds__(1024) k_jr_dir(const uint64_t* __restrict__ offs1, const unsigned long long* hdr,
                                                 uint64_t cap, uint32_t nc, uint64_t nt, uint32_t* __restrict__ tb) {
   __shared__ uint32_t s[1024];
   const uint64_t n = n_records(hdr, cap);
@@ -186,9 +186,9 @@ __global__ void __launch_bounds__(1024) k_jr_dir(const uint32_t* __restrict__ of
 // level 2: tile g is tile k of coarse range c; counts at [c][f][k]
 __global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __restrict__ rec,
                                                   const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
-                                                  uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
+                                                  uint32_t nc, uint64_t nt, const uint64_t* __restrict__ offs1,
                                                   const uint32_t* __restrict__ tb, UDiv span,
-                                                  uint32_t* __restrict__ counts2) {
+                                                  uint64_t* __restrict__ counts2) {
   extern __shared__ uint32_t h[];
   uint64_t g;
   uint32_t c, k;
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __r
 
 // exclusive scan of v[0, n) in place: block sums, their scan, then each block
 // rescans its range from its base
-__global__ void __launch_bounds__(256) k_scan_sums(const uint32_t* __restrict__ v, uint64_t n,
+__global__ void __launch_bounds__(256) k_scan_sums(const uint64_t* __restrict__ v, uint64_t n,
                                                   unsigned long long* __restrict__ bsum) {
   __shared__ unsigned long long s[256];
   const uint64_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
@@ -234,25 +234,25 @@ __global__ void k_scan_top(unsigned long long* bsum) {
   bsum[kScanBlocks] = run;
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(uint32_t* __restrict__ v, uint64_t n,
+__global__ void __launch_bounds__(256) k_scan_apply(uint64_t* __restrict__ v, uint64_t n,
                                                    const unsigned long long* __restrict__ bsum) {
-  __shared__ uint32_t s[256];
+  __shared__ uint64_t s[256];
   const uint64_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
   const uint64_t a = blockIdx.x * chunk, e = a + chunk < n ? a + chunk : n;
-  uint32_t carry = (uint32_t)bsum[blockIdx.x];
+  uint64_t carry = bsum[blockIdx.x];
   for (uint64_t k0 = a; k0 < e; k0 += 256) {
     const uint64_t k = k0 + threadIdx.x;
-    const uint32_t x = k < e ? v[k] : 0u;
+    const uint64_t x = k < e ? v[k] : 0ull;
     s[threadIdx.x] = x;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {      // inclusive scan (Hillis-Steele)
-      const uint32_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+      const uint64_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
       __syncthreads();
       s[threadIdx.x] += y;
       __syncthreads();
     }
     if (k < e) v[k] = carry + s[threadIdx.x] - x;
-    const uint32_t tot = s[255];
+    const uint64_t tot = s[255];
     __syncthreads();
     carry += tot;
   }
@@ -298,7 +298,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part
 // addresses) from run[b], the next free position of bucket b in dst.
 template <int NT>
 __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64_t a, uint64_t e, uint64_t slot0,
-                              const UDiv& span, uint32_t nb, uint32_t* run, uint32_t* pre, unsigned long long* srt,
+                              const UDiv& span, uint32_t nb, uint64_t* run, uint32_t* pre, unsigned long long* srt,
                               uint32_t* part, unsigned long long* __restrict__ dst, uint64_t n, uint32_t sub) {
   constexpr int kMaxPer = 16;                                         // sub <= 16 NT
   for (uint64_t s0 = a; s0 < e; s0 += sub) {
@@ -332,7 +332,7 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
       const uint32_t kk = k < m ? k : 0u;
       const unsigned long long x = srt[kk];
       const uint32_t b = bucket_of(x, slot0, span, nb);
-      const uint64_t d = (uint64_t)run[b] + (kk - pre[b]);
+      const uint64_t d = run[b] + (kk - pre[b]);
       // plain store: a bucket's runs are completed across sub-tiles in the L2
       // (non-temporal stores made this pass 23 % slower)
       if (k < m && d < n) dst[d] = x;
@@ -352,12 +352,12 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
 template <int NT>
 __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src,
                                                     const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                    UDiv span, uint64_t nt, const uint32_t* __restrict__ offs,
+                                                    UDiv span, uint64_t nt, const uint64_t* __restrict__ offs,
                                                     unsigned long long* __restrict__ dst, uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;                                   // [sub] records by bucket
-  uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);          // [nb] next position per bucket
-  uint32_t* pre = run + nb;                                           // [nb] counts, then prefix
+  uint64_t* run = reinterpret_cast<uint64_t*>(smem64 + sub);          // [nb] next position per bucket
+  uint32_t* pre = reinterpret_cast<uint32_t*>(run + nb);              // [nb] counts, then prefix
   __shared__ uint32_t part[NT / 64];
   const uint64_t n = n_records(hdr, cap);
   uint64_t t;
@@ -376,14 +376,14 @@ __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __r
 template <int NT>
 __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __restrict__ src,
                                                      const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
-                                                     uint32_t nc, uint64_t nt, const uint32_t* __restrict__ offs1,
+                                                     uint32_t nc, uint64_t nt, const uint64_t* __restrict__ offs1,
                                                      const uint32_t* __restrict__ tb,
-                                                     const uint32_t* __restrict__ offs2, UDiv span,
+                                                     const uint64_t* __restrict__ offs2, UDiv span,
                                                      unsigned long long* __restrict__ dst, uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;
-  uint32_t* run = reinterpret_cast<uint32_t*>(smem64 + sub);
-  uint32_t* pre = run + fpc;
+  uint64_t* run = reinterpret_cast<uint64_t*>(smem64 + sub);
+  uint32_t* pre = reinterpret_cast<uint32_t*>(run + fpc);
   __shared__ uint32_t part[NT / 64];
   uint64_t g;
   uint32_t c, k;
@@ -551,9 +551,9 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
     return o;
   };
   J.hdr = take(64);
-  J.counts = take(4 * nb1 * J.n_tiles);
+  J.counts = take(8 * nb1 * J.n_tiles);
   J.tb = take(4 * (J.nc + 1));
-  J.counts2 = take(J.two_level ? 4 * (J.n_tiles + J.nc + 1) * J.fpc : 0);
+  J.counts2 = take(J.two_level ? 8 * (J.n_tiles + J.nc + 1) * J.fpc : 0);
   J.prefix = take(8 * (kScanBlocks + 1));
   J.parts = take(4 * (nb_all + 1));
   J.recA = take(8 * capacity);
@@ -564,12 +564,12 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
 
 namespace {
 
-__global__ void k_fill_u32(uint32_t* p, uint64_t n) {
+__global__ void k_fill_u64(uint64_t* p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+    p[i] = 0ull;
 }
 
-void scan_u32(uint32_t* v, uint64_t n, unsigned long long* bsum, hipStream_t s) {
+void scan_u64(uint64_t* v, uint64_t n, unsigned long long* bsum, hipStream_t s) {
   k_scan_sums<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
   k_scan_top<<<1, 64, 0, s>>>(bsum);
   k_scan_apply<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
@@ -583,8 +583,8 @@ void scan_u32(uint32_t* v, uint64_t n, unsigned long long* bsum, hipStream_t s) 
 template <typename L>
 void scatter_launch(uint64_t nb, L launch) {
   uint32_t sub = 16384;
-  while (sub > 1024 && (size_t)sub * 8 + 8 * nb + 256 > 160 * 1024) sub >>= 1;
-  launch(sub, (size_t)sub * 8 + 8 * nb);
+  while (sub > 1024 && (size_t)sub * 8 + 12 * nb + 256 > 160 * 1024) sub >>= 1;
+  launch(sub, (size_t)sub * 8 + 12 * nb);
 }
 
 }  // namespace
@@ -594,9 +594,9 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
   const JrecLayout J = jrec_layout(n_slots, o.jrec_capacity);
   unsigned char* ws = static_cast<unsigned char*>(o.jrec_ws);
   auto* hdr = reinterpret_cast<unsigned long long*>(ws + J.hdr);
-  auto* counts = reinterpret_cast<uint32_t*>(ws + J.counts);
+  auto* counts = reinterpret_cast<uint64_t*>(ws + J.counts);
   auto* tb = reinterpret_cast<uint32_t*>(ws + J.tb);
-  auto* counts2 = reinterpret_cast<uint32_t*>(ws + J.counts2);
+  auto* counts2 = reinterpret_cast<uint64_t*>(ws + J.counts2);
   auto* bsum = reinterpret_cast<unsigned long long*>(ws + J.prefix);
   auto* parts = reinterpret_cast<uint32_t*>(ws + J.parts);
   auto* recA = reinterpret_cast<unsigned long long*>(ws + J.recA);
@@ -608,7 +608,7 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
   // level 1 (the whole partition for one level): recA -> recB
   const unsigned grid1 = (unsigned)((nt + kXcds - 1) / kXcds * kXcds);     // whole rounds over the XCDs
   k_jr_count<<<grid1, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
-  scan_u32(counts, (uint64_t)nb1 * nt, bsum, s);
+  scan_u64(counts, (uint64_t)nb1 * nt, bsum, s);
   scatter_launch(nb1, [&](uint32_t sub, size_t lds) {
     k_jr_scatter<1024><<<grid1, 1024, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
   });
@@ -622,10 +622,10 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
     const uint64_t n2 = (nt + nc + 1) * fpc;
     const unsigned grid2 = (unsigned)((nt + nc + kXcds - 1) / kXcds * kXcds);  // >= level-2 tiles
     k_jr_dir<<<1, 1024, 0, s>>>(counts, hdr, cap, nc, nt, tb);
-    k_fill_u32<<<256, 256, 0, s>>>(counts2, n2);
+    k_fill_u64<<<256, 256, 0, s>>>(counts2, n2);
     const UDiv span2 = make_udiv((uint32_t)kBucketSlots);
     k_jr_count2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, span2, counts2);
-    scan_u32(counts2, n2, bsum, s);
+    scan_u64(counts2, n2, bsum, s);
     scatter_launch(fpc, [&](uint32_t sub, size_t lds) {
       k_jr_scatter2<1024><<<grid2, 1024, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, span2, recA, sub);
     });
@@ -642,7 +642,7 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t*
 extern "C" int32_t mcrt_jrec_ws_bytes(const mcrt_ctx* ctx, uint64_t capacity, uint64_t* bytes) {
   if (!ctx || !bytes) return MCRT_E_INVALID;
   const uint64_t n_slots = (uint64_t)ctx->d.n_lambda * (uint64_t)ctx->d.n_cells;
-  if (capacity < mcrt::kRecChunk || capacity > (1ull << 31)) return MCRT_E_INVALID;
+  if (capacity < mcrt::kRecChunk || capacity > mcrt::kMaxRecords) return MCRT_E_INVALID;
   if (ctx->d.max_level > 7 || n_slots >= (1ull << 40)) return MCRT_E_UNSUPPORTED;
   const mcrt::JrecLayout J = mcrt::jrec_layout(n_slots, capacity);
   const uint64_t nb1 = J.two_level ? J.nc : J.n_buckets;

@@ -792,7 +792,15 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   uint64_t blocks = o.grid_blocks > 0 ? (uint64_t)o.grid_blocks : (uint64_t)c->n_cu * per_cu;
   if (blocks > want) blocks = want;
   if (blocks < 1) blocks = 1;
+  if (o.kernel_begin) {
+    const hipError_t e = hipEventRecord(o.kernel_begin, s);
+    if (e != hipSuccess) return e;
+  }
   kern<<<(unsigned)blocks, 256, lds, s>>>(P);
+  if (o.kernel_end) {
+    const hipError_t e = hipEventRecord(o.kernel_end, s);
+    if (e != hipSuccess) return e;
+  }
   if (peel) k_peel<R><<<(unsigned)(c->n_cu * 4), 256, 0, s>>>(P);
   if (defer) {
     const hipError_t e = launch_jrec_accumulate(c, o, t.jq, s);

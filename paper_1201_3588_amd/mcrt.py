@@ -61,7 +61,8 @@ class RunOpts(C.Structure):
                 ("frozen_nabs", _dp), ("pah_rows", _dp), ("trace", _dp), ("trace_len", _dp),
                 ("trace_cap", C.c_int32), ("pad", C.c_int32),
                 ("peel_queue", _dp), ("peel_capacity", C.c_uint64),
-                ("jrec_ws", _dp), ("jrec_capacity", C.c_uint64)]
+                ("jrec_ws", _dp), ("jrec_capacity", C.c_uint64),
+                ("kernel_begin", C.c_void_p), ("kernel_end", C.c_void_p)]
 
 
 class TableLayout(C.Structure):
@@ -299,8 +300,8 @@ class Engine:
         """Path-length tally through a record workspace of `capacity` segment
         records (mcrt_jrec_ws_bytes) instead of per-segment atomics; 0 turns
         it off.  Returns False when the grid does not support it."""
+        self._jrec = None                  # release the old workspace before sizing a new one
         if not capacity:
-            self._jrec = None
             return True
         nbytes = C.c_uint64(0)
         rc = lib().mcrt_jrec_ws_bytes(self.ctx, int(capacity), C.byref(nbytes))
@@ -312,7 +313,9 @@ class Engine:
         return True
 
     def run(self, tallies, first_id, n, n_total, seed, max_events=1_000_000, flags=None,
-            frozen_nabs=None, pah_rows=None, trace_cap=0, grid_blocks=0):
+            frozen_nabs=None, pah_rows=None, trace_cap=0, grid_blocks=0, kernel_events=None):
+        """kernel_events: optional pair of recorded torch.cuda.Events that the
+        library records again right around the transport kernel itself."""
         if flags is None:
             flags = FLAG_TALLY_J if tallies.get("jq") is not None else 0
         t = Tallies(_ptr(tallies["nabs"]), _ptr(tallies["sed"]), _ptr(tallies.get("jq")),
@@ -323,6 +326,10 @@ class Engine:
         if getattr(self, "peel_on", False) and tallies.get("peel") is not None:
             o.flags |= FLAG_PEEL
             o.peel_queue, o.peel_capacity = _ptr(self._peel_q), self.peel_capacity
+        if kernel_events is not None:
+            if not (kernel_events[0].cuda_event and kernel_events[1].cuda_event):
+                raise MCRTError(-1, "kernel_events must have been recorded once (created)")
+            o.kernel_begin, o.kernel_end = kernel_events[0].cuda_event, kernel_events[1].cuda_event
         jrec = getattr(self, "_jrec", None)
         if jrec is not None and (o.flags & FLAG_TALLY_J) and tallies.get("jq") is not None:
             o.jrec_ws, o.jrec_capacity = _ptr(jrec[0]), jrec[1]

@@ -151,7 +151,9 @@ def test_deferred_tally_workspace_codes():
     assert L.mcrt_ctx_create(C.byref(good_desc()), C.byref(ctx)) == 0
     try:
         assert L.mcrt_jrec_ws_bytes(ctx, 100, C.byref(nbytes)) == -1           # below one chunk
-        assert L.mcrt_jrec_ws_bytes(ctx, (1 << 31) + 1, C.byref(nbytes)) == -1
+        assert L.mcrt_jrec_ws_bytes(ctx, (1 << 35) + 1, C.byref(nbytes)) == -1
+        assert L.mcrt_jrec_ws_bytes(ctx, (1 << 33) + 4096, C.byref(nbytes)) == 0       # 64-bit offsets
+        assert nbytes.value >= 16 * ((1 << 33) + 4096)
         assert L.mcrt_jrec_ws_bytes(ctx, 1 << 20, None) == -1
         assert L.mcrt_jrec_ws_bytes(ctx, 1 << 20, C.byref(nbytes)) == 0
         small = nbytes.value

@@ -1,0 +1,157 @@
+"""Parity at the size of the benchmark's headline workload: the gap + spiral
+disk with PAHs on a 256^3 base grid (depth 3, 16,784,776 leaves, 26 species of
+which two PAHs, 200 wavelengths, 1e9 packets), in the launch configuration the
+benchmark times: PAH re-emission rows from the optically thin field (the exact
+solver, chunked over the cells), then one transport pass with the path-length
+tally deferred to records in id ranges sized to the workspace.  The oracle
+checks sampled outputs one by one:
+  * exact integer bookkeeping of the full pass;
+  * with a frozen absorption field (an oracle run of 1e5 packets, scaled to
+    the pass) and seeded stand-in PAH rows on both sides (the oracle reads them
+    from a compact table through a per-cell row index), sampled packet ids
+    anywhere in [0, 1e9) retrace the oracle's histories, PAH re-emission
+    included;
+  * temperatures of sampled cells of a seeded absorption field;
+  * with the frozen field, one id range of more than 2^32 segment records (64-bit
+    workspace offsets) gives the same tallies through records as through
+    per-segment atomics, bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+mcrt = pytest.importorskip("paper_1201_3588_amd.mcrt")
+
+from test_gpu_transport import _compare_traces, conservation, host  # noqa: E402
+
+GB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def c5():
+    from paper_1201_3588_amd.pah import PahSolver
+    w = synth.c5_full()
+    N, nc, nl = w.n_packets, w.grid.n_cells, w.species.n_lambda
+    eng = mcrt.Engine.from_workload(w)
+    eng.build_tables(w.source.pos, w.source.lum, w.source.teff)
+    solvers = [PahSolver.from_model(pm) for pm in w.pah]
+    rows = torch.empty((len(solvers), nc, nl), dtype=torch.float64, device="cuda")
+    J0 = eng.thin_field()
+    for p, s in enumerate(solvers):
+        for a in range(0, nc, 1 << 22):
+            b = min(nc, a + (1 << 22))
+            out = s.solve(J0[a:b])[0]
+            s.rows(out, rows=rows[p, a:b])
+            del out
+    del J0
+    tal = eng.new_tallies(tally_j=True)
+    cap = 6_000_000_000 // 4096 * 4096                # 96 GB of records, as the benchmark sizes it
+    assert eng.set_deferred_tally(cap)
+    eng.run_batched(tal, 0, N, N, w.seed, cap // 300, pah_rows=rows)
+    T = eng.temperatures(tal["nabs"], N)
+    torch.cuda.synchronize()
+    r = {k: mcrt.u64_view(tal[k]) for k in ("nabs", "sed", "counters")}
+    T_ok = bool(torch.isfinite(T).all().item())
+    del tal, T
+    return dict(w=w, eng=eng, rows=rows, r=r, T_ok=T_ok, cap=cap)
+
+
+def test_c5_bookkeeping(c5):
+    w, r = c5["w"], c5["r"]
+    conservation(r, w.n_packets)
+    c = r["counters"]
+    assert c[2] == 0                                  # nothing hit the event cap
+    assert c[9] > 1e7                                 # PAH absorptions re-emitted from the rows
+    assert c[6] > 1e11 and c[11] > 1e11               # crossings, path-tally segments
+    assert int(r["sed"].reshape(10, 8, -1).sum(axis=(0, 2)).min()) > 1e7   # every azimuth bin
+    assert c5["T_ok"]
+
+
+def stand_in_rows(w, c5):
+    """Seeded stand-in PAH rows: a compact table of 4096 CDF rows and a row
+    index per (PAH species, cell); the GPU gets the dense rows it stands for."""
+    nc, nl = w.grid.n_cells, w.species.n_lambda
+    n_pah = int((w.species.kind == 1).sum())
+    table = synth.pah_test_rows(1, 4096, nl, seed=31)[0]
+    rmap = np.random.default_rng(8).integers(0, 4096, n_pah * nc).astype(np.int32)
+    dense = c5["rows"]
+    tdev = torch.as_tensor(table).cuda()
+    mdev = torch.as_tensor(rmap).cuda().long()
+    for p in range(n_pah):
+        torch.index_select(tdev, 0, mdev[p * nc:(p + 1) * nc], out=dense[p])
+    return table, rmap
+
+
+def frozen_field(w, table, rmap):
+    """Absorption counts of an oracle run of 1e5 packets (running counts,
+    stand-in rows), scaled by 1e4 to the size of the 1e9-packet pass."""
+    s = oracle.Session(w, n_threads=8, flags=0, pah_rows=table, pah_row_map=rmap)
+    nabs = s.transport(n=100_000)["nabs"]
+    return nabs * np.uint64(10_000)
+
+
+def test_c5_sampled_packets_retrace_oracle(c5):
+    w, eng = c5["w"], c5["eng"]
+    table, rmap = stand_in_rows(w, c5)
+    frozen = frozen_field(w, table, rmap)
+    c5["frozen"] = frozen
+    frozen_dev = torch.as_tensor(frozen.reshape(-1).view(np.int64)).cuda()
+    s = oracle.Session(w, frozen_nabs=frozen, flags=oracle.FLAG_FROZEN_T, pah_rows=table, pah_row_map=rmap)
+    ids = np.linspace(0, w.n_packets - 1, 64).astype(np.int64)
+    same = pah_seen = 0
+    grazing, parted = [], []
+    for pid in ids:
+        tal = eng.new_tallies(tally_j=False)
+        gt = eng.run(tal, int(pid), 1, w.n_packets, w.seed, frozen_nabs=frozen_dev, trace_cap=1500,
+                     pah_rows=c5["rows"], flags=mcrt.FLAG_FROZEN_T)
+        ot = s.transport(int(pid), 1, trace_cap=1500)["trace"]
+        same += _compare_traces(gt, ot, 1e-5, float(w.grid.nb), grazing, parted)
+        pah_seen += int(mcrt.u64_view(tal["counters"])[9])
+        del tal
+    assert same >= 0.9 * len(ids), (same, parted)
+    assert len(grazing) <= 0.03 * len(ids), grazing
+    assert pah_seen > 0
+
+
+def test_c5_sampled_temperatures(c5):
+    w, eng = c5["w"], c5["eng"]
+    S = w.species.n_species
+    rng = np.random.default_rng(12)
+    pick = rng.choice(w.grid.n_cells, 300, replace=False)
+    pick = pick[w.grid.rho[pick] > 0][:200]
+    nabs = np.zeros((w.grid.n_cells, S), np.uint64)
+    nabs[pick] = rng.integers(0, 200_000, (len(pick), S)).astype(np.uint64)
+    Tg = eng.temperatures(torch.as_tensor(nabs.reshape(-1).view(np.int64)).cuda(), w.n_packets).cpu().numpy()
+    To = oracle.Session(w, n_threads=8, flags=0).temperatures(nabs)
+    eq = w.species.kind == 0
+    assert np.allclose(Tg.reshape(-1, S)[pick][:, eq], To[pick][:, eq], rtol=1e-11, atol=0)
+    assert np.all(Tg.reshape(-1, S)[pick][:, eq] > w.T_lo)
+
+
+def test_c5_deferred_tally_beyond_2_32_records_equals_atomic(c5):
+    # one id range whose segment records number more than 2^32: the
+    # workspace's offsets are 64-bit; the tally equals the per-segment atomic
+    # one bit for bit (compared on the device)
+    w, eng = c5["w"], c5["eng"]
+    if "frozen" not in c5:
+        c5["frozen"] = frozen_field(w, *stand_in_rows(w, c5))
+    frozen = torch.as_tensor(c5["frozen"].reshape(-1).view(np.int64)).cuda()
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    n = 22_000_000
+    out = {}
+    for mode in ("deferred", "atomic"):          # the engine holds the fixture's workspace
+        if mode == "atomic":
+            eng.set_deferred_tally(0)
+        tal = eng.new_tallies(tally_j=True)
+        eng.run(tal, 300_000_000, n, w.n_packets, w.seed, frozen_nabs=frozen, pah_rows=c5["rows"], flags=flags)
+        torch.cuda.synchronize()
+        out[mode] = tal
+    a, b = out["atomic"], out["deferred"]
+    jseg = int(mcrt.u64_view(a["counters"])[mcrt.CNT["jseg"]])
+    assert (1 << 32) < jseg < c5["cap"], jseg
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert torch.equal(a[k], b[k]), k

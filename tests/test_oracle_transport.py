@@ -198,3 +198,18 @@ def test_optically_thin_gray_temperature():
         assert abs(T[c] / Tref - 1) < 4.5 / (4 * math.sqrt(N[c])) + 5e-3
         checked += 1
     assert checked >= 8
+
+
+def test_pah_row_map_equals_dense_rows():
+    # a compact table of rows indexed per (PAH slot, cell) gives the same
+    # histories as the dense [n_pah][n_cells][nl] layout it stands for
+    w = synth.small_disk(n_packets=3000, nl=24, n_sizes=1, nb=8, with_pah=True)
+    n_pah = int((w.species.kind == 1).sum())
+    table = synth.pah_test_rows(1, 37, w.species.n_lambda, seed=5)[0]
+    rmap = np.random.default_rng(2).integers(0, 37, n_pah * w.grid.n_cells).astype(np.int32)
+    dense = table[rmap].reshape(n_pah, w.grid.n_cells, w.species.n_lambda)
+    a = oracle.Session(w, pah_rows=dense).transport()
+    b = oracle.Session(w, pah_rows=table, pah_row_map=rmap).transport()
+    assert int(a["counters"][oracle.CNT["pah_abs"]]) > 50
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
