@@ -43,6 +43,27 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_transport_gap_spiral_256_pmc.md")
+TRAFFIC_SOURCES = ("mcrt_transport.hip", "mcrt_internal.h")
+
+
+def committed_traffic():
+    """HBM bytes per packet of k_transport from the committed counter summary,
+    if it was taken on the current source of that kernel; else None."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, "paper_1201_3588_amd", "csrc", f), "rb").read())
+        kv = dict(l.strip().split(": ", 1) for l in open(TRAFFIC_FILE)
+                  if l.startswith(("traffic_bytes_per_packet:", "source_sha256:")))
+        if kv.get("source_sha256") == h.hexdigest():
+            return float(kv["traffic_bytes_per_packet"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def random_atomic_rate(n_slots, stream):
     """Achievable rate of random 64-bit atomic adds over a table of n_slots
     words (the size of the path-length tally), measured with HIP events."""
@@ -523,6 +544,67 @@ class C5Run:
                             "(disjoint slices of one permutation) and 5e4 synthetic fields of another seed"}
 
 
+def pah_kernel_rooflines(R, J, stream):
+    """The PAH step's kernels on their own, against their rooflines:
+    the fused surrogate inference (k_mlp_infer) on 4,194,304 cells of the
+    field, the exact solver (k_pah_solve) on 262,144 of them, and surrogate
+    training (forward + backward + Adam, batch 2048) on a fresh network."""
+    import torch
+    from paper_1201_3588_amd.surrogate import Surrogate
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    sur, s = R.surs[0], R.solvers[0]
+    Jc = J[: 1 << 22].contiguous()
+    n = Jc.shape[0]
+    sur.predict(Jc[:65536])
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    sur.predict(Jc)
+    e1.record(stream)
+    Jx = Jc[: 1 << 18]
+    s.solve(Jx[:4096])
+    x0, x1 = ev(), ev()
+    x0.record(stream)
+    s.solve(Jx)
+    x1.record(stream)
+    # training throughput on a throwaway network (its normalisation is refitted)
+    t = Surrogate(s, batch=2048, seed=9)
+    nt = 2048 * 64
+    out, pabs = t.exact(Jc[:nt])
+    X, Y = t.net.prepare(s, Jc[:nt], out, pabs)
+    for k in range(4):
+        t.net.train_step(X[k * 2048:(k + 1) * 2048], Y[k * 2048:(k + 1) * 2048], 1e-3, k + 1)
+    steps = 60
+    t0, t1 = ev(), ev()
+    t0.record(stream)
+    for k in range(steps):
+        a = (k % 64) * 2048
+        t.net.train_step(X[a:a + 2048], Y[a:a + 2048], 1e-3, k + 5)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ti, tx, tt = e0.elapsed_time(e1) / 1e3, x0.elapsed_time(x1) / 1e3, t0.elapsed_time(t1) / 1e3
+    ni, nh, no = s.n_lambda + 1, 256, s.n_out
+    fl_inf = 2 * (ni * nh + nh * nh + nh * no)
+    fl_train = 3 * fl_inf - 2 * ni * nh                  # forward, backward (no input gradient)
+    by_inf = 4 * s.n_lambda + 8 * no + 8 + 1             # J in (FP32); outputs, P_abs out (FP64); flag
+    inf_rate = n / ti
+    inf_roof = min(2.5e15 / fl_inf, 8e12 / by_inf)
+    ex_rate = Jx.shape[0] / tx
+    fl_ex = 0.35e6
+    tr_rate = steps * 2048 / tt
+    return {
+        "k_mlp_infer": {"cells": n, "ms": ti * 1e3, "cells_per_s": inf_rate, "flop_per_cell": fl_inf,
+                        "hbm_bytes_per_cell": by_inf, "roofline_cells_per_s": inf_roof, "frac": inf_rate / inf_roof,
+                        "bound": "hbm" if 8e12 / by_inf < 2.5e15 / fl_inf else "mfma",
+                        "peaks": "BF16 dense MFMA 2.5 PFLOP/s, HBM 8 TB/s"},
+        "k_pah_solve": {"cells": int(Jx.shape[0]), "ms": tx * 1e3, "cells_per_s": ex_rate, "flop_per_cell": fl_ex,
+                        "achieved_tflops": ex_rate * fl_ex / 1e12, "peak_tflops": 78.6,
+                        "frac": ex_rate * fl_ex / 78.6e12, "bound": "fp64"},
+        "training": {"batch": 2048, "steps": steps, "ms_per_step": tt / steps * 1e3, "samples_per_s": tr_rate,
+                     "flop_per_sample": fl_train, "achieved_tflops": tr_rate * fl_train / 1e12,
+                     "peak_tflops": 2500.0, "frac": tr_rate * fl_train / 2.5e15, "bound": "mfma"},
+    }
+
+
 def cpu_baseline_c5(w, n_s):
     """The oracle (FP64 C, threaded over the host cores) on the first n_s
     packet ids of the headline workload, path-length tally on, running
@@ -571,6 +653,11 @@ def main():
     ap.add_argument("--extra", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the smaller disks, the re-emission law comparison and the Fig. 3 set-up")
     ap.add_argument("--c3-iterate", action=argparse.BooleanOptionalAction, default=True)
+    ap.add_argument("--pah-kernels", action=argparse.BooleanOptionalAction, default=True,
+                    help="time the PAH step's kernels alone against their rooflines")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one elementwise copy of 256 MiB (read) -> 256 MiB (write) first, "
+                         "the reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
@@ -583,6 +670,12 @@ def main():
     import synth
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     R = C5Run(args, stream)
     N = R.N
     # pass 0 from the optically thin starlight field, exact PAH emission
@@ -597,6 +690,7 @@ def main():
     log(f"pass 0 (exact PAH emission) in {time.perf_counter() - t0:.1f} s")
     training = R.train(J)
     log(f"surrogates trained in {training['setup_s']:.1f} s")
+    pah_roof = pah_kernel_rooflines(R, J, stream) if args.pah_kernels else None
     plain = None
     if args.plain:
         # one pass in the plain form (exact solver for every PAH cell), same field
@@ -637,6 +731,8 @@ def main():
     alg_launch = alg_pass / n_launch
     achieved = alg_launch / k_avg / 1e9
     n_pah_cells = len(R.solvers) * R.nc
+    per_packet = committed_traffic()
+    traffic = per_packet * N / n_launch if per_packet is not None else None
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,
@@ -672,11 +768,12 @@ def main():
                 "surrogate_training": training,
                 "iteration_band_power_change_per_step": changes,
                 "pass_plain_s": plain["pass_ms"] / 1e3 if plain else None,
-                "pass_surrogate_s": wall / args.steps},
+                "pass_surrogate_s": wall / args.steps,
+                "kernels": pah_roof},
         "pass0": {"pass_ms": p0["pass_ms"], "pah_exact_ms": p0["pah_ms"], "transport_ms": p0["transport_ms"]},
         "synth_build_s": R.synth_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_transport<float,false,false,true>",
                      "launches_per_step": n_launch, "avg_launch_ms": k_avg * 1e3,
                      "alg_bytes_per_launch": alg_launch,

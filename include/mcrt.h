@@ -62,6 +62,10 @@ extern "C" {
 #define MCRT_FLAG_EXACT_BW 8
 /* Next-event (peel-off) images for the observers; see mcrt_run_opts.peel_queue. */
 #define MCRT_FLAG_PEEL 16
+/* With MCRT_FLAG_PEEL: also each observer's next-event SED over every bin
+ * (tallies->peel_sed); every emission and scattering is queued, not only
+ * those in imaged bins. */
+#define MCRT_FLAG_PEEL_SED 32
 
 /* counter slots of mcrt_tallies.counters */
 #define MCRT_CNT_LAUNCHED 0
@@ -137,6 +141,9 @@ typedef struct {
   uint64_t *peel;              /* [n_obs][n_img_lambda][npix][npix] next-event
                                   weights in units of 2^-24 (MCRT_FLAG_PEEL);
                                   NULL when the flag is off */
+  uint64_t *peel_sed;          /* [n_obs][n_lambda] next-event SED: the same
+                                  weights of every event in bin j, wherever it
+                                  projects (MCRT_FLAG_PEEL_SED); NULL when off */
 } mcrt_tallies;
 
 /* Escape images (paper Sec. 2, Fig. 2: the model seen from chosen
@@ -175,7 +182,10 @@ typedef struct {
  * line of sight, at the pixel of the event's projection on the image plane
  * (the escape images' axes and pixels).  Each weight w is added as
  * round-to-nearest(2^24 w) to tallies->peel; a pixel's flux at distance D is
- * eps / (4 pi D^2) 2^-24 times its sum (erg s^-1 cm^-2 in its bin).  The
+ * eps / (4 pi D^2) 2^-24 times its sum (erg s^-1 cm^-2 in its bin).  With
+ * MCRT_FLAG_PEEL_SED the same rounded weight of every event, in any bin, is
+ * also added to tallies->peel_sed[o][j] (the observer's SED, paper Sec. 2 and
+ * Fig. 1: the flux towards that direction per bin, same scale).  The
  * transport stores one MCRT_PEEL_REC_BYTES record per such event in
  * opts->peel_queue (device, caller-owned, peel_capacity records); a second
  * kernel on the same stream then marches every record's lines of sight.

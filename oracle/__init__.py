@@ -22,7 +22,7 @@ _lib = None
 
 CNT = dict(launched=0, escaped=1, killed=2, terminated=3, scatters=4, absorptions=5,
            crossings=6, tclamp_lo=7, tclamp_hi=8, pah_abs=9, zero_cross=10, jseg=11, peel=12)
-FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW, FLAG_PEEL = 1, 2, 4, 8, 16
+FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW, FLAG_PEEL, FLAG_PEEL_SED = 1, 2, 4, 8, 16, 32
 PEEL_ONE = 1 << 24                     # fixed-point unit of the next-event images
 EV_LAUNCH, EV_CROSS, EV_SCATTER, EV_ABSORB, EV_ESCAPE, EV_KILLED = range(6)
 
@@ -77,7 +77,7 @@ class Tables(C.Structure):
 class Out(C.Structure):
     _fields_ = [("nabs", _u64p), ("sed", _u64p), ("jq", _u64p), ("counters", _u64p), ("image", _u64p),
                 ("trace", C.c_void_p), ("trace_len", _i32p), ("trace_cap", C.c_int64),
-                ("peel", _u64p)]
+                ("peel", _u64p), ("peel_sed", _u64p)]
 
 
 def lib():
@@ -227,8 +227,9 @@ class Session:
         cnt = np.zeros(16, np.uint64)
         img = np.zeros(p.n_obs * p.n_img_lambda * p.npix * p.npix, np.uint64) if p.n_obs > 0 else None
         peel = np.zeros_like(img) if (img is not None and p.flags & FLAG_PEEL) else None
+        psed = np.zeros(p.n_obs * p.nl, np.uint64) if (peel is not None and p.flags & FLAG_PEEL_SED) else None
         o = Out(nabs=_p(nabs, _u64p), sed=_p(sed, _u64p), jq=_p(jq, _u64p), counters=_p(cnt, _u64p),
-                image=_p(img, _u64p), peel=_p(peel, _u64p))
+                image=_p(img, _u64p), peel=_p(peel, _u64p), peel_sed=_p(psed, _u64p))
         tr = tl = None
         if trace_cap > 0:
             tr = np.zeros(n * trace_cap, TRACE_DTYPE)
@@ -243,7 +244,8 @@ class Session:
                    sed=sed.reshape(p.n_theta, p.n_phi, p.nl), counters=cnt,
                    jq=jq.reshape(p.nl, p.n_cells) if jq is not None else None,
                    image=img.reshape(p.n_obs, p.n_img_lambda, p.npix, p.npix) if img is not None else None,
-                   peel=peel.reshape(p.n_obs, p.n_img_lambda, p.npix, p.npix) if peel is not None else None)
+                   peel=peel.reshape(p.n_obs, p.n_img_lambda, p.npix, p.npix) if peel is not None else None,
+                   peel_sed=psed.reshape(p.n_obs, p.nl) if psed is not None else None)
         if tr is not None:
             res["trace"] = [tr[k * trace_cap:k * trace_cap + tl[k]] for k in range(n)]
         return res
@@ -253,7 +255,8 @@ class Session:
         nabs, sed, jq, counters as made by new_accumulator)."""
         o = Out(nabs=_p(acc["nabs"], _u64p), sed=_p(acc["sed"], _u64p),
                 jq=_p(acc.get("jq"), _u64p), counters=_p(acc["counters"], _u64p),
-                image=_p(acc.get("image"), _u64p), peel=_p(acc.get("peel"), _u64p))
+                image=_p(acc.get("image"), _u64p), peel=_p(acc.get("peel"), _u64p),
+                peel_sed=_p(acc.get("peel_sed"), _u64p))
         rc = lib().orc_transport(C.byref(self.p), C.byref(self._T), first_id, n, C.byref(o))
         if rc != 0:
             raise RuntimeError(f"orc_transport failed: {rc}")
@@ -267,7 +270,9 @@ class Session:
                     counters=np.zeros(16, np.uint64),
                     image=np.zeros(p.n_obs * p.n_img_lambda * p.npix * p.npix, np.uint64) if p.n_obs else None,
                     peel=np.zeros(p.n_obs * p.n_img_lambda * p.npix * p.npix, np.uint64)
-                    if (p.n_obs and p.flags & FLAG_PEEL) else None)
+                    if (p.n_obs and p.flags & FLAG_PEEL) else None,
+                    peel_sed=np.zeros(p.n_obs * p.nl, np.uint64)
+                    if (p.n_obs and p.flags & FLAG_PEEL and p.flags & FLAG_PEEL_SED) else None)
 
     def temperatures(self, nabs):
         p = self.p

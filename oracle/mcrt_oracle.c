@@ -337,9 +337,10 @@ static double peel_tau(const orc_problem *p, const orc_tables *t, const double x
 static void peel_tally(const orc_problem *p, const orc_tables *t, orc_out *o, const double x[3],
                        int cell, int lev, const int64_t lo[3], int j, const double *din, int thr) {
   if (!o->peel || !(p->flags & ORC_FLAG_PEEL) || p->n_obs <= 0 || cell < 0) return;
+  const int sed = (p->flags & ORC_FLAG_PEEL_SED) && o->peel_sed;
   int l = -1;
   for (int q = 0; q < p->n_img_lambda; ++q) if (p->img_lambda[q] == j) l = q;
-  if (l < 0) return;
+  if (l < 0 && !sed) return;
   add_u64(&o->counters[ORC_CNT_PEEL], 1, thr);
   double X[3];
   for (int a = 0; a < 3; ++a) X[a] = p->box_min[a] + x[a] * p->base_size - p->img_center[a];
@@ -358,11 +359,16 @@ static void peel_tally(const orc_problem *p, const orc_tables *t, orc_out *o, co
     const double cb = X[0] * e2[0] + X[1] * e2[1] + X[2] * e2[2];
     const double w = p->img_half_width;
     const double fx = floor((ca + w) / (2.0 * w) * p->npix), fy = floor((cb + w) / (2.0 * w) * p->npix);
-    if (fx < 0.0 || fy < 0.0 || fx >= p->npix || fy >= p->npix) continue;
+    const int in_img = l >= 0 && !(fx < 0.0 || fy < 0.0 || fx >= p->npix || fy >= p->npix);
+    if (!in_img && !sed) continue;
     const double phase = din ? hg_phase(p->g[j], din[0] * n[0] + din[1] * n[1] + din[2] * n[2]) : 1.0;
     const double wgt = phase * exp(-peel_tau(p, t, x, cell, lev, lo, j, n));
-    add_u64(&o->peel[(((int64_t)ob * p->n_img_lambda + l) * p->npix + (int64_t)fy) * p->npix + (int64_t)fx],
-            (uint64_t)rint(wgt * 16777216.0), thr);
+    const uint64_t q = (uint64_t)rint(wgt * 16777216.0);
+    if (in_img)
+      add_u64(&o->peel[(((int64_t)ob * p->n_img_lambda + l) * p->npix + (int64_t)fy) * p->npix + (int64_t)fx],
+              q, thr);
+    /* the observer's next-event SED: every bin, wherever the event projects */
+    if (sed) add_u64(&o->peel_sed[(int64_t)ob * p->nl + j], q, thr);
   }
 }
 

@@ -25,6 +25,7 @@
 #define ORC_FLAG_KILL_ON_ABSORB 4
 #define ORC_FLAG_EXACT_BW        8
 #define ORC_FLAG_PEEL           16
+#define ORC_FLAG_PEEL_SED       32   /* with PEEL: next-event SED per observer, every bin */
 
 enum {
   ORC_CNT_LAUNCHED = 0, ORC_CNT_ESCAPED, ORC_CNT_KILLED, ORC_CNT_TERMINATED,
@@ -100,6 +101,8 @@ typedef struct {
   int64_t trace_cap;
   uint64_t *peel;                  /* [n_obs*n_img_lambda*npix*npix] next-event
                                       weights, fixed point 2^-24, or NULL */
+  uint64_t *peel_sed;              /* [n_obs*nl] next-event SED per observer
+                                      (ORC_FLAG_PEEL_SED), fixed point 2^-24, or NULL */
 } orc_out;
 
 #ifdef __cplusplus

@@ -204,10 +204,14 @@ int32_t mcrt_run(mcrt_ctx* ctx, uint64_t first_id, uint64_t n_packets, const mcr
     return fail(ctx, MCRT_E_INVALID, "TALLY_J needs tallies->jq");
   if ((opts->flags & MCRT_FLAG_FROZEN_T) && !opts->frozen_nabs)
     return fail(ctx, MCRT_E_INVALID, "FROZEN_T needs frozen_nabs");
-  if (opts->flags & ~31) return fail(ctx, MCRT_E_INVALID, "unknown flag bits");
+  if (opts->flags & ~63) return fail(ctx, MCRT_E_INVALID, "unknown flag bits");
+  if ((opts->flags & MCRT_FLAG_PEEL_SED) && !(opts->flags & MCRT_FLAG_PEEL))
+    return fail(ctx, MCRT_E_INVALID, "PEEL_SED needs PEEL");
   if (opts->flags & MCRT_FLAG_PEEL) {
     if (ctx->img.n_obs == 0) return fail(ctx, MCRT_E_INVALID, "PEEL needs observers");
     if (!tallies->peel) return fail(ctx, MCRT_E_INVALID, "PEEL needs tallies->peel");
+    if ((opts->flags & MCRT_FLAG_PEEL_SED) && !tallies->peel_sed)
+      return fail(ctx, MCRT_E_INVALID, "PEEL_SED needs tallies->peel_sed");
     if (!opts->peel_queue || opts->peel_capacity < 1)
       return fail(ctx, MCRT_E_INVALID, "PEEL needs peel_queue and peel_capacity >= 1");
   }

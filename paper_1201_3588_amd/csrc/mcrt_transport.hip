@@ -60,6 +60,7 @@ struct TP {
   const int8_t* level;
   const int4* leaf_lo;
   unsigned long long* peel;
+  unsigned long long* peel_sed;     // [n_obs][nl] or null: every event is queued
   // deferred path tally: record buffer, its capacity and fill counter
   unsigned long long* jrec;
   uint64_t jrec_cap;
@@ -204,12 +205,12 @@ __device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1
 }
 
 // Queues a next-event record when bin j is imaged (rare: a few imaged bins
-// out of the whole grid); records past the capacity are dropped and counted
-// by the march kernel.
+// out of the whole grid), or for every event when the observers' SEDs are
+// on; records past the capacity are dropped and counted by the march kernel.
 template <typename R>
 __device__ __forceinline__ void peel_push(const TP<R>& P, double x0, double x1, double x2, int cell, int j,
                                        int type, R d0, R d1, R d2) {
-  bool imaged = false;
+  bool imaged = P.peel_sed != nullptr;
   for (int q = 0; q < P.img.n_l; ++q) imaged |= P.img.lsel[q] == j;
   if (!imaged) return;
   const unsigned long long k = atomicAdd(P.peel_count, 1ull);
@@ -218,6 +219,55 @@ __device__ __forceinline__ void peel_push(const TP<R>& P, double x0, double x1, 
   r->x[0] = x0; r->x[1] = x1; r->x[2] = x2;
   r->din[0] = (double)d0; r->din[1] = (double)d1; r->din[2] = (double)d2;
   r->cell = cell; r->j = j; r->type = type; r->pad = 0;
+}
+
+// Deferred path tally: records staged per wave in LDS (kStage per wave)
+// and copied to the wave's chunk of the record buffer in bulk.
+constexpr uint32_t kStage = 512;
+
+// Copies the wave's n staged records to the record buffer: contiguous
+// positions in the wave's current chunk [rcur, rcur + rleft), claiming
+// chunks of kRecChunk records as needed; once the buffer is exhausted (rfull)
+// the records go to the tally by atomic add (the tally is the same).  Every
+// lane of the wave calls it with the same (wave-uniform) arguments.
+template <typename R>
+__device__ __forceinline__ void flush_records(const TP<R>& P, const unsigned long long* rec, uint32_t n,
+                                              uint64_t& rcur, uint64_t& rleft, bool& rfull) {
+  const int lane = __lane_id();
+  uint32_t done = 0;
+  while (done < n) {
+    if (!rfull && rleft == 0) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(P.jrec_count, (unsigned long long)kRecChunk);
+      base = __shfl(base, 0);
+      if (base + kRecChunk <= P.jrec_cap) {
+        rcur = base;
+        rleft = kRecChunk;
+      } else {
+        // buffer exhausted: neutral records (slot 0, length 0) over the part
+        // of this chunk inside the buffer; direct adds from now on
+        for (uint64_t q = base + (uint64_t)lane; q < P.jrec_cap && q < base + kRecChunk; q += 64)
+          __builtin_nontemporal_store(0ull, &P.jrec[q]);
+        rfull = true;
+      }
+    }
+    if (rfull) {
+      for (uint32_t q = done + (uint32_t)lane; q < n; q += 64) {
+        const unsigned long long r = rec[q];
+        atomicAdd(&P.jq[r >> kRecValBits], r & ((1ull << kRecValBits) - 1ull));
+      }
+      return;
+    }
+    const uint32_t take = (uint64_t)(n - done) < rleft ? n - done : (uint32_t)rleft;
+    // records are written once and read back by the next kernels:
+    // non-temporal, so they stream past the L2 lines of the grid and tables
+    // that the march gathers from
+    for (uint32_t q = (uint32_t)lane; q < take; q += 64)
+      __builtin_nontemporal_store(rec[done + q], &P.jrec[rcur + q]);
+    rcur += take;
+    rleft -= take;
+    done += take;
+  }
 }
 
 constexpr uint64_t kChunk = 128;   // packet ids claimed per atomic on the shared counter
@@ -240,6 +290,7 @@ template <typename R, bool TRACE, bool IMG, bool DEFER>
 __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
   __shared__ unsigned int s_cnt[12];
+  __shared__ unsigned long long s_stage[DEFER ? 4 * kStage : 1];
   double* s_alb = smem;
   double* s_src = s_alb + P.nl;
   R* s_kext = reinterpret_cast<R*>(s_src + P.nl);
@@ -279,51 +330,30 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   // buffer is exhausted (rfull) the wave adds to the tally directly
   unsigned long long prec = 0;
   bool hrec = false, rfull = false;
+  unsigned long long* s_rec = s_stage + (threadIdx.x >> 6) * kStage;   // this wave's staging buffer
+  uint32_t s_fill = 0u;                                                // records in it (wave-uniform)
   bool hold = false;          // at an interaction point, waiting for the wave's batch
   uint64_t rcur = 0, rleft = 0;
   auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
   for (;;) {
     if (DEFER) {
-      // every lane is here (loop head): store the pending records of the wave
-      // contiguously, claiming a new chunk when the current one runs out
+      // every lane is here (loop head): the pending records of the wave go to
+      // its LDS staging buffer, which is copied to the record buffer in bulk
+      // when it cannot take another full wave of records.  A record store per
+      // step would be waited for by the step's next wait on memory (vector
+      // memory operations are counted in issue order), a write round trip
+      // each step; LDS stores are not.
       const unsigned long long rm = __ballot(hrec);
       if (rm) {
-        const uint64_t cnt = (uint64_t)__popcll(rm);
-        const uint64_t rank = (uint64_t)__popcll(rm & lt_mask);
-        uint64_t pos = ~0ull;
-        if (!rfull) {
-          if (rank < rleft) pos = rcur + rank;
-          if (cnt > rleft) {
-            unsigned long long base = 0;
-            const int leader = __ffsll((long long)rm) - 1;
-            if (lane == leader) base = atomicAdd(P.jrec_count, (unsigned long long)kRecChunk);
-            base = __shfl(base, leader);
-            if (base + kRecChunk <= P.jrec_cap) {
-              if (rank >= rleft) pos = base + (rank - rleft);
-              rcur = base + (cnt - rleft);
-              rleft = kRecChunk - (cnt - rleft);
-            } else {
-              // buffer exhausted: neutral records (slot 0, length 0) over the
-              // part of this chunk inside the buffer; direct adds from now on
-              for (uint64_t q = base + (uint64_t)lane; q < P.jrec_cap && q < base + kRecChunk; q += 64)
-                __builtin_nontemporal_store(0ull, &P.jrec[q]);
-              rfull = true;
-              rleft = 0;
-            }
-          } else {
-            rcur += cnt;
-            rleft -= cnt;
-          }
+        if (s_fill + 64u > kStage) {
+          flush_records(P, s_rec, s_fill, rcur, rleft, rfull);
+          s_fill = 0u;
         }
-        if (hrec) {
-          // records are written once and read back by the next kernels:
-          // non-temporal, so they stream past the L2 lines of the grid and
-          // tables that the march gathers from
-          if (pos != ~0ull) __builtin_nontemporal_store(prec, &P.jrec[pos]);
-          else atomicAdd(&P.jq[prec >> kRecValBits], prec & ((1ull << kRecValBits) - 1ull));
-          hrec = false;
-        }
+        const uint32_t rank = (uint32_t)__popcll(rm & lt_mask);
+        if (hrec) s_rec[s_fill + rank] = prec;
+        s_fill += (uint32_t)__popcll(rm);
+        hrec = false;
       }
     }
     if (!exhausted || q_next < q_end) {
@@ -580,9 +610,12 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
     }
   }
 
-  // the unused tail of the wave's last chunk holds neutral records
-  if (DEFER && !rfull)
-    for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) __builtin_nontemporal_store(0ull, &P.jrec[rcur + q]);
+  if (DEFER) {
+    if (s_fill) flush_records(P, s_rec, s_fill, rcur, rleft, rfull);
+    // the unused tail of the wave's last chunk holds neutral records
+    if (!rfull)
+      for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) __builtin_nontemporal_store(0ull, &P.jrec[rcur + q]);
+  }
 
   // ---- counters: registers reduced per wave, LDS per block
   {
@@ -625,12 +658,14 @@ __global__ void __launch_bounds__(256) k_peel(const TP<R> P) {
     int l = -1;
     for (int q = 0; q < I.n_l; ++q)
       if (I.lsel[q] == j) l = q;
-    if (l < 0) continue;
+    const bool sed = P.peel_sed != nullptr;
+    if (l < 0 && !sed) continue;
     const double X0 = I.off[0] + r.x[0] * I.h, X1 = I.off[1] + r.x[1] * I.h, X2 = I.off[2] + r.x[2] * I.h;
     const double a = X0 * I.e1[o][0] + X1 * I.e1[o][1] + X2 * I.e1[o][2];
     const double b = X0 * I.e2[o][0] + X1 * I.e2[o][1] + X2 * I.e2[o][2];
     const double fx = floor((a + I.w) / (2.0 * I.w) * I.npix), fy = floor((b + I.w) / (2.0 * I.w) * I.npix);
-    if (fx < 0.0 || fy < 0.0 || fx >= I.npix || fy >= I.npix) continue;
+    const bool in_img = l >= 0 && !(fx < 0.0 || fy < 0.0 || fx >= I.npix || fy >= I.npix);
+    if (!in_img && !sed) continue;
     double ph = 1.0;
     if (r.type == 1) {
       const double g = P.gpar[j];
@@ -699,8 +734,10 @@ __global__ void __launch_bounds__(256) k_peel(const TP<R> P) {
       u2 += (R)(o2 - lo2) * inv_nf;
     }
     const double wgt = ph * exp(-(double)tau);
-    atomicAdd(&P.peel[(((int64_t)o * I.n_l + l) * I.npix + (int64_t)fy) * I.npix + (int64_t)fx],
-              (unsigned long long)rint(wgt * MCRT_PEEL_UNIT));
+    const unsigned long long q = (unsigned long long)rint(wgt * MCRT_PEEL_UNIT);
+    if (in_img) atomicAdd(&P.peel[(((int64_t)o * I.n_l + l) * I.npix + (int64_t)fy) * I.npix + (int64_t)fx], q);
+    // the observer's next-event SED: every bin, wherever the event projects
+    if (sed) atomicAdd(&P.peel_sed[(int64_t)o * P.nl + j], q);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (cnt) atomicAdd(&P.counters[MCRT_CNT_PEEL], cnt);
@@ -768,6 +805,7 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
     P.level = reinterpret_cast<const int8_t*>(T + L.level);
     P.leaf_lo = reinterpret_cast<const int4*>(T + L.leaf_lo);
     P.peel = reinterpret_cast<unsigned long long*>(t.peel);
+    P.peel_sed = (o.flags & MCRT_FLAG_PEEL_SED) ? reinterpret_cast<unsigned long long*>(t.peel_sed) : nullptr;
     k_zero_u64<<<1, 64, 0, s>>>(&scr->peel_count, 1);
   }
   k_zero_u64<<<1, 64, 0, s>>>(&scr->work_counter, 1);

@@ -559,12 +559,18 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
 #pragma unroll
   for (int rr = 0; rr < kR; ++rr) {
     const int64_t c = c0 + wave * kR + rr;
+    const int64_t cc = c < p.n ? c : p.n - 1;     // clamped, unconditional loads
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j = lane + 64 * k;
-      Jv[rr][k] = (c < p.n && j < nl) ? p.J[c * nl + j] : 0.0f;
+      Jv[rr][k] = p.J[cc * nl + (j < nl ? j : 0)];
     }
   }
+#pragma unroll
+  for (int rr = 0; rr < kR; ++rr)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      Jv[rr][k] = (c0 + wave * kR + rr < p.n && lane + 64 * k < nl) ? Jv[rr][k] : 0.0f;
   double sum[kR];
 #pragma unroll
   for (int rr = 0; rr < kR; ++rr) {
@@ -653,10 +659,241 @@ __global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent fused inference with the weights on chip for the whole kernel.
+// One workgroup of 8 waves per CU; wave w owns output columns 32 w .. 32 w +
+// 31 of every layer.  The second and third layers' slices of the zero-padded
+// [256][256] bfloat16 matrices stay in the wave's registers (16 K-steps of one
+// 16-byte MFMA B fragment each: 128 VGPRs); the first layer's matrix (K
+// padded to 16 K1S) sits in LDS.  So the weights are read from memory once
+// per CU instead of once per cell tile.  Cells go 32 at a time (the M of
+// v_mfma_f32_32x32x16_bf16): features into LDS, three layers, each one MFMA
+// tile per wave and K-step, activations through two LDS buffers; the next
+// tile's field is loaded while the current one runs through the layers.
+// Same instruction, operand layout and k order as k_mlp_infer and k_gemm, so
+// the products are the same.
+constexpr int kRT = 32;          // cells per tile
+constexpr int kRW = 8;           // waves per workgroup
+constexpr int kRK = kFW / 16;    // K-steps of the second and third layers (zero-padded to 256)
+
+// LDS row stride of the first layer's matrix: K1S K-steps plus 8 (banks spread)
+__host__ __device__ constexpr int w1_stride(int k1s) { return 16 * k1s + 8; }
+
+size_t resident_lds(int nl, int k1s) {
+  return sizeof(uint16_t) * ((size_t)kFW * w1_stride(k1s) + 2 * kRT * kFP) +
+         sizeof(double) * (kRT + kRW * kRT + 2 * (size_t)nl) + sizeof(float) * 4 * kFW + sizeof(int) * kRT;
+}
+
+__device__ __forceinline__ void resident_layer(const uint16_t* act, const u16x8 (&w)[kRK], f32x16& acc) {
+  const int lane = threadIdx.x & 63;
+  const uint16_t* arow = act + (lane & 31) * kFP + 8 * (lane >> 5);
+  acc = f32x16{};
+#pragma unroll
+  for (int k = 0; k < kRK; ++k) {
+    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + 16 * k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, w[k]),
+                                                  acc, 0, 0, 0);
+  }
+}
+
+// first layer: B fragments from the LDS copy of the matrix
+template <int K1S>
+__device__ __forceinline__ void resident_layer1(const uint16_t* act, const uint16_t* w1, f32x16& acc) {
+  const int lane = threadIdx.x & 63, col = (threadIdx.x >> 6) * 32 + (lane & 31);
+  const uint16_t* arow = act + (lane & 31) * kFP + 8 * (lane >> 5);
+  const uint16_t* wrow = w1 + col * w1_stride(K1S) + 8 * (lane >> 5);
+  acc = f32x16{};
+#pragma unroll
+  for (int k = 0; k < K1S; ++k) {
+    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + 16 * k);
+    const u16x8 b = *reinterpret_cast<const u16x8*>(wrow + 16 * k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                  acc, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void resident_hidden(const f32x16& acc, float bias, bool on, uint16_t* dst) {
+  const int lane = threadIdx.x & 63, col = (threadIdx.x >> 6) * 32 + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    dst[row * kFP + col] = on ? f2bf(silu(acc[r] + bias)) : (uint16_t)0;
+  }
+}
+
+// K1S: K-steps of the first layer (13 covers the 201 inputs of the PAH model)
+template <int K1S>
+__global__ void __launch_bounds__(kRW * 64, 1) k_mlp_infer_resident(const InferP p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char rsm[];
+  uint16_t* sW1 = reinterpret_cast<uint16_t*>(rsm);                 // [256][w1_stride]
+  uint16_t* bufA = sW1 + kFW * w1_stride(K1S);                       // [32][kFP]
+  uint16_t* bufB = bufA + kRT * kFP;                                 // [32][kFP]
+  double* sPabs = reinterpret_cast<double*>(bufB + kRT * kFP);       // [32]
+  double* sRow = sPabs + kRT;                                        // [8][32]
+  double* sCa = sRow + kRW * kRT;                                    // [nl] cabs
+  double* sDn = sCa + p.nl;                                          // [nl] dnu
+  float* sMu = reinterpret_cast<float*>(sDn + p.nl);                 // [256] x_mu, x_sd, x_lo, x_hi
+  float* sSd = sMu + kFW;
+  float* sLo = sSd + kFW;
+  float* sHi = sLo + kFW;
+  int* sBad = reinterpret_cast<int*>(sHi + kFW);                     // [32]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nl = p.nl, ni = p.ni, nh = p.nh, no = p.no;
+  const int col = wave * 32 + (lane & 31);
+
+  for (int j = threadIdx.x; j < nl; j += kRW * 64) {
+    sCa[j] = p.cabs[j];
+    sDn[j] = p.dnu[j];
+  }
+  for (int j = threadIdx.x; j < kFW; j += kRW * 64) {
+    const bool in = j < ni;
+    sMu[j] = in ? p.x_mu[j] : 0.0f;
+    sSd[j] = in ? p.x_sd[j] : 1.0f;
+    sLo[j] = in ? p.x_lo[j] : 0.0f;
+    sHi[j] = in ? p.x_hi[j] : 0.0f;
+  }
+  // this wave's weight slices: B fragment of K-step k is
+  // W[col][16 k + 8 (lane >> 5) .. + 7] of the padded matrix
+  // first layer's matrix into LDS, 16 bytes at a time
+  for (int q = threadIdx.x; q < kFW * 2 * K1S; q += kRW * 64) {
+    const int r = q / (2 * K1S), k8 = q - r * 2 * K1S;
+    *reinterpret_cast<u16x8*>(sW1 + r * w1_stride(K1S) + 8 * k8) =
+        *reinterpret_cast<const u16x8*>(p.Wp + (size_t)r * kFW + 8 * k8);
+  }
+  u16x8 w2[kRK], w3[kRK];
+  {
+    const uint16_t* r0 = p.Wp + (size_t)col * kFW + 8 * (lane >> 5);
+#pragma unroll
+    for (int k = 0; k < kRK; ++k) {
+      w2[k] = *reinterpret_cast<const u16x8*>(r0 + kFW * kFW + 16 * k);
+      w3[k] = *reinterpret_cast<const u16x8*>(r0 + 2 * kFW * kFW + 16 * k);
+    }
+  }
+  const float b1 = col < nh ? p.b1[col] : 0.0f, b2 = col < nh ? p.b2[col] : 0.0f;
+  const float b3 = col < no ? p.b3[col] : 0.0f;
+  const float ymu = col < no ? p.y_mu[col] : 0.0f, ysd = col < no ? p.y_sd[col] : 0.0f;
+
+  // field of this wave's 4 rows of a tile: bins lane + 64 q (n_lambda <= 256)
+  constexpr int kR = kRT / kRW;
+  float Jv[kR][4];
+  // unconditional loads from clamped addresses, out-of-range values zeroed
+  // afterwards: a load under a branch makes the compiler wait for it before
+  // the next one, which would serialise the sixteen loads of a lane
+  auto load_tile = [&](int64_t c0) {
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) {
+      const int64_t c = c0 + wave * kR + rr;
+      const int64_t cc = c < p.n ? c : p.n - 1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        Jv[rr][q] = p.J[cc * nl + (j < nl ? j : 0)];
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) {
+      const bool cin = c0 + wave * kR + rr < p.n;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Jv[rr][q] = (cin && lane + 64 * q < nl) ? Jv[rr][q] : 0.0f;
+    }
+  };
+  const int64_t n_tiles = (p.n + kRT - 1) / kRT;
+  int64_t t = blockIdx.x;
+  if (t < n_tiles) load_tile(t * kRT);
+  __syncthreads();
+  for (; t < n_tiles; t += gridDim.x) {
+    const int64_t c0 = t * kRT;
+    // ---- features of the tile's 32 cells (wave w: rows 4 w .. 4 w + 3)
+    double sum[kR];
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        if (j < nl) s += sCa[j] * (double)Jv[rr][q] * sDn[j];
+      }
+      sum[rr] = s;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int rr = 0; rr < kR; ++rr) sum[rr] += __shfl_xor(sum[rr], off);
+#pragma unroll
+    for (int rr = 0; rr < kR; ++rr) {
+      const int row = wave * kR + rr;
+      const bool valid = c0 + row < p.n;
+      const double inv = sum[rr] > 0.0 ? 1.0 / sum[rr] : 0.0;
+      const double pa = 4.0 * kPi * sum[rr];
+      int bad = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = lane + 64 * q;
+        uint16_t h = 0;
+        if (valid && j < ni) {
+          const float f = j < nl ? (float)(sCa[j] * (double)Jv[rr][q] * sDn[j] * inv)
+                                 : (float)log10(fmax(pa, 1e-300));
+          const float x = (f - sMu[j]) / sSd[j];
+          if (x < sLo[j] - p.margin || x > sHi[j] + p.margin) bad = 1;
+          h = f2bf(x);
+        }
+        bufA[row * kFP + j] = h;
+      }
+      // a dark cell (no absorbed power) has the exact answer F = 0
+      bad = __any(bad) && pa > 0.0;
+      if (lane == 0) {
+        sBad[row] = bad;
+        sPabs[row] = pa;
+      }
+    }
+    // the next tile's field goes in flight behind the three layers
+    if (t + gridDim.x < n_tiles) load_tile((t + gridDim.x) * kRT);
+    __syncthreads();
+
+    f32x16 acc;
+    resident_layer1<K1S>(bufA, sW1, acc);
+    resident_hidden(acc, b1, col < nh, bufB);
+    __syncthreads();
+    resident_layer(bufB, w2, acc);
+    resident_hidden(acc, b2, col < nh, bufA);
+    __syncthreads();
+    resident_layer(bufA, w3, acc);
+
+    // ---- outputs F = 10^(y sd + mu) P_abs and their per-cell sums over
+    // this wave's 32 columns (one row at a time: few live registers)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      double F = 0.0;
+      if (col < no) {
+        const float y = acc[r] + b3;
+        F = sPabs[row] > 0.0 ? (double)exp10f(y * ysd + ymu) * sPabs[row] : 0.0;
+        if (c0 + row < p.n) p.out[(c0 + row) * no + col] = F;
+      }
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) F += __shfl_xor(F, off);
+      if ((lane & 31) == 0) sRow[wave * kRT + row] = F;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRT && c0 + threadIdx.x < p.n) {
+      const int row = threadIdx.x;
+      double tot = 0.0;
+      for (int w = 0; w < kRW; ++w) tot += sRow[w * kRT + row];
+      const double pa = sPabs[row];
+      const int bal = !(fabs(tot - pa) <= p.tol * pa);
+      p.ood[c0 + row] = (uint8_t)(sBad[row] | (bal << 1));
+      p.pabs[c0 + row] = pa;
+    }
+    // the buffers and row sums are rewritten by the next tile
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 struct pah_mlp {
   int ni, nh, no, batch;
+  int resident_blocks = -1;         // grid of the persistent inference kernel
   MlpLayout L;
   unsigned char* st = nullptr;
   std::string err;
@@ -877,7 +1114,40 @@ int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int6
   if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
   const MlpLayout& L = m->L;
   if (n == 0) return MCRT_OK;
+  if (m->ni <= 13 * 16 && m->nh <= kFW && m->no <= kFW) {
+    k_pack<<<(3 * kFW * kFW + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.W1h), at<uint16_t>(m, L.W2h),
+                                                        at<uint16_t>(m, L.W3h), m->ni, m->nh, m->no,
+                                                        at<uint16_t>(m, L.Wpk));
+    InferP p{};
+    p.J = J; p.n = n; p.nl = d.n_lambda; p.ni = m->ni; p.nh = m->nh; p.no = m->no;
+    p.cabs = d.cabs; p.dnu = dnu;
+    p.x_mu = at<float>(m, L.x_mu); p.x_sd = at<float>(m, L.x_sd);
+    p.x_lo = at<float>(m, L.x_lo); p.x_hi = at<float>(m, L.x_hi);
+    p.y_mu = at<float>(m, L.y_mu); p.y_sd = at<float>(m, L.y_sd);
+    const float* P = at<float>(m, L.params);
+    p.b1 = P + L.ob1; p.b2 = P + L.ob2; p.b3 = P + L.ob3;
+    p.Wp = at<uint16_t>(m, L.Wpk);
+    p.margin = in_margin; p.tol = balance_tol;
+    p.out = out; p.ood = ood; p.pabs = pabs;
+    if (m->resident_blocks < 0) {
+      int dev = 0, ncu = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_infer_resident<13>, kRW * 64,
+                                                       resident_lds(d.n_lambda, 13)) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      m->resident_blocks = ncu * per_cu;
+    }
+    const int64_t tiles = (n + kRT - 1) / kRT;
+    const int64_t blocks = tiles < m->resident_blocks ? tiles : m->resident_blocks;
+    k_mlp_infer_resident<13><<<(unsigned)blocks, kRW * 64, resident_lds(d.n_lambda, 13), s>>>(p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
+    return MCRT_OK;
+  }
   if (m->ni <= kFW && m->nh <= kFW && m->no <= kFW) {
+    // wider inputs: the weights stay in L2, 64 cells per workgroup
     k_pack<<<(3 * kFW * kFW + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.W1h), at<uint16_t>(m, L.W2h),
                                                         at<uint16_t>(m, L.W3h), m->ni, m->nh, m->no,
                                                         at<uint16_t>(m, L.Wpk));

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcrt.so")
 
 F32, F64 = 0, 1
-FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW, FLAG_PEEL = 1, 2, 4, 8, 16
+FLAG_TALLY_J, FLAG_FROZEN_T, FLAG_KILL_ON_ABSORB, FLAG_EXACT_BW, FLAG_PEEL, FLAG_PEEL_SED = 1, 2, 4, 8, 16, 32
 PEEL_REC_BYTES = 64
 PEEL_UNIT = 1 << 24                     # fixed-point unit of the next-event images
 CNT = dict(launched=0, escaped=1, killed=2, terminated=3, scatters=4, absorptions=5,
@@ -46,7 +46,8 @@ class Source(C.Structure):
 
 
 class Tallies(C.Structure):
-    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp), ("image", _dp), ("peel", _dp)]
+    _fields_ = [("nabs", _dp), ("sed", _dp), ("jq", _dp), ("counters", _dp), ("image", _dp), ("peel", _dp),
+                ("peel_sed", _dp)]
 
 
 class Observers(C.Structure):
@@ -255,10 +256,12 @@ class Engine:
                                             self.tables.numel(), _stream()), "mcrt_build_tables")
 
     def set_observers(self, dirs=(), npix=1, half_width=1.0, center=(0.0, 0.0, 0.0), cos_cone=1.0,
-                      lambda_bins=(), peel=False, peel_capacity=1 << 22):
+                      lambda_bins=(), peel=False, peel_capacity=1 << 22, peel_sed=False):
         """Escape images (see mcrt_observers); no directions turns them off.
         peel: also next-event images (MCRT_FLAG_PEEL) in tallies["peel"], with a
-        device queue of peel_capacity records held by the engine."""
+        device queue of peel_capacity records held by the engine.
+        peel_sed: also each observer's next-event SED over every bin
+        (MCRT_FLAG_PEEL_SED) in tallies["peel_sed"] [n_obs, n_lambda]."""
         ob = Observers()
         ob.n_obs, ob.npix, ob.n_img_lambda = len(dirs), int(npix), len(lambda_bins)
         for q, jb in enumerate(lambda_bins):
@@ -271,6 +274,7 @@ class Engine:
         self._check(lib().mcrt_set_observers(self.ctx, C.byref(ob)), "mcrt_set_observers")
         self.image_shape = (len(dirs), len(lambda_bins), int(npix), int(npix)) if len(dirs) else None
         self.peel_on = bool(peel) and len(dirs) > 0
+        self.peel_sed_on = self.peel_on and bool(peel_sed)
         if self.peel_on:
             cap = int(peel_capacity)
             if getattr(self, "_peel_q", None) is None or self._peel_q.numel() < cap * PEEL_REC_BYTES:
@@ -285,7 +289,9 @@ class Engine:
                     jq=z(self.n_lambda * self.n_cells) if tally_j else None,
                     counters=z(16),
                     image=z(np.prod(shape)) if shape else None,
-                    peel=z(np.prod(shape)) if shape and getattr(self, "peel_on", False) else None)
+                    peel=z(np.prod(shape)) if shape and getattr(self, "peel_on", False) else None,
+                    peel_sed=z(shape[0] * self.n_lambda) if shape and getattr(self, "peel_sed_on", False)
+                    else None)
 
     def counters_sync(self, tallies):
         """The run counters as numpy uint64, after the stream has drained."""
@@ -319,12 +325,15 @@ class Engine:
         if flags is None:
             flags = FLAG_TALLY_J if tallies.get("jq") is not None else 0
         t = Tallies(_ptr(tallies["nabs"]), _ptr(tallies["sed"]), _ptr(tallies.get("jq")),
-                    _ptr(tallies["counters"]), _ptr(tallies.get("image")), _ptr(tallies.get("peel")))
+                    _ptr(tallies["counters"]), _ptr(tallies.get("image")), _ptr(tallies.get("peel")),
+                    _ptr(tallies.get("peel_sed")))
         o = RunOpts()
         o.n_total, o.seed, o.max_events = int(n_total), int(seed), int(max_events)
         o.flags, o.grid_blocks = int(flags), int(grid_blocks)
         if getattr(self, "peel_on", False) and tallies.get("peel") is not None:
             o.flags |= FLAG_PEEL
+            if tallies.get("peel_sed") is not None:
+                o.flags |= FLAG_PEEL_SED
             o.peel_queue, o.peel_capacity = _ptr(self._peel_q), self.peel_capacity
         if kernel_events is not None:
             if not (kernel_events[0].cuda_event and kernel_events[1].cuda_event):

@@ -235,6 +235,43 @@ def test_peel_fp32_and_queue_overflow():
     assert 0 < s["peel"].sum() < g["peel"].sum()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_peel_sed_equals_oracle(precision):
+    # each observer's next-event SED over every bin (emissions and
+    # scatterings in any bin are queued and marched): FP64 with a frozen
+    # field and equal seeds gives the oracle's weights to the rounding unit
+    # per bin; FP32 agrees to the packets whose histories part (a few %)
+    w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
+    w.precision = precision
+    base = oracle.Session(w).transport()["nabs"]
+    e = engine(w)
+    obs = disk_observers(w)
+    e.set_observers(**obs, peel=True, peel_sed=True, peel_capacity=1 << 16)
+    tal = e.new_tallies()
+    assert tal["peel_sed"] is not None and tal["peel_sed"].numel() == 3 * w.species.n_lambda
+    e.run(tal, 0, 3000, 3000, w.seed, frozen_nabs=base, flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    g = host(tal)
+    o = oracle.Session(w, frozen_nabs=base, observers=obs,
+                       flags=oracle.FLAG_TALLY_J | oracle.FLAG_PEEL | oracle.FLAG_PEEL_SED).transport()
+    gs = g["peel_sed"].reshape(3, -1).astype(np.int64)
+    os_ = o["peel_sed"].astype(np.int64)
+    n_ev = int(o["counters"][oracle.CNT["peel"]])
+    assert n_ev > 3000 and int(g["counters"][mcrt.CNT["peel_dropped"]]) == 0
+    assert os_.sum() > 1000 * oracle.PEEL_ONE and np.count_nonzero(os_[0]) > 20
+    if precision == "f64":
+        assert np.array_equal(g["counters"], o["counters"])
+        assert np.abs(gs - os_).max() <= 2
+        assert np.abs(g["peel"].astype(np.int64) - o["peel"].reshape(-1).astype(np.int64)).max() <= 2
+    else:
+        assert abs(int(g["counters"][mcrt.CNT["peel"]]) - n_ev) <= 0.02 * n_ev
+        for ob in range(3):
+            assert abs(gs[ob].sum() - os_[ob].sum()) <= 0.03 * os_[ob].sum()
+    # the images at the imaged bins are the SED's weights where the events project inside
+    img = g["peel"].reshape(3, 3, -1).astype(np.int64).sum(2)
+    for l, jb in enumerate(obs["lambda_bins"]):
+        assert np.all(img[:, l] <= gs[:, jb])
+
+
 def test_images_count_every_in_cone_escape():
     # FP32 transport, traced: each image holds exactly the escapes whose
     # direction lies in the observer's cone (the field of view encloses every

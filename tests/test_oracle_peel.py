@@ -150,3 +150,57 @@ def test_scattered_beam_agrees_with_escape_cones():
         ratio = _hg_cone(g, beam, n, cos_c) / _hg(g, float(np.dot(beam, n)))
         assert esc > 400
         assert abs(esc - ratio * peel) < 4.0 * math.sqrt(esc) + 0.02 * esc, (ths[o], esc, ratio * peel)
+
+
+# --------------------------------------------------------------------------
+# next-event SEDs (ORC_FLAG_PEEL_SED): per observer, every bin
+def test_peel_sed_star_alone_is_the_launch_spectrum():
+    # dust-free: every launch weighs 1 towards every observer, in its own bin
+    w = synth.uniform_cube(8, 0.0, nl=16, n_packets=3000)
+    obs = _obs(w, [(0, 0, 1), (0.3, -0.5, 0.2)], bins=(3,))
+    r = oracle.Session(w, observers=obs, flags=oracle.FLAG_PEEL | oracle.FLAG_PEEL_SED).transport()
+    launched = r["sed"].sum(axis=(0, 1)).astype(np.int64)
+    assert launched.sum() == 3000 and np.count_nonzero(launched) >= 6
+    for o in range(2):
+        assert np.array_equal(r["peel_sed"][o].astype(np.int64), launched * ONE)
+    assert int(r["counters"][oracle.CNT["peel"]]) == 3000       # every event queued, not only bin 3
+
+
+def test_peel_sed_direct_starlight_closed_form():
+    # pure absorber, packets end at their first absorption: each launch in
+    # bin j adds round(2^24 exp(-tau)) towards observer n, tau = alpha times
+    # the distance along n from the star (cube centre) to the first face
+    w = synth.uniform_cube(8, 0.3, albedo=0.0, nl=16, n_packets=2000)
+    dirs = [(0, 0, 1), (0, 0.6, 0.8), (-1, 0, 0)]
+    obs = _obs(w, dirs, bins=(5,))
+    r = oracle.Session(w, observers=obs, flags=oracle.FLAG_PEEL | oracle.FLAG_PEEL_SED |
+                       oracle.FLAG_KILL_ON_ABSORB).transport(trace_cap=4)
+    per_bin = np.bincount([t[0]["j"] for t in r["trace"]], minlength=16).astype(np.int64)
+    for o, n in enumerate(dirs):
+        n = np.array(n, float) / np.linalg.norm(n)
+        dist = min((8.0 - 4.0) / a if a > 0 else (0.0 - 4.0) / a for a in n if a != 0)
+        unit = int(round(math.exp(-0.3 * dist) * ONE))
+        got = r["peel_sed"][o].astype(np.int64)
+        assert np.all(np.abs(got - per_bin * unit) <= per_bin // 2 + 1), (o, got, per_bin * unit)
+
+
+def test_peel_sed_at_imaged_bins_equals_image_totals():
+    # scattering, re-emitting disk; a field of view enclosing every projected
+    # event: at an imaged bin the SED holds the same weights as the image
+    w = synth.small_disk(n_packets=3000, nl=32, n_sizes=2, nb=8)
+    half = 4.0 * w.grid.nb * w.grid.base_size
+    obs = _obs(w, [(0, 0, 1), (1, 0, 0), (0, 0.5, 0.866)], npix=15, bins=(10, 14, 16), half=half)
+    base = oracle.Session(w).transport()["nabs"]
+    r = oracle.Session(w, frozen_nabs=base, observers=obs,
+                       flags=oracle.FLAG_TALLY_J | oracle.FLAG_PEEL | oracle.FLAG_PEEL_SED).transport()
+    img = r["peel"].astype(np.int64)
+    sed = r["peel_sed"].astype(np.int64)
+    for o in range(3):
+        for l, jb in enumerate(obs["lambda_bins"]):
+            assert img[o, l].sum() == sed[o, jb] and sed[o, jb] > 5 * ONE
+    # every bin with escaping light has a next-event estimate
+    esc = r["sed"].sum(axis=(0, 1))
+    assert np.all(sed[:, esc > 50] > 0)
+    # without the SED flag nothing changes in the images
+    r0 = oracle.Session(w, frozen_nabs=base, observers=obs, flags=oracle.FLAG_TALLY_J | oracle.FLAG_PEEL).transport()
+    assert np.array_equal(r0["peel"], r["peel"]) and r0["peel_sed"] is None
