@@ -62,6 +62,20 @@ struct RunScratch {
 
 Layout make_layout(const mcrt_desc& d);
 
+// The packed base-cube table (entry + FP32 density term) of the FP32
+// transport is stored in bricks of 4 x 2 x 2 base cubes, one 128-byte cache
+// line each: a packet stepping to a neighbour in y or z then stays in the
+// line half of the time (in raster order never), in x three times in four.
+// Bricks are in raster order over ceil(nb/4) x ceil(nb/2) x ceil(nb/2).
+__host__ __device__ __forceinline__ int64_t binfo_index(int nb, int bx, int by, int bz) {
+  const int64_t nx4 = (nb + 3) >> 2, ny2 = (nb + 1) >> 1;
+  const int64_t brick = ((int64_t)(bz >> 1) * ny2 + (by >> 1)) * nx4 + (bx >> 2);
+  return brick * 16 + (((bz & 1) << 3) | ((by & 1) << 2) | (bx & 3));
+}
+__host__ __device__ __forceinline__ uint64_t binfo_entries(int nb) {
+  return (uint64_t)((nb + 3) >> 2) * (uint64_t)((nb + 1) >> 1) * (uint64_t)((nb + 1) >> 1) * 16;
+}
+
 // Deferred path-length tally: the transport appends one 64-bit record per
 // path segment, (tally index << 24) | fixed-point length, in chunks of
 // kRecChunk claimed per wave; a partition by tally range and an LDS sum then

@@ -208,13 +208,16 @@ __global__ void k_cells(int64_t n_cells, double h, const double* __restrict__ rh
   rho_h32[c] = rho_h_f32(rho[c], h);
 }
 
-// base-map entry packed with the FP32 density term of an unrefined base cube
-__global__ void k_binfo(int64_t nbase, double h, const int32_t* __restrict__ base_map,
-                        const double* __restrict__ rho, int2* __restrict__ binfo) {
+// base-map entry packed with the FP32 density term of an unrefined base
+// cube, in brick order (4 x 2 x 2 cubes per 128-byte line, binfo_index)
+__global__ void k_binfo(int nb, double h, const int32_t* __restrict__ base_map, const double* __restrict__ rho,
+                        int2* __restrict__ binfo) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nbase = (int64_t)nb * nb * nb;
   if (b >= nbase) return;
+  const int bx = (int)(b % nb), by = (int)((b / nb) % nb), bz = (int)(b / ((int64_t)nb * nb));
   const int32_t e = base_map[b];
-  binfo[b] = make_int2(e, e >= 0 ? __float_as_int(rho_h_f32(rho[e], h)) : 0);
+  binfo[binfo_index(nb, bx, by, bz)] = make_int2(e, e >= 0 ? __float_as_int(rho_h_f32(rho[e], h)) : 0);
 }
 
 __global__ void k_check_species(int nl, int S, const double* __restrict__ lam_um,
@@ -264,7 +267,7 @@ Layout make_layout(const mcrt_desc& d) {
   L.rho_h32 = take(4 * (uint64_t)d.n_cells);
   L.level = take((uint64_t)d.n_cells);
   L.leaf_lo = take(16 * (uint64_t)d.n_cells);
-  L.binfo = take(8 * (uint64_t)d.nb * d.nb * d.nb);
+  L.binfo = take(8 * binfo_entries(d.nb));
   L.pah_slot = take(4 * S);
   L.scratch = take(sizeof(RunScratch));
   L.total = off;
@@ -307,7 +310,7 @@ hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s) {
                                                             reinterpret_cast<int4*>(T + L.leaf_lo));
   k_cells<<<(unsigned)((d.n_cells + 255) / 256), 256, 0, s>>>(d.n_cells, d.base_size, d.rho,
                                                               F(L.rho_h32));
-  k_binfo<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(nbase, d.base_size, d.base_map, d.rho,
+  k_binfo<<<(unsigned)((nbase + 255) / 256), 256, 0, s>>>(d.nb, d.base_size, d.base_map, d.rho,
                                                           reinterpret_cast<int2*>(T + L.binfo));
   return hipGetLastError();
 }

@@ -116,14 +116,13 @@ __device__ __forceinline__ int locate(const TP<R>& P, int F0, int F1, int F2, in
   const int L = P.L, nb = P.nb;
   const unsigned ext = (unsigned)nb << L;
   if ((unsigned)F0 >= ext || (unsigned)F1 >= ext || (unsigned)F2 >= ext) return -1;
-  const int b = (F0 >> L) + nb * ((F1 >> L) + nb * (F2 >> L));
   int e;
   if (sizeof(R) == 4) {
-    const int2 bi = P.binfo[b];
+    const int2 bi = P.binfo[binfo_index(nb, F0 >> L, F1 >> L, F2 >> L)];
     e = bi.x;
     dens = (R)__int_as_float(bi.y);
   } else {
-    e = P.base_map[b];
+    e = P.base_map[(F0 >> L) + nb * ((F1 >> L) + nb * (F2 >> L))];
   }
   int l = 0;
   if (e < 0) {
