@@ -19,6 +19,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
@@ -440,18 +441,27 @@ __global__ void k_standardise(float* __restrict__ A, int64_t n, int m, const flo
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference for networks no wider than 256: 64 cells per workgroup.
-// The cells' features, both hidden activations and the outputs never leave
-// the chip: two LDS buffers of [64][264] bfloat16 take turns as layer input
-// and output; weight fragments come from a zero-padded [256][256] copy of each
-// matrix (L2 resident); the last layer writes F and the balance flag straight
-// from its accumulators.  Same MFMA instruction and k order as k_gemm, so the
-// products equal the layer-by-layer path.
-constexpr int kFT = 64;          // cells per workgroup
+// Fused persistent inference for networks no wider than 256.  A tile of 64
+// cells goes through features, three layers and outputs without leaving the
+// chip: two LDS buffers of [64][264] bfloat16 take turns as layer input and
+// output.  Eight waves per workgroup, two workgroups per CU: wave w computes
+// columns 32 w .. 32 w + 31 of every layer for all 64 cells (4 x 2 blocks of
+// v_mfma_f32_16x16x32_bf16), A fragments from LDS, B fragments streamed from
+// the zero-padded [256][256] matrices (L2 resident) four K-steps ahead of
+// their use.  One workgroup's field loads and epilogues overlap the other's
+// products.
 constexpr int kFW = 256;         // packed width
-constexpr int kFP = kFW + 8;     // LDS row stride (16-byte rows, banks spread)
+constexpr int kFP = kFW + 8;     // LDS row stride in bf16 (16-byte rows, banks spread)
+constexpr int kTT = 64;          // cells per tile
+constexpr int kTW = 8;           // waves per workgroup
+constexpr int kKS = kFW / 32;    // K-steps per layer (inputs zero-padded to 256)
+constexpr int kBR = 4;           // B fragments in flight (K-steps ahead)
+constexpr int kTR = kTT / kTW;   // field rows per wave
 
-size_t fused_lds() { return 2 * sizeof(uint16_t) * kFT * kFP + sizeof(double) * 3 * kFT + sizeof(int) * kFT; }
+size_t tile_lds(int nl) {
+  (void)nl;
+  return sizeof(uint16_t) * 2 * kTT * kFP + sizeof(double) * (kTT + kFW) + sizeof(float) * 9 * kFW + sizeof(int) * kTT;
+}
 
 // zero-padded [256][256] bf16 copies of W1, W2, W3 (row = output unit)
 __global__ void k_pack(const uint16_t* __restrict__ W1, const uint16_t* __restrict__ W2,
@@ -478,407 +488,285 @@ struct InferP {
   double* pabs;
 };
 
-// acc = act[64][K] W^T on the tile; wave (wr, wc) owns rows 32 wr .. 32 wr + 31
-// and the column blocks 128 wc + 32 cb (cb < 4) that start below N
-__device__ __forceinline__ void fused_layer(const uint16_t* act, const uint16_t* __restrict__ W, int K, int N,
-                                            f32x16* acc) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int Kp = (K + 15) & ~15;
-  bool on[4];
+// acc[mb][cb] = act[16 mb .. + 15][:] W[32 w + 16 cb .. + 15][:]^T.  Lane l
+// holds A row l & 15 and B column l & 15 at k = 32 s + 8 (l >> 4) .. + 7;
+// accumulator element i is row 4 (l >> 4) + i, column l & 15 of its block.
+__device__ __forceinline__ void tile_layer(const uint16_t* act, const uint16_t* __restrict__ W,
+                                           f32x4 (&acc)[4][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint16_t* arow = act + (lane & 15) * kFP + 8 * (lane >> 4);
+  // opaque per call: the fragment addresses are formed where they are used
+  // rather than hoisted out of the tile loop (48 addresses would not fit)
+  int wofs = (wave * 32 + (lane & 15)) * kFW + 8 * (lane >> 4);
+  asm volatile("" : "+v"(wofs));
+  const uint16_t* wrow = W + wofs;
+  u16x8 b[kBR][2];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    on[cb] = wc * 128 + cb * 32 < N;
-    acc[cb] = f32x16{};
-  }
-  const uint16_t* arow = act + (wr * 32 + (lane & 31)) * kFP + 8 * (lane >> 5);
-  const uint16_t* wrow = W + (wc * 128 + (lane & 31)) * kFW + 8 * (lane >> 5);
-  u16x8 bn[4];
+  for (int s = 0; s < kBR; ++s)
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-    if (on[cb]) bn[cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 32 * kFW);
-  for (int k0 = 0; k0 < Kp; k0 += 16) {
-    u16x8 bc[4];
+    for (int cb = 0; cb < 2; ++cb) b[s][cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 16 * kFW + 32 * s);
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) bc[cb] = bn[cb];
-    if (k0 + 16 < Kp) {                   // fetch the next step's fragments first
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (on[cb]) bn[cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 32 * kFW + k0 + 16);
-    }
-    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + k0);
+    for (int cb = 0; cb < 2; ++cb) acc[mb][cb] = f32x4{};
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      if (on[cb])
-        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                          __builtin_bit_cast(bf16x8, bc[cb]), acc[cb], 0, 0, 0);
-  }
-}
-
-// hidden-layer epilogue: bias, SiLU, bfloat16 into the next LDS buffer
-__device__ __forceinline__ void fused_hidden(const f32x16* acc, const float* __restrict__ bias, int N,
-                                             uint16_t* dst) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  for (int k = 0; k < kKS; ++k) {
+    u16x8 a[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    const int col = wc * 128 + cb * 32 + (lane & 31);
-    if (wc * 128 + cb * 32 >= N) continue;
-    const float bcol = col < N ? bias[col] : 0.0f;
+    for (int mb = 0; mb < 4; ++mb) a[mb] = *reinterpret_cast<const u16x8*>(arow + 16 * mb * kFP + 32 * k);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      dst[row * kFP + col] = f2bf(silu(acc[cb][r] + bcol));
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+        acc[mb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mb]),
+                                                              __builtin_bit_cast(bf16x8, b[k % kBR][cb]),
+                                                              acc[mb][cb], 0, 0, 0);
+    if (k + kBR < kKS) {
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+        b[k % kBR][cb] = *reinterpret_cast<const u16x8*>(wrow + cb * 16 * kFW + 32 * (k + kBR));
     }
   }
 }
 
-__global__ void __launch_bounds__(256, 2) k_mlp_infer(const InferP p) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
-  uint16_t* bufA = reinterpret_cast<uint16_t*>(fsm);               // [64][kFP]
-  uint16_t* bufB = bufA + kFT * kFP;                                // [64][kFP]
-  double* sPabs = reinterpret_cast<double*>(bufB + kFT * kFP);      // [64]
-  double* sRow = sPabs + kFT;                                       // [2][64]
-  int* sBad = reinterpret_cast<int*>(sRow + 2 * kFT);               // [64]
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t c0 = (int64_t)blockIdx.x * kFT;
-  const int nl = p.nl, ni = p.ni;
+// bfloat16 rounded to nearest even by the conversion instruction (as f2bf)
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-  // ---- features (wave w: rows 16 w .. 16 w + 15), standardised, range flag.
-  // Every lane first loads its bins of all 16 rows (n_lambda <= 255 here, so
-  // at most 4 bins per lane), then the rows are reduced and written.
-  constexpr int kR = kFT / 4;
-  double ca[4], dn[4];
+// hidden-layer epilogue: bias, SiLU (hardware reciprocal), bfloat16 into the
+// other buffer.  Columns past the layer's width have zero weights and zero
+// bias, so their activation is SiLU(0) = 0.
+__device__ __forceinline__ void tile_hidden(const f32x4 (&acc)[4][2], const float* bias, uint16_t* dst) {
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int j = lane + 64 * k;
-    ca[k] = j < nl ? p.cabs[j] : 0.0;
-    dn[k] = j < nl ? p.dnu[j] : 0.0;
-  }
-  float Jv[kR][4];
+  for (int cb = 0; cb < 2; ++cb) {
+    const int col = wave * 32 + 16 * cb + (lane & 15);
+    const float b = bias[col];
 #pragma unroll
-  for (int rr = 0; rr < kR; ++rr) {
-    const int64_t c = c0 + wave * kR + rr;
-    const int64_t cc = c < p.n ? c : p.n - 1;     // clamped, unconditional loads
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int j = lane + 64 * k;
-      Jv[rr][k] = p.J[cc * nl + (j < nl ? j : 0)];
-    }
-  }
-#pragma unroll
-  for (int rr = 0; rr < kR; ++rr)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      Jv[rr][k] = (c0 + wave * kR + rr < p.n && lane + 64 * k < nl) ? Jv[rr][k] : 0.0f;
-  double sum[kR];
-#pragma unroll
-  for (int rr = 0; rr < kR; ++rr) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s += ca[k] * (double)Jv[rr][k] * dn[k];
-    sum[rr] = s;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int rr = 0; rr < kR; ++rr) sum[rr] += __shfl_xor(sum[rr], off);
-#pragma unroll
-  for (int rr = 0; rr < kR; ++rr) {
-    const int row = wave * kR + rr;
-    const bool valid = c0 + row < p.n;
-    const double inv = sum[rr] > 0.0 ? 1.0 / sum[rr] : 0.0;
-    const double pa = 4.0 * kPi * sum[rr];
-    int bad = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int j = lane + 64 * k;
-      uint16_t h = 0;
-      if (valid && j < ni) {
-        const float f = j < nl ? (float)(ca[k] * (double)Jv[rr][k] * dn[k] * inv) : (float)log10(fmax(pa, 1e-300));
-        const float x = (f - p.x_mu[j]) / p.x_sd[j];
-        if (x < p.x_lo[j] - p.margin || x > p.x_hi[j] + p.margin) bad = 1;
-        h = f2bf(x);
+      for (int i = 0; i < 4; ++i) {
+        const float z = acc[mb][cb][i] + b;
+        const float h = z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+        dst[(16 * mb + 4 * (lane >> 4) + i) * kFP + col] = bf16_rne(h);
       }
-      bufA[row * kFP + j] = h;
-    }
-    // a dark cell (no absorbed power) has the exact answer F = 0 (the
-    // molecule stays in its ground state), whatever its inputs look like
-    bad = __any(bad) && pa > 0.0;
-    if (lane == 0) {
-      sBad[row] = bad;
-      sPabs[row] = pa;
-    }
-  }
-  __syncthreads();
-
-  f32x16 acc[4];
-  fused_layer(bufA, p.Wp, ni, p.nh, acc);
-  fused_hidden(acc, p.b1, p.nh, bufB);
-  __syncthreads();
-  fused_layer(bufB, p.Wp + kFW * kFW, p.nh, p.nh, acc);
-  fused_hidden(acc, p.b2, p.nh, bufA);
-  __syncthreads();
-  fused_layer(bufA, p.Wp + 2 * kFW * kFW, p.nh, p.no, acc);
-
-  // ---- outputs F = 10^(y sd + mu) P_abs and their per-cell sum
-  const int wr = wave >> 1, wc = wave & 1;
-  double rs[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) rs[r] = 0.0;
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    const int col = wc * 128 + cb * 32 + (lane & 31);
-    if (wc * 128 + cb * 32 >= p.no || col >= p.no) continue;
-    const float bcol = p.b3[col], sd = p.y_sd[col], mu = p.y_mu[col];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      // 10^z in FP32: the network's own error (BF16 operands, ~1e-3) dwarfs
-      // the exponential's (~1e-7 relative)
-      const float y = acc[cb][r] + bcol;
-      const double F = sPabs[row] > 0.0 ? (double)exp10f(y * sd + mu) * sPabs[row] : 0.0;
-      if (c0 + row < p.n) p.out[(c0 + row) * p.no + col] = F;
-      rs[r] += F;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    double v = rs[r];
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((lane & 31) == 0) sRow[wc * kFT + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kFT && c0 + threadIdx.x < p.n) {
-    const int row = threadIdx.x;
-    const double tot = sRow[row] + sRow[kFT + row], pa = sPabs[row];
-    const int bal = !(fabs(tot - pa) <= p.tol * pa);
-    p.ood[c0 + row] = (uint8_t)(sBad[row] | (bal << 1));
-    p.pabs[c0 + row] = pa;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Persistent fused inference with the weights on chip for the whole kernel.
-// One workgroup of 8 waves per CU; wave w owns output columns 32 w .. 32 w +
-// 31 of every layer.  The second and third layers' slices of the zero-padded
-// [256][256] bfloat16 matrices stay in the wave's registers (16 K-steps of one
-// 16-byte MFMA B fragment each: 128 VGPRs); the first layer's matrix (K
-// padded to 16 K1S) sits in LDS.  So the weights are read from memory once
-// per CU instead of once per cell tile.  Cells go 32 at a time (the M of
-// v_mfma_f32_32x32x16_bf16): features into LDS, three layers, each one MFMA
-// tile per wave and K-step, activations through two LDS buffers; the next
-// tile's field is loaded while the current one runs through the layers.
-// Same instruction, operand layout and k order as k_mlp_infer and k_gemm, so
-// the products are the same.
-constexpr int kRT = 32;          // cells per tile
-constexpr int kRW = 8;           // waves per workgroup
-constexpr int kRK = kFW / 16;    // K-steps of the second and third layers (zero-padded to 256)
-
-// LDS row stride of the first layer's matrix: K1S K-steps plus 8 (banks spread)
-__host__ __device__ constexpr int w1_stride(int k1s) { return 16 * k1s + 8; }
-
-size_t resident_lds(int nl, int k1s) {
-  return sizeof(uint16_t) * ((size_t)kFW * w1_stride(k1s) + 2 * kRT * kFP) +
-         sizeof(double) * (kRT + kRW * kRT + 2 * (size_t)nl) + sizeof(float) * 4 * kFW + sizeof(int) * kRT;
-}
-
-__device__ __forceinline__ void resident_layer(const uint16_t* act, const u16x8 (&w)[kRK], f32x16& acc) {
-  const int lane = threadIdx.x & 63;
-  const uint16_t* arow = act + (lane & 31) * kFP + 8 * (lane >> 5);
-  acc = f32x16{};
+// Sums over the wave's 64 lanes of 8 per-lane values v[r] (r = 0..7), by
+// halving: at each exchange a lane keeps the half of its values selected by
+// one bit of its index and sends the other half.  Returns, on lane L, the
+// total of value r = (L >> 3) & 7.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane) {
+  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  double w[4], u[2];
 #pragma unroll
-  for (int k = 0; k < kRK; ++k) {
-    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + 16 * k);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, w[k]),
-                                                  acc, 0, 0, 0);
-  }
-}
-
-// first layer: B fragments from the LDS copy of the matrix
-template <int K1S>
-__device__ __forceinline__ void resident_layer1(const uint16_t* act, const uint16_t* w1, f32x16& acc) {
-  const int lane = threadIdx.x & 63, col = (threadIdx.x >> 6) * 32 + (lane & 31);
-  const uint16_t* arow = act + (lane & 31) * kFP + 8 * (lane >> 5);
-  const uint16_t* wrow = w1 + col * w1_stride(K1S) + 8 * (lane >> 5);
-  acc = f32x16{};
+  for (int k = 0; k < 4; ++k) w[k] = (b5 ? v[4 + k] : v[k]) + __shfl_xor(b5 ? v[k] : v[4 + k], 32);
 #pragma unroll
-  for (int k = 0; k < K1S; ++k) {
-    const u16x8 a = *reinterpret_cast<const u16x8*>(arow + 16 * k);
-    const u16x8 b = *reinterpret_cast<const u16x8*>(wrow + 16 * k);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                  acc, 0, 0, 0);
-  }
+  for (int k = 0; k < 2; ++k) u[k] = (b4 ? w[2 + k] : w[k]) + __shfl_xor(b4 ? w[k] : w[2 + k], 16);
+  double x = (b3 ? u[1] : u[0]) + __shfl_xor(b3 ? u[0] : u[1], 8);
+  x += __shfl_xor(x, 4);
+  x += __shfl_xor(x, 2);
+  x += __shfl_xor(x, 1);
+  return x;
 }
 
-__device__ __forceinline__ void resident_hidden(const f32x16& acc, float bias, bool on, uint16_t* dst) {
-  const int lane = threadIdx.x & 63, col = (threadIdx.x >> 6) * 32 + (lane & 31);
+// Sums over the 16 lanes of each quarter-wave of 16 per-lane values v[s].
+// Returns, on lane L, the total of value s = L & 15 over its quarter.
+__device__ __forceinline__ double quarter_sum16(const double (&v)[16], int lane) {
+  const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+  double w[8], u[4], t[2];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    dst[row * kFP + col] = on ? f2bf(silu(acc[r] + bias)) : (uint16_t)0;
-  }
+  for (int k = 0; k < 8; ++k) w[k] = (b3 ? v[8 + k] : v[k]) + __shfl_xor(b3 ? v[k] : v[8 + k], 8);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = (b2 ? w[4 + k] : w[k]) + __shfl_xor(b2 ? w[k] : w[4 + k], 4);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) t[k] = (b1 ? u[2 + k] : u[k]) + __shfl_xor(b1 ? u[k] : u[2 + k], 2);
+  return (b0 ? t[1] : t[0]) + __shfl_xor(b0 ? t[0] : t[1], 1);
 }
 
-// K1S: K-steps of the first layer (13 covers the 201 inputs of the PAH model)
-template <int K1S>
-__global__ void __launch_bounds__(kRW * 64, 1) k_mlp_infer_resident(const InferP p) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char rsm[];
-  uint16_t* sW1 = reinterpret_cast<uint16_t*>(rsm);                 // [256][w1_stride]
-  uint16_t* bufA = sW1 + kFW * w1_stride(K1S);                       // [32][kFP]
-  uint16_t* bufB = bufA + kRT * kFP;                                 // [32][kFP]
-  double* sPabs = reinterpret_cast<double*>(bufB + kRT * kFP);       // [32]
-  double* sRow = sPabs + kRT;                                        // [8][32]
-  double* sCa = sRow + kRW * kRT;                                    // [nl] cabs
-  double* sDn = sCa + p.nl;                                          // [nl] dnu
-  float* sMu = reinterpret_cast<float*>(sDn + p.nl);                 // [256] x_mu, x_sd, x_lo, x_hi
-  float* sSd = sMu + kFW;
-  float* sLo = sSd + kFW;
+__device__ __forceinline__ double bcast_f64(double x, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, src), hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer access to one tile's rows: offsets at or past the byte count
+// read zero and drop writes (the hardware's range check), so rows past the
+// end of the arrays and masked columns need no branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr uint32_t kOffOut = 0x40000000u;     // an offset past every tile's range
+
+// four waves per SIMD: two workgroups per CU
+__global__ void __launch_bounds__(kTW * 64, 4) k_mlp_infer(const InferP p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char tsm[];
+  uint16_t* bufA = reinterpret_cast<uint16_t*>(tsm);                // [64][kFP]
+  uint16_t* bufB = bufA + kTT * kFP;                                 // [64][kFP]
+  double* sPabs = reinterpret_cast<double*>(bufB + kTT * kFP);       // [64]
+  double* sW = sPabs + kTT;                                          // [256] cabs dnu (zero past n_lambda)
+  float* sMu = reinterpret_cast<float*>(sW + kFW);                   // [256] per input: x_mu, 1 / x_sd,
+  float* sRs = sMu + kFW;                                            //   x_lo - margin, x_hi + margin
+  float* sLo = sRs + kFW;
   float* sHi = sLo + kFW;
-  int* sBad = reinterpret_cast<int*>(sHi + kFW);                     // [32]
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* sB1 = sHi + kFW;                                            // [256] per unit: b1, b2, b3, y_mu, y_sd
+  float* sB2 = sB1 + kFW;
+  float* sB3 = sB2 + kFW;
+  float* sYm = sB3 + kFW;
+  float* sYs = sYm + kFW;
+  int* sBad = reinterpret_cast<int*>(sYs + kFW);                     // [64]
+  double* sRow = reinterpret_cast<double*>(bufB);                    // [8][64] row sums (bufB is free then)
   const int nl = p.nl, ni = p.ni, nh = p.nh, no = p.no;
-  const int col = wave * 32 + (lane & 31);
 
-  for (int j = threadIdx.x; j < nl; j += kRW * 64) {
-    sCa[j] = p.cabs[j];
-    sDn[j] = p.dnu[j];
-  }
-  for (int j = threadIdx.x; j < kFW; j += kRW * 64) {
+  for (int j = threadIdx.x; j < kFW; j += kTW * 64) {
+    sW[j] = j < nl ? p.cabs[j] * p.dnu[j] : 0.0;
     const bool in = j < ni;
     sMu[j] = in ? p.x_mu[j] : 0.0f;
-    sSd[j] = in ? p.x_sd[j] : 1.0f;
-    sLo[j] = in ? p.x_lo[j] : 0.0f;
-    sHi[j] = in ? p.x_hi[j] : 0.0f;
+    sRs[j] = in ? 1.0f / p.x_sd[j] : 1.0f;
+    sLo[j] = in ? p.x_lo[j] - p.margin : 0.0f;
+    sHi[j] = in ? p.x_hi[j] + p.margin : 0.0f;
+    sB1[j] = j < nh ? p.b1[j] : 0.0f;
+    sB2[j] = j < nh ? p.b2[j] : 0.0f;
+    sB3[j] = j < no ? p.b3[j] : 0.0f;
+    sYm[j] = j < no ? p.y_mu[j] : 0.0f;
+    sYs[j] = j < no ? p.y_sd[j] : 0.0f;
   }
-  // this wave's weight slices: B fragment of K-step k is
-  // W[col][16 k + 8 (lane >> 5) .. + 7] of the padded matrix
-  // first layer's matrix into LDS, 16 bytes at a time
-  for (int q = threadIdx.x; q < kFW * 2 * K1S; q += kRW * 64) {
-    const int r = q / (2 * K1S), k8 = q - r * 2 * K1S;
-    *reinterpret_cast<u16x8*>(sW1 + r * w1_stride(K1S) + 8 * k8) =
-        *reinterpret_cast<const u16x8*>(p.Wp + (size_t)r * kFW + 8 * k8);
-  }
-  u16x8 w2[kRK], w3[kRK];
-  {
-    const uint16_t* r0 = p.Wp + (size_t)col * kFW + 8 * (lane >> 5);
-#pragma unroll
-    for (int k = 0; k < kRK; ++k) {
-      w2[k] = *reinterpret_cast<const u16x8*>(r0 + kFW * kFW + 16 * k);
-      w3[k] = *reinterpret_cast<const u16x8*>(r0 + 2 * kFW * kFW + 16 * k);
-    }
-  }
-  const float b1 = col < nh ? p.b1[col] : 0.0f, b2 = col < nh ? p.b2[col] : 0.0f;
-  const float b3 = col < no ? p.b3[col] : 0.0f;
-  const float ymu = col < no ? p.y_mu[col] : 0.0f, ysd = col < no ? p.y_sd[col] : 0.0f;
-
-  // field of this wave's 4 rows of a tile: bins lane + 64 q (n_lambda <= 256)
-  constexpr int kR = kRT / kRW;
-  float Jv[kR][4];
-  // unconditional loads from clamped addresses, out-of-range values zeroed
-  // afterwards: a load under a branch makes the compiler wait for it before
-  // the next one, which would serialise the sixteen loads of a lane
-  auto load_tile = [&](int64_t c0) {
-#pragma unroll
-    for (int rr = 0; rr < kR; ++rr) {
-      const int64_t c = c0 + wave * kR + rr;
-      const int64_t cc = c < p.n ? c : p.n - 1;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = lane + 64 * q;
-        Jv[rr][q] = p.J[cc * nl + (j < nl ? j : 0)];
-      }
-    }
-#pragma unroll
-    for (int rr = 0; rr < kR; ++rr) {
-      const bool cin = c0 + wave * kR + rr < p.n;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Jv[rr][q] = (cin && lane + 64 * q < nl) ? Jv[rr][q] : 0.0f;
-    }
-  };
-  const int64_t n_tiles = (p.n + kRT - 1) / kRT;
-  int64_t t = blockIdx.x;
-  if (t < n_tiles) load_tile(t * kRT);
   __syncthreads();
-  for (; t < n_tiles; t += gridDim.x) {
-    const int64_t c0 = t * kRT;
-    // ---- features of the tile's 32 cells (wave w: rows 4 w .. 4 w + 3)
-    double sum[kR];
+
+  const int64_t n_tiles = (p.n + kTT - 1) / kTT;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t c0 = t * kTT;
+    // the thread index is opaque to the compiler each tile, so that per-row
+    // and per-bin addresses and constants are formed (or read from LDS) where
+    // they are used instead of being kept in registers across the tile loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int fw = tid >> 6, jb = tid & 63;
+    const int rows = p.n - c0 < kTT ? (int)(p.n - c0) : kTT;
+    // ---- features of the tile's cells (wave w: rows 8 w .. 8 w + 7; bins
+    // lane + 64 q, n_lambda <= 255).  One buffer range per row: bins past
+    // n_lambda and rows past the end read zero.
+    const int fwu = __builtin_amdgcn_readfirstlane(fw);
+    float Jv[kTR][4];
 #pragma unroll
-    for (int rr = 0; rr < kR; ++rr) {
+    for (int rr = 0; rr < kTR; ++rr) {
+      const int64_t c = c0 + fwu * kTR + rr;
+      const __amdgpu_buffer_rsrc_t jr = tile_rsrc(p.J + c * nl, c < p.n ? 4u * (uint32_t)nl : 0u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Jv[rr][q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(jr, 4u * jb + 256u * q, 0, 0));
+    }
+    // absorbed power per cell in FP64: sum over bins of C_abs J dnu; then
+    // lane L finishes row 8 w + ((L >> 3) & 7): P_abs, its reciprocal and
+    // the last input log10 P_abs (mantissa in FP32 plus exponent)
+    double v[kTR];
+#pragma unroll
+    for (int rr = 0; rr < kTR; ++rr) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = lane + 64 * q;
-        if (j < nl) s += sCa[j] * (double)Jv[rr][q] * sDn[j];
-      }
-      sum[rr] = s;
+      for (int q = 0; q < 4; ++q) s = fma(sW[jb + 64 * q], (double)Jv[rr][q], s);
+      v[rr] = s;
     }
+    const double tot = wave_sum8(v, jb);
+    const double inv_l = tot > 0.0 ? 1.0 / tot : 0.0;
+    const double pa_l = 4.0 * kPi * tot;
+    int e2 = 0;
+    const float m2 = (float)frexp(fmax(pa_l, 1e-300), &e2);
+    const float lpa_l = log10f(m2) + (float)e2 * 0.301029995663981f;
+    if ((jb & 7) == 0) sPabs[fw * kTR + (jb >> 3)] = pa_l;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int rr = 0; rr < kR; ++rr) sum[rr] += __shfl_xor(sum[rr], off);
-#pragma unroll
-    for (int rr = 0; rr < kR; ++rr) {
-      const int row = wave * kR + rr;
-      const bool valid = c0 + row < p.n;
-      const double inv = sum[rr] > 0.0 ? 1.0 / sum[rr] : 0.0;
-      const double pa = 4.0 * kPi * sum[rr];
-      int bad = 0;
+    for (int rr = 0; rr < kTR; ++rr) {
+      const int row = fw * kTR + rr;
+      const double inv = bcast_f64(inv_l, 8 * rr), pa = bcast_f64(pa_l, 8 * rr);
+      const float lpa = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(uint32_t, lpa_l), 8 * rr));
+      bool bad = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int j = lane + 64 * q;
-        uint16_t h = 0;
-        if (valid && j < ni) {
-          const float f = j < nl ? (float)(sCa[j] * (double)Jv[rr][q] * sDn[j] * inv)
-                                 : (float)log10(fmax(pa, 1e-300));
-          const float x = (f - sMu[j]) / sSd[j];
-          if (x < sLo[j] - p.margin || x > sHi[j] + p.margin) bad = 1;
-          h = f2bf(x);
+        // Every operand is read unconditionally (a read under a condition
+        // becomes a branch).  Past the inputs (j >= n_in) the tables hold
+        // C_abs dnu = 0, x_mu = 0, 1 / x_sd = 1 and a range [0, 0], so x = 0
+        // exactly there, never flagged and multiplied by zero weights; a row
+        // past the end has a zero field and finite inputs, and no outputs.
+        const int j = jb + 64 * q;
+        const double w = sW[j];
+        const float mu = sMu[j], rsd = sRs[j], lo = sLo[j], hi = sHi[j];
+        const float fj = (float)(w * (double)Jv[rr][q] * inv);
+        const float x = ((j == nl ? lpa : fj) - mu) * rsd;
+        bad |= (x < lo) | (x > hi);
+        bufA[row * kFP + j] = bf16_rne(x);
+      }
+      // a dark cell (no absorbed power) has the exact answer F = 0 (the
+      // molecule stays in its ground state), whatever its inputs look like
+      const int flag = __any(bad) && pa > 0.0;
+      if (jb == 0) sBad[row] = flag;
+    }
+    __syncthreads();
+
+    f32x4 acc[4][2];
+    tile_layer(bufA, p.Wp, acc);
+    tile_hidden(acc, sB1, bufB);
+    __syncthreads();
+    tile_layer(bufB, p.Wp + kFW * kFW, acc);
+    tile_hidden(acc, sB2, bufA);
+    __syncthreads();
+    tile_layer(bufA, p.Wp + 2 * kFW * kFW, acc);
+
+    // ---- outputs F = 10^(y sd + mu) P_abs and their per-cell sums over this
+    // wave's 32 columns.  10^z = 2^(z log2 10) in FP32 (relative error
+    // ~1e-6 at |z| ~ 10): the network's own error (BF16 operands, ~1e-3)
+    // dwarfs it
+    int ot = threadIdx.x;
+    asm volatile("" : "+v"(ot));
+    const int lane = ot & 63, wave = ot >> 6;
+    // z log2 10 = y' a + c with a = sd log2 10, c = (b3 sd + mu) log2 10;
+    // a column past the network's width has a = 0, c = -inf (F = 0).  The
+    // exponent is capped at 2^127 so that F stays finite and a dark cell's
+    // F = 10^z * 0 is exactly zero.
+    float ea[2], ec[2];
+    uint32_t co[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int col = wave * 32 + 16 * cb + (lane & 15);
+      const bool on = col < no;
+      ea[cb] = on ? sYs[col] * 3.32192809488736f : 0.0f;
+      ec[cb] = on ? fmaf(sB3[col], sYs[col], sYm[col]) * 3.32192809488736f : -__builtin_inff();
+      co[cb] = on ? 8u * col : kOffOut;
+    }
+    const __amdgpu_buffer_rsrc_t orr = tile_rsrc(p.out + c0 * no, (uint32_t)(rows * no) * 8u);
+    double rs[16];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * mb + 4 * (lane >> 4) + i;
+        const double pa = fmax(sPabs[row], 0.0);
+        const uint32_t ro = 8u * (uint32_t)(row * no);
+        double F2 = 0.0;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const float e = __builtin_amdgcn_exp2f(fminf(fmaf(acc[mb][cb][i], ea[cb], ec[cb]), 127.0f));
+          const double F = (double)e * pa;
+          const uint64_t fb = __builtin_bit_cast(uint64_t, F);
+          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+          const u32x2 fv = {(uint32_t)fb, (uint32_t)(fb >> 32)};
+          __builtin_amdgcn_raw_buffer_store_b64(fv, orr, ro + co[cb], 0, 0);
+          F2 += F;
         }
-        bufA[row * kFP + j] = h;
+        rs[4 * mb + i] = F2;
       }
-      // a dark cell (no absorbed power) has the exact answer F = 0
-      bad = __any(bad) && pa > 0.0;
-      if (lane == 0) {
-        sBad[row] = bad;
-        sPabs[row] = pa;
-      }
-    }
-    // the next tile's field goes in flight behind the three layers
-    if (t + gridDim.x < n_tiles) load_tile((t + gridDim.x) * kRT);
-    __syncthreads();
-
-    f32x16 acc;
-    resident_layer1<K1S>(bufA, sW1, acc);
-    resident_hidden(acc, b1, col < nh, bufB);
-    __syncthreads();
-    resident_layer(bufB, w2, acc);
-    resident_hidden(acc, b2, col < nh, bufA);
-    __syncthreads();
-    resident_layer(bufA, w3, acc);
-
-    // ---- outputs F = 10^(y sd + mu) P_abs and their per-cell sums over
-    // this wave's 32 columns (one row at a time: few live registers)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      double F = 0.0;
-      if (col < no) {
-        const float y = acc[r] + b3;
-        F = sPabs[row] > 0.0 ? (double)exp10f(y * ysd + ymu) * sPabs[row] : 0.0;
-        if (c0 + row < p.n) p.out[(c0 + row) * no + col] = F;
-      }
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) F += __shfl_xor(F, off);
-      if ((lane & 31) == 0) sRow[wave * kRT + row] = F;
+    {
+      // lane L: sum over this wave's columns of row 16 (s >> 2) + 4 (L >> 4) + (s & 3), s = L & 15
+      const double x = quarter_sum16(rs, lane);
+      const int s16 = lane & 15;
+      sRow[wave * kTT + 16 * (s16 >> 2) + 4 * (lane >> 4) + (s16 & 3)] = x;
     }
     __syncthreads();
-    if (threadIdx.x < kRT && c0 + threadIdx.x < p.n) {
+    if (threadIdx.x < kTT && c0 + threadIdx.x < p.n) {
       const int row = threadIdx.x;
       double tot = 0.0;
-      for (int w = 0; w < kRW; ++w) tot += sRow[w * kRT + row];
+      for (int w = 0; w < kTW; ++w) tot += sRow[w * kTT + row];
       const double pa = sPabs[row];
       const int bal = !(fabs(tot - pa) <= p.tol * pa);
       p.ood[c0 + row] = (uint8_t)(sBad[row] | (bal << 1));
@@ -893,7 +781,7 @@ __global__ void __launch_bounds__(kRW * 64, 1) k_mlp_infer_resident(const InferP
 
 struct pah_mlp {
   int ni, nh, no, batch;
-  int resident_blocks = -1;         // grid of the persistent inference kernel
+  int infer_blocks = -1;            // grid of the persistent inference kernel
   MlpLayout L;
   unsigned char* st = nullptr;
   std::string err;
@@ -1114,7 +1002,7 @@ int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int6
   if (!dnu) return mfail(m, MCRT_E_STATE, "PAH tables not built");
   const MlpLayout& L = m->L;
   if (n == 0) return MCRT_OK;
-  if (m->ni <= 13 * 16 && m->nh <= kFW && m->no <= kFW) {
+  if (m->ni <= kFW && m->nh <= kFW && m->no <= kFW) {
     k_pack<<<(3 * kFW * kFW + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.W1h), at<uint16_t>(m, L.W2h),
                                                         at<uint16_t>(m, L.W3h), m->ni, m->nh, m->no,
                                                         at<uint16_t>(m, L.Wpk));
@@ -1129,40 +1017,19 @@ int32_t pah_surrogate_infer(pah_mlp* m, const pah_ctx* ctx, const float* J, int6
     p.Wp = at<uint16_t>(m, L.Wpk);
     p.margin = in_margin; p.tol = balance_tol;
     p.out = out; p.ood = ood; p.pabs = pabs;
-    if (m->resident_blocks < 0) {
+    if (m->infer_blocks < 0) {
       int dev = 0, ncu = 0, per_cu = 0;
       if (hipGetDevice(&dev) != hipSuccess ||
           hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         ncu = 256;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_infer_resident<13>, kRW * 64,
-                                                       resident_lds(d.n_lambda, 13)) != hipSuccess || per_cu < 1)
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_infer, kTW * 64, tile_lds(d.n_lambda)) !=
+              hipSuccess || per_cu < 1)
         per_cu = 1;
-      m->resident_blocks = ncu * per_cu;
+      m->infer_blocks = ncu * per_cu;
     }
-    const int64_t tiles = (n + kRT - 1) / kRT;
-    const int64_t blocks = tiles < m->resident_blocks ? tiles : m->resident_blocks;
-    k_mlp_infer_resident<13><<<(unsigned)blocks, kRW * 64, resident_lds(d.n_lambda, 13), s>>>(p);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
-    return MCRT_OK;
-  }
-  if (m->ni <= kFW && m->nh <= kFW && m->no <= kFW) {
-    // wider inputs: the weights stay in L2, 64 cells per workgroup
-    k_pack<<<(3 * kFW * kFW + 255) / 256, 256, 0, s>>>(at<uint16_t>(m, L.W1h), at<uint16_t>(m, L.W2h),
-                                                        at<uint16_t>(m, L.W3h), m->ni, m->nh, m->no,
-                                                        at<uint16_t>(m, L.Wpk));
-    InferP p{};
-    p.J = J; p.n = n; p.nl = d.n_lambda; p.ni = m->ni; p.nh = m->nh; p.no = m->no;
-    p.cabs = d.cabs; p.dnu = dnu;
-    p.x_mu = at<float>(m, L.x_mu); p.x_sd = at<float>(m, L.x_sd);
-    p.x_lo = at<float>(m, L.x_lo); p.x_hi = at<float>(m, L.x_hi);
-    p.y_mu = at<float>(m, L.y_mu); p.y_sd = at<float>(m, L.y_sd);
-    const float* P = at<float>(m, L.params);
-    p.b1 = P + L.ob1; p.b2 = P + L.ob2; p.b3 = P + L.ob3;
-    p.Wp = at<uint16_t>(m, L.Wpk);
-    p.margin = in_margin; p.tol = balance_tol;
-    p.out = out; p.ood = ood; p.pabs = pabs;
-    k_mlp_infer<<<(unsigned)((n + kFT - 1) / kFT), 256, fused_lds(), s>>>(p);
+    const int64_t tiles = (n + kTT - 1) / kTT;
+    const int64_t blocks = tiles < m->infer_blocks ? tiles : m->infer_blocks;
+    k_mlp_infer<<<(unsigned)blocks, kTW * 64, tile_lds(d.n_lambda), s>>>(p);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mfail(m, MCRT_E_HIP, hipGetErrorString(e));
     return MCRT_OK;
