@@ -311,7 +311,10 @@ def hard_photon_block(stream):
         rows.append({"hnu_ev": float(e), "T_median": q(0.5), "T_99": q(0.99), "T_9999": q(0.9999),
                      "P_above_1000K": float(P[k][T > 1000.0].sum())})
     return {"n_c": 100, "flux": case["flux"], "M": len(T), "n_lambda": len(case["lam"]),
-            "solve_ms_6_fields": e0.elapsed_time(e1), "P_of_T": rows}
+            "solve_ms_6_fields": e0.elapsed_time(e1), "P_of_T": rows,
+            "energy_deposition": "every absorbed photon deposits its full energy (the Dwek & Smith loss of "
+                                 "kinetic energy above 100 eV is not modelled): the 300 eV and 1 keV "
+                                 "distributions are upper bounds on the heating"}
 
 
 def random_load_rate(n_load, stream):

@@ -489,14 +489,20 @@ def test_pah_reemission_in_transport_equals_oracle():
     assert np.array_equal(g["jq"], o["jq"].reshape(-1))
 
 
-def test_pah_loop_iterates():
+def test_pah_loop_converges():
+    # the PAH iteration from the thin starlight field: the first pass moves
+    # the emitted band power a lot, later passes by less and less, and the
+    # iteration stops once the change is below the 1 % tolerance (the noise
+    # of a pass of 1e6 packets is a few tenths of a per cent here)
     from paper_1201_3588_amd.pipeline import PahLoop
-    w = synth.small_disk(n_packets=200000, nl=200, n_sizes=1, nb=16, with_pah=True)
-    res = PahLoop(w).run(n_iter=3)
+    w = synth.small_disk(n_packets=1_000_000, nl=200, n_sizes=1, nb=16, with_pah=True)
+    res = PahLoop(w).run(n_iter=6, tol=0.01)
     h = res["history"]
-    assert len(h) >= 2 and all(x["pah_abs"] > 0 for x in h)
+    ch = [x["change"] for x in h[1:]]
+    assert len(h) >= 3 and all(x["pah_abs"] > 1000 for x in h)
     conservation(host(res["tallies"]), w.n_packets)
-    assert h[-1]["change"] < 0.2
+    assert ch[0] > 0.05, ch
+    assert ch[-1] < 0.01 and ch[-1] < 0.2 * ch[0], ch
 
 
 def test_exact_bw_correction_vanishes_with_many_absorptions():
