@@ -67,10 +67,11 @@ Layout make_layout(const mcrt_desc& d);
 // line each: a packet stepping to a neighbour in y or z then stays in the
 // line half of the time (in raster order never), in x three times in four.
 // Bricks are in raster order over ceil(nb/4) x ceil(nb/2) x ceil(nb/2).
-__host__ __device__ __forceinline__ int64_t binfo_index(int nb, int bx, int by, int bz) {
-  const int64_t nx4 = (nb + 3) >> 2, ny2 = (nb + 1) >> 1;
-  const int64_t brick = ((int64_t)(bz >> 1) * ny2 + (by >> 1)) * nx4 + (bx >> 2);
-  return brick * 16 + (((bz & 1) << 3) | ((by & 1) << 2) | (bx & 3));
+// (32-bit arithmetic: nb^3 <= 2^31 keeps every index below 2^32.)
+__host__ __device__ __forceinline__ uint32_t binfo_index(int nb, int bx, int by, int bz) {
+  const uint32_t nx4 = (uint32_t)(nb + 3) >> 2, ny2 = (uint32_t)(nb + 1) >> 1;
+  const uint32_t brick = ((uint32_t)(bz >> 1) * ny2 + (uint32_t)(by >> 1)) * nx4 + (uint32_t)(bx >> 2);
+  return brick * 16u + (uint32_t)(((bz & 1) << 3) | ((by & 1) << 2) | (bx & 3));
 }
 __host__ __device__ __forceinline__ uint64_t binfo_entries(int nb) {
   return (uint64_t)((nb + 3) >> 2) * (uint64_t)((nb + 1) >> 1) * (uint64_t)((nb + 1) >> 1) * 16;

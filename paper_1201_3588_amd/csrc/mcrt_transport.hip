@@ -118,9 +118,13 @@ __device__ __forceinline__ int locate(const TP<R>& P, int F0, int F1, int F2, in
   if ((unsigned)F0 >= ext || (unsigned)F1 >= ext || (unsigned)F2 >= ext) return -1;
   int e;
   if (sizeof(R) == 4) {
-    const int2 bi = P.binfo[binfo_index(nb, F0 >> L, F1 >> L, F2 >> L)];
-    e = bi.x;
-    dens = (R)__int_as_float(bi.y);
+    // one 8-byte load, both halves materialised at once (otherwise the
+    // compiler defers the density half past the refined-cube test, a second
+    // dependent load per crossing)
+    uint64_t raw = *reinterpret_cast<const uint64_t*>(P.binfo + binfo_index(nb, F0 >> L, F1 >> L, F2 >> L));
+    asm volatile("" : "+v"(raw));
+    e = (int)(uint32_t)raw;
+    dens = (R)__uint_as_float((uint32_t)(raw >> 32));
   } else {
     e = P.base_map[(F0 >> L) + nb * ((F1 >> L) + nb * (F2 >> L))];
   }
@@ -316,11 +320,28 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   uint64_t pid = 0, kidx = 0;
   uint32_t events = 0;
   R u0 = 0, u1 = 0, u2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0, dens = 0;
-  R r0 = 0, r1 = 0, r2 = 1;                 // 1/d (FP32 path)
+  // FP32 path: 1/d per axis, and an additive term that puts the exit along
+  // an axis the direction does not move along (1/d not finite) at infinity
+  R r0 = 0, r1 = 0, r2 = 1, p0 = 0, p1 = 0, p2 = 0;
   auto set_recip = [&]() {
-    if (sizeof(R) == 4) { r0 = R(1) / d0; r1 = R(1) / d1; r2 = R(1) / d2; }
+    if (sizeof(R) == 4) {
+      auto one = [](R d, R& r, R& pen) {
+        const R q = R(1) / d;
+        const bool fin = __builtin_isfinite(q);
+        r = fin ? q : R(0);
+        pen = fin ? R(0) : (R)INFINITY;
+      };
+      one(d0, r0, p0);
+      one(d1, r1, p1);
+      one(d2, r2, p2);
+    }
   };
   int j = 0, cell = 0, lev = 0, lo0 = 0, lo1 = 0, lo2 = 0;
+  // record key of the current bin (deferred tally): (j * n_cells) << 24
+  unsigned long long jkey = 0;
+  auto set_jkey = [&]() {
+    if (DEFER) jkey = (unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells) << kRecValBits;
+  };
   // frequent counters in registers, rare ones in LDS
   uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
   auto bump = [&](int k) { atomicAdd(&s_cnt[k], 1u); };
@@ -380,6 +401,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
             uint32_t w[4];
             philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), 0u, 0u, key0, key1, w);
             j = cdf_search(s_src, P.nl, u24(w[0]));
+            set_jkey();
             if (P.beam_on) { d0 = P.bx; d1 = P.by; d2 = P.bz; }
             else {
               const R mu = (R)(2.0 * u24(w[1]) - 1.0);
@@ -424,23 +446,31 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
       const R side = (R)span * inv_nf;
       R tex = (R)INFINITY;
       int ax = -1;
-      {
-        // FP32: multiply by the direction's reciprocals (one rounding more than
-        // a division, well inside FP32 geometry tolerance); FP64: divide, as the
-        // definition does
+      if (sizeof(R) == 4) {
+        // FP32: the distance to the face the direction points to, per axis,
+        // by the direction's reciprocals (one rounding more than a division,
+        // well inside FP32 geometry tolerance; an axis not moved along is at
+        // infinity); the lowest axis wins ties.  No branches.
+        const R t0 = fmax(fma(d0 > R(0) ? side - u0 : -u0, r0, p0), R(0));
+        const R t1 = fmax(fma(d1 > R(0) ? side - u1 : -u1, r1, p1), R(0));
+        const R t2 = fmax(fma(d2 > R(0) ? side - u2 : -u2, r2, p2), R(0));
+        tex = fmin(t0, fmin(t1, t2));
+        ax = (t0 <= t1 && t0 <= t2) ? 0 : (t1 <= t2 ? 1 : 2);
+      } else {
+        // FP64: divide, as the definition does
         R t;
         if (d0 != R(0)) {
-          t = sizeof(R) == 4 ? (d0 > R(0) ? side - u0 : -u0) * r0 : (d0 > R(0) ? side - u0 : -u0) / d0;
+          t = (d0 > R(0) ? side - u0 : -u0) / d0;
           t = t < R(0) ? R(0) : t;
           if (t < tex) { tex = t; ax = 0; }
         }
         if (d1 != R(0)) {
-          t = sizeof(R) == 4 ? (d1 > R(0) ? side - u1 : -u1) * r1 : (d1 > R(0) ? side - u1 : -u1) / d1;
+          t = (d1 > R(0) ? side - u1 : -u1) / d1;
           t = t < R(0) ? R(0) : t;
           if (t < tex) { tex = t; ax = 1; }
         }
         if (d2 != R(0)) {
-          t = sizeof(R) == 4 ? (d2 > R(0) ? side - u2 : -u2) * r2 : (d2 > R(0) ? side - u2 : -u2) / d2;
+          t = (d2 > R(0) ? side - u2 : -u2) / d2;
           t = t < R(0) ? R(0) : t;
           if (t < tex) { tex = t; ax = 2; }
         }
@@ -454,9 +484,10 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
         const R s = tau / alpha;
         u0 += s * d0; u1 += s * d1; u2 += s * d2;
         if (tally_j && dusty) {
-          const unsigned long long q = (unsigned long long)rrint(s * P.qscale);
+          // lengths are below 2^24 units of the finest cell / 2^16
+          const unsigned long long q = (unsigned long long)(uint32_t)rrint(s * P.qscale);
           if (DEFER) {
-            prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+            prec = (jkey + ((unsigned long long)(uint32_t)cell << kRecValBits)) | q;
             hrec = true;
           } else {
             atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
@@ -468,9 +499,10 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
         // ---- cross the face into the neighbour
         if (alpha > R(0)) tau -= alpha * tex;
         if (tally_j && dusty) {
-          const unsigned long long q = (unsigned long long)rrint(tex * P.qscale);
+          // lengths are below 2^24 units of the finest cell / 2^16
+          const unsigned long long q = (unsigned long long)(uint32_t)rrint(tex * P.qscale);
           if (DEFER) {
-            prec = ((unsigned long long)((int64_t)j * P.n_cells + cell) << kRecValBits) | q;
+            prec = (jkey + ((unsigned long long)(uint32_t)cell << kRecValBits)) | q;
             hrec = true;
           } else {
             atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
@@ -596,6 +628,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
               j = cdf_search(row, P.nl, u24(v[0]));
               bump(9);
             }
+            set_jkey();
             const R mu = (R)(2.0 * u24(v[1]) - 1.0);
             const R st = rsqrt0(R(1) - mu * mu);
             d0 = st * cp; d1 = st * sp; d2 = mu;
