@@ -320,28 +320,22 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   uint64_t pid = 0, kidx = 0;
   uint32_t events = 0;
   R u0 = 0, u1 = 0, u2 = 0, d0 = 0, d1 = 0, d2 = 1, tau = 0, dens = 0;
-  // FP32 path: 1/d per axis, and an additive term that puts the exit along
-  // an axis the direction does not move along (1/d not finite) at infinity
-  R r0 = 0, r1 = 0, r2 = 1, p0 = 0, p1 = 0, p2 = 0;
+  // FP32 path: 1/d per axis; -inf for an axis the direction does not move
+  // along (1/d not finite), which puts that axis's exit at +inf (or NaN, on
+  // its low face, which the minimum below ignores)
+  R r0 = 0, r1 = 0, r2 = 1;
   auto set_recip = [&]() {
     if (sizeof(R) == 4) {
-      auto one = [](R d, R& r, R& pen) {
+      auto one = [](R d) {
         const R q = R(1) / d;
-        const bool fin = __builtin_isfinite(q);
-        r = fin ? q : R(0);
-        pen = fin ? R(0) : (R)INFINITY;
+        return __builtin_isfinite(q) ? q : -(R)INFINITY;
       };
-      one(d0, r0, p0);
-      one(d1, r1, p1);
-      one(d2, r2, p2);
+      r0 = one(d0);
+      r1 = one(d1);
+      r2 = one(d2);
     }
   };
   int j = 0, cell = 0, lev = 0, lo0 = 0, lo1 = 0, lo2 = 0;
-  // record key of the current bin (deferred tally): (j * n_cells) << 24
-  unsigned long long jkey = 0;
-  auto set_jkey = [&]() {
-    if (DEFER) jkey = (unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells) << kRecValBits;
-  };
   // frequent counters in registers, rare ones in LDS
   uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
   auto bump = [&](int k) { atomicAdd(&s_cnt[k], 1u); };
@@ -401,7 +395,6 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
             uint32_t w[4];
             philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), 0u, 0u, key0, key1, w);
             j = cdf_search(s_src, P.nl, u24(w[0]));
-            set_jkey();
             if (P.beam_on) { d0 = P.bx; d1 = P.by; d2 = P.bz; }
             else {
               const R mu = (R)(2.0 * u24(w[1]) - 1.0);
@@ -449,13 +442,15 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
       if (sizeof(R) == 4) {
         // FP32: the distance to the face the direction points to, per axis,
         // by the direction's reciprocals (one rounding more than a division,
-        // well inside FP32 geometry tolerance; an axis not moved along is at
-        // infinity); the lowest axis wins ties.  No branches.
-        const R t0 = fmax(fma(d0 > R(0) ? side - u0 : -u0, r0, p0), R(0));
-        const R t1 = fmax(fma(d1 > R(0) ? side - u1 : -u1, r1, p1), R(0));
-        const R t2 = fmax(fma(d2 > R(0) ? side - u2 : -u2, r2, p2), R(0));
+        // well inside FP32 geometry tolerance), negative distances clamped to
+        // 0; an axis not moved along gives +inf or NaN, and the minimum skips
+        // a NaN.  The lowest axis wins ties.  No branches.
+        auto dist = [](R w, R r) { const R x = w * r; return !(x <= R(0)) ? x : R(0); };
+        const R t0 = dist(d0 > R(0) ? side - u0 : -u0, r0);
+        const R t1 = dist(d1 > R(0) ? side - u1 : -u1, r1);
+        const R t2 = dist(d2 > R(0) ? side - u2 : -u2, r2);
         tex = fmin(t0, fmin(t1, t2));
-        ax = (t0 <= t1 && t0 <= t2) ? 0 : (t1 <= t2 ? 1 : 2);
+        ax = t0 == tex ? 0 : (t1 == tex ? 1 : 2);
       } else {
         // FP64: divide, as the definition does
         R t;
@@ -487,7 +482,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
           // lengths are below 2^24 units of the finest cell / 2^16
           const unsigned long long q = (unsigned long long)(uint32_t)rrint(s * P.qscale);
           if (DEFER) {
-            prec = (jkey + ((unsigned long long)(uint32_t)cell << kRecValBits)) | q;
+            prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell) << kRecValBits) | q;
             hrec = true;
           } else {
             atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
@@ -502,7 +497,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
           // lengths are below 2^24 units of the finest cell / 2^16
           const unsigned long long q = (unsigned long long)(uint32_t)rrint(tex * P.qscale);
           if (DEFER) {
-            prec = (jkey + ((unsigned long long)(uint32_t)cell << kRecValBits)) | q;
+            prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell) << kRecValBits) | q;
             hrec = true;
           } else {
             atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
@@ -628,7 +623,6 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
               j = cdf_search(row, P.nl, u24(v[0]));
               bump(9);
             }
-            set_jkey();
             const R mu = (R)(2.0 * u24(v[1]) - 1.0);
             const R st = rsqrt0(R(1) - mu * mu);
             d0 = st * cp; d1 = st * sp; d2 = mu;
