@@ -128,6 +128,28 @@ def test_fixed_random_traces(precision, tol, min_frac):
         assert same + len(parted) == 400
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("beam", [(0.0, 0.0, 1.0), (-1.0, 0.0, 0.0)])
+def test_axis_aligned_beam_traces(precision, tol, beam):
+    # a pencil beam along a grid axis from the star on a grid vertex: until
+    # its first scattering a packet does not move along two axes and sits on
+    # their faces, so their exits are at infinity (FP32: a reciprocal of -inf,
+    # and 0 * inf on the low face, which the minimum must skip)
+    w = synth.uniform_cube(8, 0.7, albedo=0.5, g=0.6, n_packets=400)
+    w.source.beam = np.array(beam)
+    base = oracle.Session(w).transport(n=2000)["nabs"]
+    e = engine(w, precision)
+    tal = e.new_tallies(tally_j=True)
+    gt = e.run(tal, 0, 400, w.n_packets, w.seed, frozen_nabs=base, trace_cap=600,
+               flags=mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T)
+    ot = oracle.Session(w, frozen_nabs=base).transport(0, 400, trace_cap=600)["trace"]
+    assert np.allclose(ot[0]["d"][0], beam) and ot[0]["type"][0] == 0
+    parted = []
+    same = _compare_traces(gt, ot, tol, float(w.grid.nb), parted=parted)
+    assert same >= (0.999 if precision == "f64" else 0.98) * 400, (precision, same, parted)
+    assert same + len(parted) == 400
+
+
 def disk_observers(w, npix=25):
     # face-on, edge-on and inclined views of the disk, centred on the star,
     # field of view the whole grid, three near- and mid-infrared bins; an odd
