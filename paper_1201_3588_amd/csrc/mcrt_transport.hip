@@ -67,6 +67,20 @@ struct TP {
   unsigned long long* jrec_count;
 };
 
+// The kernel's argument block, read through an address the compiler cannot
+// see through: in the launch and interaction branches the fields are loaded
+// (scalar loads from the argument segment) where they are used, instead of
+// being held in scalar registers across the whole march, where they would
+// crowd out (and spill) the values the march itself uses.
+template <typename R>
+using ArgPtr = const __attribute__((address_space(4))) TP<R>*;
+template <typename R>
+__device__ __forceinline__ ArgPtr<R> cold_args() {
+  ArgPtr<R> q = (ArgPtr<R>)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(q));
+  return q;
+}
+
 // One queued next-event: where (base-cube units, inside leaf `cell`), in which
 // bin, and for a scattering the direction the packet arrived along.
 struct PeelRec {
@@ -171,22 +185,23 @@ __device__ __forceinline__ void record(const TP<R>& P, uint64_t k, int type, int
 }
 
 template <typename R>
-__device__ __forceinline__ void escape_tally(const TP<R>& P, R d0, R d1, R d2, int j) {
-  int bt = (int)rfloor((d2 + R(1)) * R(0.5) * (R)P.n_theta);
-  bt = bt < 0 ? 0 : (bt >= P.n_theta ? P.n_theta - 1 : bt);
+__device__ __forceinline__ void escape_tally(R d0, R d1, R d2, int j) {
+  const ArgPtr<R> Q = cold_args<R>();
+  int bt = (int)rfloor((d2 + R(1)) * R(0.5) * (R)Q->n_theta);
+  bt = bt < 0 ? 0 : (bt >= Q->n_theta ? Q->n_theta - 1 : bt);
   R phi = ratan2(d1, d0);
   if (phi < R(0)) phi += R(2.0 * kPi);
-  int bp = (int)rfloor(phi / R(2.0 * kPi) * (R)P.n_phi);
-  bp = bp < 0 ? 0 : (bp >= P.n_phi ? P.n_phi - 1 : bp);
-  atomicAdd(&P.sed[((int64_t)bt * P.n_phi + bp) * P.nl + j], 1ull);
+  int bp = (int)rfloor(phi / R(2.0 * kPi) * (R)Q->n_phi);
+  bp = bp < 0 ? 0 : (bp >= Q->n_phi ? Q->n_phi - 1 : bp);
+  atomicAdd(&Q->sed[((int64_t)bt * Q->n_phi + bp) * Q->nl + j], 1ull);
 }
 
 // escape images: the exit point x (base-cube units), moved back along the ray
 // to the observer's image plane, in plane pixels (see mcrt_observers)
 template <typename R>
-__device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1, double x2, R d0, R d1,
-                                         R d2, int j) {
-  const ImgP& I = P.img;
+__device__ __forceinline__ void image_tally(double x0, double x1, double x2, R d0, R d1, R d2, int j) {
+  const ArgPtr<R> Q = cold_args<R>();
+  const __attribute__((address_space(4))) ImgP& I = Q->img;
   int l = -1;
   for (int q = 0; q < I.n_l; ++q)
     if (I.lsel[q] == j) l = q;
@@ -194,7 +209,7 @@ __device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1
   const double X0 = I.off[0] + x0 * I.h, X1 = I.off[1] + x1 * I.h, X2 = I.off[2] + x2 * I.h;
   const double e0 = d0, e1 = d1, e2 = d2;
   for (int o = 0; o < I.n_obs; ++o) {
-    const double* n = I.n[o];
+    const auto* n = I.n[o];
     const double dn = e0 * n[0] + e1 * n[1] + e2 * n[2];
     if (dn < I.cos_cone) continue;
     const double t = (X0 * n[0] + X1 * n[1] + X2 * n[2]) / dn;
@@ -211,14 +226,15 @@ __device__ __forceinline__ void image_tally(const TP<R>& P, double x0, double x1
 // out of the whole grid), or for every event when the observers' SEDs are
 // on; records past the capacity are dropped and counted by the march kernel.
 template <typename R>
-__device__ __forceinline__ void peel_push(const TP<R>& P, double x0, double x1, double x2, int cell, int j,
-                                       int type, R d0, R d1, R d2) {
-  bool imaged = P.peel_sed != nullptr;
-  for (int q = 0; q < P.img.n_l; ++q) imaged |= P.img.lsel[q] == j;
+__device__ __forceinline__ void peel_push(double x0, double x1, double x2, int cell, int j, int type, R d0, R d1,
+                                          R d2) {
+  const ArgPtr<R> Q = cold_args<R>();
+  bool imaged = Q->peel_sed != nullptr;
+  for (int q = 0; q < Q->img.n_l; ++q) imaged |= Q->img.lsel[q] == j;
   if (!imaged) return;
-  const unsigned long long k = atomicAdd(P.peel_count, 1ull);
-  if (k >= P.peel_cap) return;
-  PeelRec* r = reinterpret_cast<PeelRec*>(P.peel_q) + k;
+  const unsigned long long k = atomicAdd(Q->peel_count, 1ull);
+  if (k >= Q->peel_cap) return;
+  PeelRec* r = reinterpret_cast<PeelRec*>(Q->peel_q) + k;
   r->x[0] = x0; r->x[1] = x1; r->x[2] = x2;
   r->din[0] = (double)d0; r->din[1] = (double)d1; r->din[2] = (double)d2;
   r->cell = cell; r->j = j; r->type = type; r->pad = 0;
@@ -234,30 +250,31 @@ constexpr uint32_t kStage = 512;
 // the records go to the tally by atomic add (the tally is the same).  Every
 // lane of the wave calls it with the same (wave-uniform) arguments.
 template <typename R>
-__device__ __forceinline__ void flush_records(const TP<R>& P, const unsigned long long* rec, uint32_t n,
-                                              uint64_t& rcur, uint64_t& rleft, bool& rfull) {
+__device__ __forceinline__ void flush_records(const unsigned long long* rec, uint32_t n, uint64_t& rcur,
+                                              uint64_t& rleft, bool& rfull) {
+  const ArgPtr<R> Q = cold_args<R>();
   const int lane = __lane_id();
   uint32_t done = 0;
   while (done < n) {
     if (!rfull && rleft == 0) {
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(P.jrec_count, (unsigned long long)kRecChunk);
+      if (lane == 0) base = atomicAdd(Q->jrec_count, (unsigned long long)kRecChunk);
       base = __shfl(base, 0);
-      if (base + kRecChunk <= P.jrec_cap) {
+      if (base + kRecChunk <= Q->jrec_cap) {
         rcur = base;
         rleft = kRecChunk;
       } else {
         // buffer exhausted: neutral records (slot 0, length 0) over the part
         // of this chunk inside the buffer; direct adds from now on
-        for (uint64_t q = base + (uint64_t)lane; q < P.jrec_cap && q < base + kRecChunk; q += 64)
-          __builtin_nontemporal_store(0ull, &P.jrec[q]);
+        for (uint64_t q = base + (uint64_t)lane; q < Q->jrec_cap && q < base + kRecChunk; q += 64)
+          __builtin_nontemporal_store(0ull, &Q->jrec[q]);
         rfull = true;
       }
     }
     if (rfull) {
       for (uint32_t q = done + (uint32_t)lane; q < n; q += 64) {
         const unsigned long long r = rec[q];
-        atomicAdd(&P.jq[r >> kRecValBits], r & ((1ull << kRecValBits) - 1ull));
+        atomicAdd(&Q->jq[r >> kRecValBits], r & ((1ull << kRecValBits) - 1ull));
       }
       return;
     }
@@ -266,7 +283,7 @@ __device__ __forceinline__ void flush_records(const TP<R>& P, const unsigned lon
     // non-temporal, so they stream past the L2 lines of the grid and tables
     // that the march gathers from
     for (uint32_t q = (uint32_t)lane; q < take; q += 64)
-      __builtin_nontemporal_store(rec[done + q], &P.jrec[rcur + q]);
+      __builtin_nontemporal_store(rec[done + q], &Q->jrec[rcur + q]);
     rcur += take;
     rleft -= take;
     done += take;
@@ -361,7 +378,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
       const unsigned long long rm = __ballot(hrec);
       if (rm) {
         if (s_fill + 64u > kStage) {
-          flush_records(P, s_rec, s_fill, rcur, rleft, rfull);
+          flush_records<R>(s_rec, s_fill, rcur, rleft, rfull);
           s_fill = 0u;
         }
         const uint32_t rank = (uint32_t)__popcll(rm & lt_mask);
@@ -373,15 +390,16 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
     if (!exhausted || q_next < q_end) {
       const unsigned long long dead = __ballot(!alive);
       if (dead && (__popcll(dead) >= kRefillMin || !__any(alive))) {
+        const ArgPtr<R> Q = cold_args<R>();
         const int nd = __popcll(dead);
         if (q_next >= q_end && !exhausted) {
           const int leader = __ffsll((long long)dead) - 1;
           unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(P.work, (unsigned long long)kChunk);
+          if (lane == leader) base = atomicAdd(Q->work, (unsigned long long)kChunk);
           base = __shfl(base, leader);
           q_next = base;
-          q_end = base + kChunk < P.n ? base + kChunk : P.n;
-          if (base + kChunk >= P.n) exhausted = true;
+          q_end = base + kChunk < Q->n ? base + kChunk : Q->n;
+          if (base + kChunk >= Q->n) exhausted = true;
         }
         const uint64_t avail = q_end > q_next ? q_end - q_next : 0;
         const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
@@ -390,12 +408,12 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
           {
             // launch (event slot 0): bin from the source CDF, direction, optical depth
             if (TRACE) kidx = k;
-            pid = P.first_id + k;
+            pid = Q->first_id + k;
             events = 0;
             uint32_t w[4];
             philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), 0u, 0u, key0, key1, w);
-            j = cdf_search(s_src, P.nl, u24(w[0]));
-            if (P.beam_on) { d0 = P.bx; d1 = P.by; d2 = P.bz; }
+            j = cdf_search(s_src, Q->nl, u24(w[0]));
+            if (Q->beam_on) { d0 = Q->bx; d1 = Q->by; d2 = Q->bz; }
             else {
               const R mu = (R)(2.0 * u24(w[1]) - 1.0);
               const R st = rsqrt0(R(1) - mu * mu);
@@ -406,21 +424,21 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
             tau = -rlog((R)u24(w[3]));
             set_recip();
             const double nf = (double)(1 << L);
-            cell = locate(P, (int)floor(P.x0 * nf), (int)floor(P.y0 * nf), (int)floor(P.z0 * nf),
+            cell = locate(P, (int)floor(Q->x0 * nf), (int)floor(Q->y0 * nf), (int)floor(Q->z0 * nf),
                           lev, lo0, lo1, lo2, dens);
             const double ifn = (double)inv_nf;
-            u0 = (R)(P.x0 - (double)lo0 * ifn);
-            u1 = (R)(P.y0 - (double)lo1 * ifn);
-            u2 = (R)(P.z0 - (double)lo2 * ifn);
+            u0 = (R)(Q->x0 - (double)lo0 * ifn);
+            u1 = (R)(Q->y0 - (double)lo1 * ifn);
+            u2 = (R)(Q->z0 - (double)lo2 * ifn);
             bump(0);
-            if (IMG && P.peel_q && cell >= 0 && !P.beam_on)
-              peel_push(P, P.x0, P.y0, P.z0, cell, j, 0, d0, d1, d2);
-            if (TRACE) record(P, kidx, 0, cell, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
+            if (IMG && Q->peel_q && cell >= 0 && !Q->beam_on)
+              peel_push(Q->x0, Q->y0, Q->z0, cell, j, 0, d0, d1, d2);
+            if (TRACE) record(P, kidx, 0, cell, j, Q->x0, Q->y0, Q->z0, d0, d1, d2, tau);
             if (cell < 0) {
               bump(1);
-              escape_tally(P, d0, d1, d2, j);
-              if (IMG) image_tally(P, P.x0, P.y0, P.z0, d0, d1, d2, j);
-              if (TRACE) record(P, kidx, 4, -1, j, P.x0, P.y0, P.z0, d0, d1, d2, tau);
+              escape_tally(d0, d1, d2, j);
+              if (IMG) image_tally(Q->x0, Q->y0, Q->z0, d0, d1, d2, j);
+              if (TRACE) record(P, kidx, 4, -1, j, Q->x0, Q->y0, Q->z0, d0, d1, d2, tau);
             } else {
               alive = true;
             }
@@ -530,8 +548,8 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
         if (cell < 0) {
           bump(1);
           alive = false;
-          escape_tally(P, d0, d1, d2, j);
-          if (IMG) image_tally(P, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
+          escape_tally(d0, d1, d2, j);
+          if (IMG) image_tally(gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
           if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
         } else {
           // re-base the local position on the new leaf (exact integer offsets)
@@ -548,9 +566,10 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
       const unsigned long long hm = __ballot(hold);
       if (hm && __popcll(hm) * kHoldFrac >= __popcll(__ballot(alive))) {
         if (hold) {
+          const ArgPtr<R> Q = cold_args<R>();
           hold = false;
           events += 1;
-          if ((uint64_t)events > P.max_events) {
+          if ((uint64_t)events > Q->max_events) {
             bump(2);
             alive = false;
             if (TRACE) record(P, kidx, 5, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
@@ -562,8 +581,8 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
           sincos_rev(u24(w[2]), &sp, &cp);
           if (u24(w[0]) <= s_alb[j]) {
             // scattering: new direction from the phase function
-            if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 1, d0, d1, d2);
-            const R mu = (R)hg_mu(P.gpar[j], u24(w[1]));
+            if (IMG && Q->peel_q) peel_push(gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 1, d0, d1, d2);
+            const R mu = (R)hg_mu(Q->gpar[j], u24(w[1]));
             const R st = rsqrt0(R(1) - mu * mu);
             if (d2 > R(0.99999) || d2 < R(-0.99999)) {
               d0 = st * cp; d1 = st * sp; d2 = d2 >= R(0) ? mu : -mu;
@@ -582,45 +601,45 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
             // absorption: species, tally, new frequency, isotropic re-emission
             uint32_t v[4];
             philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), events, 1u, key0, key1, v);
-            const int sp_i = cdf_search(P.sp_cdf + (int64_t)j * P.S, P.S, u24(w[1]));
-            unsigned long long before = atomicAdd(&P.nabs[(int64_t)cell * P.S + sp_i], 1ull);
+            const int sp_i = cdf_search(Q->sp_cdf + (int64_t)j * Q->S, Q->S, u24(w[1]));
+            unsigned long long before = atomicAdd(&Q->nabs[(int64_t)cell * Q->S + sp_i], 1ull);
             bump(5);
-            if (P.flags & MCRT_FLAG_FROZEN_T) before = P.frozen[(int64_t)cell * P.S + sp_i];
-            if (P.flags & MCRT_FLAG_KILL_ON_ABSORB) {
+            if (Q->flags & MCRT_FLAG_FROZEN_T) before = Q->frozen[(int64_t)cell * Q->S + sp_i];
+            if (Q->flags & MCRT_FLAG_KILL_ON_ABSORB) {
               bump(3);
               alive = false;
               if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
               continue;
             }
-            if (P.kind[sp_i] == 0) {
+            if (Q->kind[sp_i] == 0) {
               // Bracket of the absorbed energy; with the exact Bjorkman-Wood form
               // a point uniform between the energies before and after this
               // absorption, which picks the rows spanning T_before..T_after in
               // proportion to the energy each covers.
-              const double vol = ldexp(P.h3, -3 * lev);
+              const double vol = ldexp(Q->h3, -3 * lev);
               double nb = (double)before;
-              if (P.flags & MCRT_FLAG_EXACT_BW) nb += u24(v[2]);
-              const double pw = nb * P.eps / (P.rho[cell] * vol);
-              const double* E = P.E + (int64_t)sp_i * P.K;
+              if (Q->flags & MCRT_FLAG_EXACT_BW) nb += u24(v[2]);
+              const double pw = nb * Q->eps / (Q->rho[cell] * vol);
+              const double* E = Q->E + (int64_t)sp_i * Q->K;
               int kb;
               if (pw < E[0]) {
                 kb = 0;
                 bump(7);
               } else {
-                int a = 0, b = P.K - 1;
-                if (E[P.K - 1] <= pw) a = P.K - 1;
+                int a = 0, b = Q->K - 1;
+                if (E[Q->K - 1] <= pw) a = Q->K - 1;
                 else
                   while (b - a > 1) {
                     const int m = (a + b) >> 1;
                     if (E[m] <= pw) a = m; else b = m;
                   }
                 kb = a;
-                if (kb > P.K - 2) { kb = P.K - 2; bump(8); }
+                if (kb > Q->K - 2) { kb = Q->K - 2; bump(8); }
               }
-              j = cdf_search(P.Rrows + ((int64_t)sp_i * (P.K - 1) + kb) * P.nl, P.nl, u24(v[0]));
+              j = cdf_search(Q->Rrows + ((int64_t)sp_i * (Q->K - 1) + kb) * Q->nl, Q->nl, u24(v[0]));
             } else {
-              const double* row = P.pah_rows + ((int64_t)P.pah_slot[sp_i] * P.n_cells + cell) * P.nl;
-              j = cdf_search(row, P.nl, u24(v[0]));
+              const double* row = Q->pah_rows + ((int64_t)Q->pah_slot[sp_i] * P.n_cells + cell) * Q->nl;
+              j = cdf_search(row, Q->nl, u24(v[0]));
               bump(9);
             }
             const R mu = (R)(2.0 * u24(v[1]) - 1.0);
@@ -628,7 +647,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
             d0 = st * cp; d1 = st * sp; d2 = mu;
             set_recip();
             tau = -rlog((R)u24(w[3]));
-            if (IMG && P.peel_q) peel_push(P, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 0, d0, d1, d2);
+            if (IMG && Q->peel_q) peel_push(gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), cell, j, 0, d0, d1, d2);
             if (TRACE) record(P, kidx, 3, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
           }
         }
@@ -637,7 +656,7 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   }
 
   if (DEFER) {
-    if (s_fill) flush_records(P, s_rec, s_fill, rcur, rleft, rfull);
+    if (s_fill) flush_records<R>(s_rec, s_fill, rcur, rleft, rfull);
     // the unused tail of the wave's last chunk holds neutral records
     if (!rfull)
       for (uint64_t q = (uint64_t)lane; q < rleft; q += 64) __builtin_nontemporal_store(0ull, &P.jrec[rcur + q]);
