@@ -103,10 +103,13 @@ def c3_block(n_packets, micro, stream, iterate=True):
     loop = PahLoop(w)
     eng = loop.eng
     N = w.n_packets
-    # deferred path tally: about 140 segment records per packet here, so the
-    # pass runs in id ranges of 12 M packets against a 2^31-record workspace
-    deferred = eng.set_deferred_tally(1 << 31)
-    batch = 12_000_000 if deferred else N
+    # deferred path tally: about 131 segment records per packet here; the
+    # workspace takes the device memory that is free (up to 2^33 records, 137 GB)
+    # and the pass runs in id ranges whose records fit it with 8 % to spare
+    free = torch.cuda.mem_get_info()[0]
+    cap = min(1 << 33, max(1 << 22, (free - (24 << 30)) // 16)) // 4096 * 4096
+    deferred = eng.set_deferred_tally(cap)
+    batch = min(N, int(cap / (1.08 * 131))) if deferred else N
     J = eng.thin_field()
     torch.cuda.synchronize()
     p0 = torch.cuda.Event(enable_timing=True)
