@@ -92,9 +92,17 @@ struct JrecLayout {
   uint64_t n_buckets, n_tiles, capacity;
   bool two_level;
   uint64_t fpc, nc;                               // two levels: buckets per coarse range, coarse ranges
-  uint64_t hdr, counts, tb, counts2, prefix, parts, recA, recB, total;   // byte offsets
+  uint64_t hdr, tb, parts, lvl1, lvl2, recA, recB, total;   // byte offsets
 };
 JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity);
+// The last deferred-tally range a context ran: its workspace, capacity,
+// seed, pass size, the packet id after it and how many consecutive ranges
+// led up to it.  A range that continues it sizes its partition regions from
+// the record totals of the ranges before.
+struct JrecChain {
+  const void* ws = nullptr;
+  uint64_t capacity = 0, seed = 0, n_total = 0, next_id = 0, length = 0;
+};
 
 }  // namespace mcrt
 
@@ -121,6 +129,7 @@ struct mcrt_ctx {
   std::string err;
   int device = 0;
   int n_cu = 256;
+  mcrt::JrecChain jchain;
 };
 
 namespace mcrt {
@@ -128,7 +137,8 @@ hipError_t launch_checks(mcrt_ctx* c, hipStream_t s);
 hipError_t launch_build_tables(mcrt_ctx* c, hipStream_t s);
 hipError_t launch_transport(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_opts& o,
                             const mcrt_tallies& t, hipStream_t s);
-hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t* jq, hipStream_t s);
+hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t first_id, uint64_t n_packets,
+                                  uint64_t* jq, hipStream_t s);
 hipError_t launch_temperatures(mcrt_ctx* c, const uint64_t* nabs, uint64_t n_total, double* T,
                                hipStream_t s);
 hipError_t launch_thin_field(mcrt_ctx* c, float* J, hipStream_t s);

@@ -4,10 +4,17 @@
 // table size, so the transport instead appends one record per path segment,
 // (tally index << 24) | fixed-point length, contiguously per wave.  Here the
 // records are added to the tally with streaming passes and LDS sums:
-//   count    histogram of records per (bucket, tile)
-//   scan     exclusive scan of the counts, bucket-major: each bucket's records
-//            become one contiguous range, ordered by tile
-//   scatter  records to their bucket ranges (sub-tiles sorted in LDS first)
+//   plan     every bucket (kBucketSlots tally words) gets a region of the
+//            destination array: its exact record count for the first id
+//            range of a chain of consecutive ranges (a counting pass), else
+//            the previous range's total scaled to this range's records, plus
+//            kPad records and a share of the array's room left in proportion
+//            to it; regions that would not fit the array are shrunk in
+//            proportion
+//   scatter  records to their bucket regions (sub-tiles sorted in LDS first);
+//            each sub-tile claims its run of every bucket with one atomic add
+//            on that bucket's fill counter, and the records past the end of a
+//            region are added to the tally directly (atomic adds)
 //   items    work items of at most kPart records per bucket
 //   sum      per item, u32 partial sums of its bucket (kBucketSlots tally
 //            words) in LDS (a carry past 2^32 goes straight to the tally),
@@ -17,17 +24,20 @@
 // scatter writes long runs: first into coarse ranges of fpc buckets, then
 // each coarse range, tile by tile, into its buckets.
 // Integer sums do not depend on order, so the tally equals the one the
-// atomic path gives, bit for bit.
+// atomic path gives, bit for bit, whichever records overflow their regions.
 #include "mcrt_internal.h"
 
 namespace mcrt {
 
 namespace {
 
-constexpr int kScanBlocks = 256;
 constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
 constexpr int kLoads = 16;                  // record loads per thread in flight (count, sum)
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
+constexpr uint64_t kPad = 1024;             // records added to every estimated region
+// a scatter block's 1024 threads claim for at most two buckets each: one
+// level has at most kOneLevelMax buckets, two levels at most 1024 per range
+static_assert(kOneLevelMax <= 2048 && kMaxBuckets <= 1024 * 1024, "bucket counts per scatter block");
 
 // Unsigned 32-bit division by an invariant divisor as a multiply-high, two
 // shifts and an add (Granlund & Montgomery, "Division by invariant integers
@@ -52,33 +62,46 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv& D) {
   return (t + ((n - t) >> D.s1)) >> D.s2;
 }
 
-// bucket of a record among nb buckets of D.d tally words from slot0
+// bucket of a record among nb buckets of D.d tally words from slot0; WIDE
+// for a tally of 2^32 words or more (else the offset always fits 32 bits,
+// and the kernel has no 64-bit division to hold registers for)
+template <bool WIDE = true>
 __device__ __forceinline__ uint32_t bucket_of(unsigned long long r, uint64_t slot0, const UDiv& D, uint32_t nb) {
   const uint64_t slot = r >> kRecValBits;
   const uint64_t d = slot >= slot0 ? slot - slot0 : 0;
-  // 32-bit division when the offset fits (every tally below 2^32 words)
-  const uint64_t b = d < (1ull << 32) ? (uint64_t)udiv((uint32_t)d, D) : d / D.d;
+  const uint64_t b = !WIDE || d < (1ull << 32) ? (uint64_t)udiv((uint32_t)d, D) : d / D.d;
   return b < nb ? (uint32_t)b : nb - 1;
 }
 
-// Where the buckets' records are after the last partition pass.  One level:
-// bucket b starts at offs[b nt].  Two levels: bucket b = c fpc + f starts at
-// entry (c, f, 0) of the level-2 counts, laid out [c][f][tile of c] with
-// tb[c] tiles before coarse range c.
-struct BucketMap {
-  const uint64_t* offs;
-  const uint32_t* tb;       // null for one level
-  uint64_t nt;
-  uint32_t fpc, nc, nb;     // nb: buckets
+// The regions of one partition level's nb buckets in its destination array:
+// est[b] the record total a region is sized from (one more word after the
+// level-1 totals: the records they stand for), start[b] and size[b] the
+// region, fill[b] its next free place (start[b] plus the records claimed so
+// far: the exact total once the scatter is done, overflow included), prev[b]
+// the total of the range before.
+struct Level {
+  unsigned long long* est;
+  unsigned long long* fill;
+  uint64_t* start;
+  uint64_t* size;
+  unsigned long long* prev;
+  uint32_t nb;
 };
 
-__device__ __forceinline__ uint64_t bucket_start(const BucketMap& M, uint32_t b, uint64_t n) {
-  if (b >= M.nb) return n;
-  if (!M.tb) return M.offs[(uint64_t)b * M.nt];
-  const uint32_t c = b / M.fpc, f = b - c * M.fpc;
-  const uint32_t t0 = M.tb[c], ntc = M.tb[c + 1] - t0;
-  const uint64_t idx = (uint64_t)t0 * M.fpc + (uint64_t)f * ntc;
-  return idx < (uint64_t)M.tb[M.nc] * M.fpc ? M.offs[idx] : n;
+// records a bucket's region holds after the scatter
+__device__ __forceinline__ uint64_t filled(const Level& L, uint32_t b) {
+  const uint64_t f = L.fill[b] - L.start[b], z = L.size[b];
+  return f < z ? f : z;
+}
+
+// Barrier for LDS hazards only: fences limited to the local address space,
+// so a wave does not first wait for its global loads and stores in flight
+// (__syncthreads does).  The scatter's threads share nothing but LDS, and its
+// next sub-tile's loads then overlap the stores of the previous one.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // level-2 tile g: its coarse range c (largest c with tb[c] <= g) and index k
@@ -133,39 +156,96 @@ __device__ __forceinline__ void count_range(const unsigned long long* __restrict
   }
 }
 
-// level 1: tile t of the record array; counts [bucket][tile]
-__global__ void __launch_bounds__(256) k_jr_count(const unsigned long long* __restrict__ rec,
+// Exact record totals of the first range of a chain, level 1: tile t of the
+// record array counted in LDS, then one atomic add per bucket into est.
+__global__ void __launch_bounds__(256) k_jr_total(const unsigned long long* __restrict__ rec,
                                                  const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                 UDiv span, uint64_t nt, uint64_t* __restrict__ counts) {
+                                                 UDiv span, unsigned long long* __restrict__ est) {
   extern __shared__ uint32_t h[];
   const uint64_t n = n_records(hdr, cap);
-  const uint64_t used = (n + kTile1 - 1) / kTile1;
   uint64_t t;
-  if (xcd_tile(blockIdx.x, used, t)) {
-    for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
-    __syncthreads();
-    const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
-    count_range(rec, a, e, 0, span, nb, h);
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + t] = h[i];
-  }
-  // the tiles past the last record: block t writes their zero counts
-  if (blockIdx.x >= used && blockIdx.x < nt)
-    for (uint32_t i = threadIdx.x; i < nb; i += 256) counts[(uint64_t)i * nt + blockIdx.x] = 0ull;
+  if (!xcd_tile(blockIdx.x, (n + kTile1 - 1) / kTile1, t)) return;
+  for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint64_t a = t * kTile1, e = a + kTile1 < n ? a + kTile1 : n;
+  count_range(rec, a, e, 0, span, nb, h);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nb; i += 256)
+    if (h[i]) atomicAdd(&est[i], (unsigned long long)h[i]);
 }
 
-// tiles of each coarse range for level 2: tb[c] = tiles before range c
-// (ranges from the level-1 offsets), tb[nc] = all tiles
-__global__ void __launch_bounds__(1024) k_jr_dir(const uint64_t* __restrict__ offs1, const unsigned long long* hdr,
-                                                uint64_t cap, uint32_t nc, uint64_t nt, uint32_t* __restrict__ tb) {
-  __shared__ uint32_t s[1024];
+// Block-wide inclusive scan of one u64 per thread (1024 threads) in s.
+__device__ __forceinline__ uint64_t scan1024(uint64_t x, uint64_t* s) {
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint64_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    s[threadIdx.x] += y;
+    __syncthreads();
+  }
+  return s[threadIdx.x];
+}
+
+// Regions of one level (one block).  Exact totals are the sizes as they
+// are.  Estimates are scaled by n / est_n (this range's records over those
+// they were taken from) and given kPad records each, and the space left in
+// the destination (`space` records) is dealt out in proportion to them: the
+// totals of one bucket vary by tens of percent from range to range (a few
+// packets that scatter many times in thick cells leave most of some cells'
+// records).  Regions that would not fit are shrunk in proportion (and by one
+// record against rounding).  Records past a region's end are still added
+// exactly.  Sets the fill counters to the region starts.
+__global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr, uint64_t cap, Level L,
+                                                 const unsigned long long* est_n, int exact, uint64_t space) {
+  __shared__ uint64_t s[1024];
   const uint64_t n = n_records(hdr, cap);
+  const uint32_t nb = L.nb, per = (nb + 1023) / 1024, b0 = threadIdx.x * per;
+  const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
+  const uint64_t en = exact ? 0 : *est_n;
+  const double f = en ? (double)n / (double)en : 0.0;
+  auto base = [&](uint32_t b) -> uint64_t {
+    const uint64_t x = L.est[b];
+    return exact ? x : (uint64_t)((double)x * f) + 1;
+  };
+  uint64_t loc = 0;
+  for (uint32_t b = b0; b < b1; ++b) loc += base(b);
+  scan1024(loc, s);
+  const uint64_t W = s[1023];
+  const uint64_t pads = exact ? 0 : (uint64_t)nb * kPad;
+  // sizes: exact; base + kPad + a share of the room left; or shrunk
+  const int mode = exact ? 0 : (W + pads <= space ? 1 : 2);
+  const double g = mode == 1 ? (double)(space - W - pads) / (double)W : (double)space / (double)(W + pads);
+  __syncthreads();
+  auto size = [&](uint32_t b) -> uint64_t {
+    const uint64_t w = base(b);
+    if (mode == 0) return w;
+    if (mode == 1) {
+      const uint64_t x = (uint64_t)((double)w * g);
+      return w + kPad + (x ? x - 1 : 0);
+    }
+    const uint64_t x = (uint64_t)((double)(w + kPad) * g);
+    return x ? x - 1 : 0;
+  };
+  loc = 0;
+  for (uint32_t b = b0; b < b1; ++b) loc += size(b);
+  uint64_t run = scan1024(loc, s) - loc;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint64_t z = size(b);
+    L.start[b] = run;
+    L.size[b] = z;
+    L.fill[b] = run;
+    run += z;
+  }
+}
+
+// level-2 tiles of each coarse range: tb[c] = tiles before range c (the
+// records its level-1 region holds), tb[nc] = all tiles
+__global__ void __launch_bounds__(1024) k_jr_dir(const Level L1, uint32_t nc, uint32_t* __restrict__ tb) {
+  __shared__ uint32_t s[1024];
   const uint32_t per = (nc + 1023) / 1024, c0 = threadIdx.x * per;
   uint32_t loc = 0;
-  for (uint32_t c = c0; c < c0 + per && c < nc; ++c) {
-    const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
-    loc += (uint32_t)((hi - lo + kTile1 - 1) / kTile1);
-  }
+  for (uint32_t c = c0; c < c0 + per && c < nc; ++c) loc += (uint32_t)((filled(L1, c) + kTile1 - 1) / kTile1);
   s[threadIdx.x] = loc;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -177,91 +257,43 @@ __global__ void __launch_bounds__(1024) k_jr_dir(const uint64_t* __restrict__ of
   uint32_t run = s[threadIdx.x] - loc;
   for (uint32_t c = c0; c < c0 + per && c < nc; ++c) {
     tb[c] = run;
-    const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
-    run += (uint32_t)((hi - lo + kTile1 - 1) / kTile1);
+    run += (uint32_t)((filled(L1, c) + kTile1 - 1) / kTile1);
   }
   if (threadIdx.x == 1023) tb[nc] = s[1023];
 }
 
-// level 2: tile g is tile k of coarse range c; counts at [c][f][k]
-__global__ void __launch_bounds__(256) k_jr_count2(const unsigned long long* __restrict__ rec,
-                                                  const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
-                                                  uint32_t nc, uint64_t nt, const uint64_t* __restrict__ offs1,
-                                                  const uint32_t* __restrict__ tb, UDiv span,
-                                                  uint64_t* __restrict__ counts2) {
+// records [a, e) of level-2 tile g (tile k of coarse range c's region)
+__device__ __forceinline__ bool tile2_range(const uint32_t* tb, uint32_t nc, uint64_t g, const Level& L1,
+                                            uint32_t& c, uint64_t& a, uint64_t& e) {
+  uint32_t k;
+  if (!tile2(tb, nc, (uint32_t)g, c, k)) return false;
+  const uint64_t lo = L1.start[c], hi = lo + filled(L1, c);
+  a = lo + (uint64_t)k * kTile1;
+  e = a + kTile1 < hi ? a + kTile1 : hi;
+  return true;
+}
+
+// Exact record totals, level 2: level-2 tile g counted over the fpc buckets
+// of its coarse range c, one atomic add per bucket into est.
+__global__ void __launch_bounds__(256) k_jr_total2(const unsigned long long* __restrict__ rec, uint32_t fpc,
+                                                  uint32_t nc, const Level L1, const uint32_t* __restrict__ tb,
+                                                  UDiv span, unsigned long long* __restrict__ est) {
   extern __shared__ uint32_t h[];
-  uint64_t g;
-  uint32_t c, k;
-  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2(tb, nc, (uint32_t)g, c, k)) return;
-  const uint64_t n = n_records(hdr, cap);
-  const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
+  uint64_t g, a, e;
+  uint32_t c;
+  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2_range(tb, nc, g, L1, c, a, e)) return;
   for (uint32_t i = threadIdx.x; i < fpc; i += 256) h[i] = 0u;
   __syncthreads();
-  const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
   count_range(rec, a, e, (uint64_t)c * fpc * kBucketSlots, span, fpc, h);
   __syncthreads();
-  const uint32_t t0 = tb[c], ntc = tb[c + 1] - t0;
   for (uint32_t f = threadIdx.x; f < fpc; f += 256)
-    counts2[(uint64_t)t0 * fpc + (uint64_t)f * ntc + k] = h[f];
-}
-
-// exclusive scan of v[0, n) in place: block sums, their scan, then each block
-// rescans its range from its base
-__global__ void __launch_bounds__(256) k_scan_sums(const uint64_t* __restrict__ v, uint64_t n,
-                                                  unsigned long long* __restrict__ bsum) {
-  __shared__ unsigned long long s[256];
-  const uint64_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
-  const uint64_t a = blockIdx.x * chunk, e = a + chunk < n ? a + chunk : n;
-  unsigned long long acc = 0;
-  for (uint64_t k = a + threadIdx.x; k < e; k += 256) acc += v[k];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
-}
-
-__global__ void k_scan_top(unsigned long long* bsum) {
-  if (threadIdx.x != 0) return;
-  unsigned long long run = 0;
-  for (int g = 0; g < kScanBlocks; ++g) {
-    const unsigned long long x = bsum[g];
-    bsum[g] = run;
-    run += x;
-  }
-  bsum[kScanBlocks] = run;
-}
-
-__global__ void __launch_bounds__(256) k_scan_apply(uint64_t* __restrict__ v, uint64_t n,
-                                                   const unsigned long long* __restrict__ bsum) {
-  __shared__ uint64_t s[256];
-  const uint64_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
-  const uint64_t a = blockIdx.x * chunk, e = a + chunk < n ? a + chunk : n;
-  uint64_t carry = bsum[blockIdx.x];
-  for (uint64_t k0 = a; k0 < e; k0 += 256) {
-    const uint64_t k = k0 + threadIdx.x;
-    const uint64_t x = k < e ? v[k] : 0ull;
-    s[threadIdx.x] = x;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {      // inclusive scan (Hillis-Steele)
-      const uint64_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
-      __syncthreads();
-      s[threadIdx.x] += y;
-      __syncthreads();
-    }
-    if (k < e) v[k] = carry + s[threadIdx.x] - x;
-    const uint64_t tot = s[255];
-    __syncthreads();
-    carry += tot;
-  }
+    if (h[f]) atomicAdd(&est[(uint64_t)c * fpc + f], (unsigned long long)h[f]);
 }
 
 // Block-wide exclusive scan of v[0, n) in LDS with NT threads; returns the
 // total.  Each thread sums its run of entries, the runs are scanned within
 // each wave by shuffles and across the NT / 64 waves through part (LDS
-// scratch of NT / 64 words): two barriers in all.
+// scratch of NT / 64 words): two barriers in all (LDS only).
 template <int NT>
 __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part) {
   const uint32_t per = (n + NT - 1) / NT, a = threadIdx.x * per;
@@ -275,7 +307,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part
     if (lane >= off) inc += y;
   }
   if (lane == 63u) part[wave] = inc;
-  __syncthreads();
+  lds_barrier();
   uint32_t before = 0, total = 0;
 #pragma unroll
   for (uint32_t w = 0; w < NT / 64; ++w) {
@@ -289,22 +321,30 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t n, uint32_t* part
     v[i] = run;
     run += x;
   }
-  __syncthreads();
+  lds_barrier();
   return total;
 }
 
 // The records [a, e) of src, sub-tile by sub-tile sorted by bucket in LDS
 // and written as contiguous runs (consecutive threads, consecutive
-// addresses) from run[b], the next free position of bucket b in dst.
-template <int NT>
+// addresses) into the buckets' regions of dst.  Each sub-tile claims the run
+// of each of its buckets with one atomic add on the bucket's fill counter
+// (fill[b], the next free place); a record whose place falls past its
+// region's end (lim[b]) is added to the tally jq directly, and counted in
+// ovf.  Thread i claims for buckets i, i + NT, ... (OWN of them, nb <= OWN NT).
+// LDS: srt [sub] records, run [nb] place of the sub-tile's run per bucket,
+// lim [nb], pre [nb] counts, then their prefix.
+template <int NT, int OWN, bool WIDE>
 __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64_t a, uint64_t e, uint64_t slot0,
-                              const UDiv& span, uint32_t nb, uint64_t* run, uint32_t* pre, unsigned long long* srt,
-                              uint32_t* part, unsigned long long* __restrict__ dst, uint64_t n, uint32_t sub) {
+                              const UDiv& span, uint32_t nb, unsigned long long* fill, uint64_t* run,
+                              const uint64_t* lim, uint32_t* pre, unsigned long long* srt, uint32_t* part,
+                              unsigned long long* __restrict__ dst, unsigned long long* __restrict__ jq,
+                              uint64_t n_slots, uint32_t sub, uint32_t& ovf) {
   constexpr int kMaxPer = 16;                                         // sub <= 16 NT
   for (uint64_t s0 = a; s0 < e; s0 += sub) {
     const uint32_t m = (uint32_t)(e - s0 < sub ? e - s0 : sub);
     unsigned long long r[kMaxPer];
-    uint32_t bk[kMaxPer], rk[kMaxPer];
+    uint32_t br[kMaxPer];                     // bucket << 16 | rank in the bucket (nb <= 2048, sub <= 16384)
     // all loads first (positions past m re-read record s0 and are dropped),
     // so that a wave has its whole share in flight at once
 #pragma unroll
@@ -315,105 +355,150 @@ __device__ void scatter_range(const unsigned long long* __restrict__ src, uint64
 #pragma unroll
     for (int q = 0; q < kMaxPer; ++q) {
       const uint32_t k = (uint32_t)q * NT + threadIdx.x;
-      bk[q] = bucket_of(r[q], slot0, span, nb);
-      if (k < m) rk[q] = atomicAdd(&pre[bk[q]], 1u);
+      const uint32_t b = bucket_of<WIDE>(r[q], slot0, span, nb);
+      br[q] = b << 16 | (k < m ? atomicAdd(&pre[b], 1u) : 0u);
     }
-    __syncthreads();
+    lds_barrier();
+    // claim the runs; their places are first needed after the LDS sort
+    unsigned long long got[OWN];
+#pragma unroll
+    for (int j = 0; j < OWN; ++j) {
+      const uint32_t i = threadIdx.x + (uint32_t)j * NT;
+      const uint32_t cnt = i < nb ? pre[i] : 0u;
+      got[j] = cnt ? atomicAdd(&fill[i], (unsigned long long)cnt) : ~0ull;
+    }
     block_exclusive_scan<NT>(pre, nb, part);
 #pragma unroll
     for (int q = 0; q < kMaxPer; ++q) {
       const uint32_t k = (uint32_t)q * NT + threadIdx.x;
-      if (k < m) srt[pre[bk[q]] + rk[q]] = r[q];
+      if (k < m) srt[pre[br[q] >> 16] + (br[q] & 0xffffu)] = r[q];
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < OWN; ++j)
+      if (got[j] != ~0ull) run[threadIdx.x + (uint32_t)j * NT] = got[j];
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < kMaxPer; ++q) {
+      // in two halves: the LDS reads of all sixteen at once would not fit
+      // the registers of four waves per SIMD
+      if (q == kMaxPer / 2) __builtin_amdgcn_sched_barrier(0);
       const uint32_t k = (uint32_t)q * NT + threadIdx.x;
       const uint32_t kk = k < m ? k : 0u;
       const unsigned long long x = srt[kk];
-      const uint32_t b = bucket_of(x, slot0, span, nb);
+      const uint32_t b = bucket_of<WIDE>(x, slot0, span, nb);
       const uint64_t d = run[b] + (kk - pre[b]);
       // plain store: a bucket's runs are completed across sub-tiles in the L2
       // (non-temporal stores made this pass 23 % slower)
-      if (k < m && d < n) dst[d] = x;
+      if (k < m) {
+        if (d < lim[b]) {
+          dst[d] = x;
+        } else {
+          const uint64_t slot = x >> kRecValBits;
+          const unsigned long long val = x & kValMask;
+          if (val && slot < n_slots) atomicAdd(&jq[slot], val);
+          ++ovf;
+        }
+      }
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t next = i + 1 < nb ? pre[i + 1] : m;
-      run[i] += next - pre[i];
-    }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t i = threadIdx.x; i < nb; i += NT) pre[i] = 0u;
-    __syncthreads();
+    lds_barrier();
   }
 }
 
-// level 1: tile t of src into the bucket ranges of dst
+// LDS of a scatter block: the sort buffer and the three bucket arrays
+constexpr size_t scatter_lds(uint32_t sub, uint64_t nb) { return (size_t)sub * 8 + 20 * nb; }
+
+// region ends of buckets [b0, b0 + nb) of L into LDS
 template <int NT>
-__global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src,
-                                                    const unsigned long long* hdr, uint64_t cap, uint32_t nb,
-                                                    UDiv span, uint64_t nt, const uint64_t* __restrict__ offs,
-                                                    unsigned long long* __restrict__ dst, uint32_t sub) {
+__device__ __forceinline__ void scatter_setup(const Level& L, uint32_t b0, uint32_t nb, uint64_t* lim, uint32_t* pre) {
+  for (uint32_t i = threadIdx.x; i < nb; i += NT) {
+    lim[i] = L.start[b0 + i] + L.size[b0 + i];
+    pre[i] = 0u;
+  }
+  __syncthreads();
+}
+
+// level 1: tile t of src into the regions of L's buckets in dst
+template <int NT, int OWN, bool WIDE>
+__global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src, unsigned long long* hdr,
+                                                    uint64_t cap, UDiv span, const Level L,
+                                                    unsigned long long* __restrict__ dst,
+                                                    unsigned long long* __restrict__ jq, uint64_t n_slots,
+                                                    uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
-  unsigned long long* srt = smem64;                                   // [sub] records by bucket
-  uint64_t* run = reinterpret_cast<uint64_t*>(smem64 + sub);          // [nb] next position per bucket
-  uint32_t* pre = reinterpret_cast<uint32_t*>(run + nb);              // [nb] counts, then prefix
+  const uint32_t nb = L.nb;
+  unsigned long long* srt = smem64;
+  uint64_t* run = reinterpret_cast<uint64_t*>(smem64 + sub);
+  uint64_t* lim = run + nb;
+  uint32_t* pre = reinterpret_cast<uint32_t*>(lim + nb);
   __shared__ uint32_t part[NT / 64];
   const uint64_t n = n_records(hdr, cap);
   uint64_t t;
   if (!xcd_tile(blockIdx.x, (n + kTile1 - 1) / kTile1, t)) return;
   const uint64_t a = t * kTile1;
   const uint64_t e = a + kTile1 < n ? a + kTile1 : n;
-  for (uint32_t i = threadIdx.x; i < nb; i += NT) {
-    run[i] = offs[(uint64_t)i * nt + t];
-    pre[i] = 0u;
-  }
-  __syncthreads();
-  scatter_range<NT>(src, a, e, 0, span, nb, run, pre, srt, part, dst, n, sub);
+  scatter_setup<NT>(L, 0, nb, lim, pre);
+  uint32_t ovf = 0;
+  scatter_range<NT, OWN, WIDE>(src, a, e, 0, span, nb, L.fill, run, lim, pre, srt, part, dst, jq, n_slots, sub, ovf);
+  if (ovf) atomicAdd(&hdr[2], (unsigned long long)ovf);
 }
 
-// level 2: tile k of coarse range c into its fpc buckets
-template <int NT>
-__global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __restrict__ src,
-                                                     const unsigned long long* hdr, uint64_t cap, uint32_t fpc,
-                                                     uint32_t nc, uint64_t nt, const uint64_t* __restrict__ offs1,
-                                                     const uint32_t* __restrict__ tb,
-                                                     const uint64_t* __restrict__ offs2, UDiv span,
-                                                     unsigned long long* __restrict__ dst, uint32_t sub) {
+// level 2: level-2 tile g (tile k of coarse range c's region in src) into the
+// regions of c's fpc buckets of L2 in dst
+template <int NT, bool WIDE>
+__global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __restrict__ src, unsigned long long* hdr,
+                                                     uint32_t fpc, uint32_t nc, const Level L1,
+                                                     const uint32_t* __restrict__ tb, const Level L2, UDiv span,
+                                                     unsigned long long* __restrict__ dst,
+                                                     unsigned long long* __restrict__ jq, uint64_t n_slots,
+                                                     uint32_t sub) {
   extern __shared__ unsigned long long smem64[];
   unsigned long long* srt = smem64;
   uint64_t* run = reinterpret_cast<uint64_t*>(smem64 + sub);
-  uint32_t* pre = reinterpret_cast<uint32_t*>(run + fpc);
+  uint64_t* lim = run + fpc;
+  uint32_t* pre = reinterpret_cast<uint32_t*>(lim + fpc);
   __shared__ uint32_t part[NT / 64];
-  uint64_t g;
-  uint32_t c, k;
-  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2(tb, nc, (uint32_t)g, c, k)) return;
-  const uint64_t n = n_records(hdr, cap);
-  const uint64_t lo = offs1[(uint64_t)c * nt], hi = c + 1 < nc ? offs1[(uint64_t)(c + 1) * nt] : n;
-  const uint64_t a = lo + (uint64_t)k * kTile1, e = a + kTile1 < hi ? a + kTile1 : hi;
-  const uint32_t t0 = tb[c], ntc = tb[c + 1] - t0;
-  for (uint32_t f = threadIdx.x; f < fpc; f += NT) {
-    run[f] = offs2[(uint64_t)t0 * fpc + (uint64_t)f * ntc + k];
-    pre[f] = 0u;
-  }
-  __syncthreads();
-  scatter_range<NT>(src, a, e, (uint64_t)c * fpc * kBucketSlots, span, fpc, run, pre, srt, part, dst, n, sub);
+  uint64_t g, a, e;
+  uint32_t c;
+  if (!xcd_tile(blockIdx.x, tb[nc], g) || !tile2_range(tb, nc, g, L1, c, a, e)) return;
+  const uint32_t b0 = c * fpc;
+  scatter_setup<NT>(L2, b0, fpc, lim, pre);
+  uint32_t ovf = 0;
+  scatter_range<NT, 1, WIDE>(src, a, e, (uint64_t)b0 * kBucketSlots, span, fpc, L2.fill + b0, run, lim, pre, srt, part,
+                       dst, jq, n_slots, sub, ovf);
+  if (ovf) atomicAdd(&hdr[2], (unsigned long long)ovf);
 }
 
-// parts[b] = exclusive prefix of ceil(len_b / kPart) over buckets
-__global__ void __launch_bounds__(1024) k_jr_items(const BucketMap M, unsigned long long* hdr, uint64_t cap,
+// The estimate of a bucket for the next range from its total t of this one
+// and p of the one before (counted over n and n_prev records): t plus the
+// growth since, if it grew.  Over a pass the totals drift (re-emission
+// follows the dust temperatures, which rise as absorptions are counted), by
+// tens of percent between the first ranges.
+__device__ __forceinline__ uint64_t next_estimate(uint64_t t, uint64_t p, uint64_t n, uint64_t n_prev, bool first) {
+  if (first || !n_prev) return t;
+  const double grow = (double)t - (double)p * ((double)n / (double)n_prev);
+  return grow > 0.0 ? t + (uint64_t)grow : t;
+}
+
+// parts[b] = exclusive prefix of ceil(len_b / kPart) over the buckets of M
+// (the last level); then the next range's estimates of both levels (L1 and M,
+// the same level for one level), with est_n = n; `first`: the first range of
+// a chain (no totals before).  With two levels (fpc > 0), a coarse range's
+// records that did not fit its level-1 region never reached level 2: its
+// buckets' totals are scaled up by the coarse range's total over the records
+// its region held.
+__global__ void __launch_bounds__(1024) k_jr_items(const Level M, const Level L1, uint32_t fpc, int first,
+                                                  unsigned long long* hdr, uint64_t cap,
                                                   uint32_t* __restrict__ parts) {
   __shared__ uint32_t s[1024];
   const uint64_t n = n_records(hdr, cap);
+  const uint64_t n_prev = first ? 0 : L1.est[L1.nb];     // read by all before the barriers below
   const uint32_t nb = M.nb;
   const uint32_t per = (nb + 1023) / 1024;
   const uint32_t b0 = threadIdx.x * per;
   uint32_t loc = 0;
-  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) {
-    const uint64_t lo = bucket_start(M, b, n);
-    const uint64_t hi = bucket_start(M, b + 1, n);
-    loc += (uint32_t)((hi - lo + kPart - 1) / kPart);
-  }
+  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) loc += (uint32_t)((filled(M, b) + kPart - 1) / kPart);
   s[threadIdx.x] = loc;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -425,30 +510,43 @@ __global__ void __launch_bounds__(1024) k_jr_items(const BucketMap M, unsigned l
   uint32_t run = s[threadIdx.x] - loc;
   for (uint32_t b = b0; b < b0 + per && b < nb; ++b) {
     parts[b] = run;
-    const uint64_t lo = bucket_start(M, b, n);
-    const uint64_t hi = bucket_start(M, b + 1, n);
-    run += (uint32_t)((hi - lo + kPart - 1) / kPart);
+    run += (uint32_t)((filled(M, b) + kPart - 1) / kPart);
+    uint64_t t = M.fill[b] - M.start[b];
+    if (fpc) {
+      const uint32_t c = b / fpc;
+      const uint64_t t1 = L1.fill[c] - L1.start[c], h1 = filled(L1, c);
+      if (t1 > h1 && h1) t = (uint64_t)((double)t * (double)t1 / (double)h1);
+    }
+    M.est[b] = next_estimate(t, M.prev[b], n, n_prev, first);
+    M.prev[b] = t;
+  }
+  if (fpc) {
+    for (uint32_t c = threadIdx.x; c < L1.nb; c += 1024) {
+      const uint64_t t = L1.fill[c] - L1.start[c];
+      L1.est[c] = next_estimate(t, L1.prev[c], n, n_prev, first);
+      L1.prev[c] = t;
+    }
   }
   if (threadIdx.x == 1023) {
     parts[nb] = s[1023];
+    L1.est[L1.nb] = n;
     hdr[1] = 0ull;
   }
 }
 
 __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __restrict__ recB,
-                                                unsigned long long* hdr, uint64_t cap, const BucketMap M,
+                                                unsigned long long* hdr, const Level M,
                                                 const uint32_t* __restrict__ parts, uint64_t n_slots,
                                                 unsigned long long* __restrict__ jq) {
   extern __shared__ uint32_t acc[];
   __shared__ uint32_t s_item;
-  const uint64_t n = n_records(hdr, cap);
   const uint32_t nb = M.nb;
   const uint32_t total = parts[nb];
   for (;;) {
     if (threadIdx.x == 0) s_item = (uint32_t)atomicAdd(&hdr[1], 1ull);
-    __syncthreads();
+    lds_barrier();
     const uint32_t item = s_item;
-    __syncthreads();
+    lds_barrier();
     if (item >= total) break;
     uint32_t lo = 0, hi = nb;                       // bucket with parts[b] <= item < parts[b+1]
     while (hi - lo > 1) {
@@ -456,8 +554,8 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
       if (parts[mid] <= item) lo = mid; else hi = mid;
     }
     const uint32_t b = lo;
-    const uint64_t start = bucket_start(M, b, n);
-    const uint64_t end = bucket_start(M, b + 1, n);
+    const uint64_t start = M.start[b];
+    const uint64_t end = start + filled(M, b);
     const uint64_t r0 = start + (uint64_t)(item - parts[b]) * kPart;
     const uint64_t r1 = r0 + kPart < end ? r0 + kPart : end;
     const bool shared_bucket = parts[b + 1] - parts[b] > 1;
@@ -523,7 +621,9 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
           if (v[q]) jq[base + i0 + q * 1024] = old[q] + v[q];
       }
     }
-    __syncthreads();
+    // LDS only: the next item's loads overlap this item's write-back (no
+    // other item writes these tally words but by atomics)
+    lds_barrier();
   }
 }
 
@@ -551,11 +651,10 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
     return o;
   };
   J.hdr = take(64);
-  J.counts = take(8 * nb1 * J.n_tiles);
   J.tb = take(4 * (J.nc + 1));
-  J.counts2 = take(J.two_level ? 8 * (J.n_tiles + J.nc + 1) * J.fpc : 0);
-  J.prefix = take(8 * (kScanBlocks + 1));
   J.parts = take(4 * (nb_all + 1));
+  J.lvl1 = take(8 * (5 * nb1 + 1));                     // est [nb1 + 1], fill, start, size, prev
+  J.lvl2 = take(J.two_level ? 8 * 5 * nb_all : 0);     // est, fill, start, size, prev
   J.recA = take(8 * capacity);
   J.recB = take(8 * capacity);
   J.total = off;
@@ -564,77 +663,102 @@ JrecLayout jrec_layout(uint64_t n_slots, uint64_t capacity) {
 
 namespace {
 
-__global__ void k_fill_u64(uint64_t* p, uint64_t n) {
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0ull;
 }
 
-void scan_u64(uint64_t* v, uint64_t n, unsigned long long* bsum, hipStream_t s) {
-  k_scan_sums<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
-  k_scan_top<<<1, 64, 0, s>>>(bsum);
-  k_scan_apply<<<kScanBlocks, 256, 0, s>>>(v, n, bsum);
+Level level_at(unsigned char* base, uint64_t nb, uint64_t est_words) {
+  Level L{};
+  auto* w = reinterpret_cast<unsigned long long*>(base);
+  L.est = w;
+  L.fill = w + est_words;
+  L.start = reinterpret_cast<uint64_t*>(L.fill + nb);
+  L.size = L.start + nb;
+  L.prev = reinterpret_cast<unsigned long long*>(L.size + nb);
+  L.nb = (uint32_t)nb;
+  return L;
 }
 
 // one scatter launch: one 1024-thread block per CU with the largest
 // power-of-two sub-tile (<= 16384 records) whose sort buffer fits beside the
-// two bucket arrays in 160 KB of LDS.  Longer sub-tiles mean longer runs of
+// bucket arrays in 160 KB of LDS.  Longer sub-tiles mean longer runs of
 // each bucket's stores, which pays more than two smaller blocks per CU
 // overlapping their loads and sorts (7 % on the scatter of the flared disk).
-template <typename L>
-void scatter_launch(uint64_t nb, L launch) {
+template <typename F>
+void scatter_launch(uint64_t nb, F launch) {
   uint32_t sub = 16384;
-  while (sub > 1024 && (size_t)sub * 8 + 12 * nb + 256 > 160 * 1024) sub >>= 1;
-  launch(sub, (size_t)sub * 8 + 12 * nb);
+  while (sub > 1024 && scatter_lds(sub, nb) + 256 > 160 * 1024) sub >>= 1;
+  launch(sub, scatter_lds(sub, nb));
 }
 
 }  // namespace
 
-hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t* jq, hipStream_t s) {
+hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t first_id, uint64_t n_packets,
+                                  uint64_t* jq, hipStream_t s) {
   const uint64_t n_slots = (uint64_t)c->d.n_lambda * (uint64_t)c->d.n_cells;
   const JrecLayout J = jrec_layout(n_slots, o.jrec_capacity);
   unsigned char* ws = static_cast<unsigned char*>(o.jrec_ws);
   auto* hdr = reinterpret_cast<unsigned long long*>(ws + J.hdr);
-  auto* counts = reinterpret_cast<uint64_t*>(ws + J.counts);
   auto* tb = reinterpret_cast<uint32_t*>(ws + J.tb);
-  auto* counts2 = reinterpret_cast<uint64_t*>(ws + J.counts2);
-  auto* bsum = reinterpret_cast<unsigned long long*>(ws + J.prefix);
   auto* parts = reinterpret_cast<uint32_t*>(ws + J.parts);
   auto* recA = reinterpret_cast<unsigned long long*>(ws + J.recA);
   auto* recB = reinterpret_cast<unsigned long long*>(ws + J.recB);
   auto* tally = reinterpret_cast<unsigned long long*>(jq);
   const uint64_t nt = J.n_tiles, cap = J.capacity;
   const uint32_t nb1 = (uint32_t)(J.two_level ? J.nc : J.n_buckets);
+  const Level L1 = level_at(ws + J.lvl1, nb1, nb1 + 1);
+  // a range that continues the last one of this context on the same
+  // workspace (same capacity, seed and pass size, the next packet ids) is the
+  // next of a chain; the first two of a chain count their records, the
+  // others size their regions from the totals of the two before
+  JrecChain& ch = c->jchain;
+  const bool chained = ch.ws == o.jrec_ws && ch.capacity == cap && ch.seed == o.seed && ch.n_total == o.n_total &&
+                       ch.next_id == first_id;
+  const uint64_t ch_len = chained ? ch.length : 0;
+  const bool exact = ch_len < 2;
+  ch = JrecChain{};
   const UDiv span1 = make_udiv((uint32_t)(J.two_level ? J.fpc * kBucketSlots : kBucketSlots));
   // level 1 (the whole partition for one level): recA -> recB
   const unsigned grid1 = (unsigned)((nt + kXcds - 1) / kXcds * kXcds);     // whole rounds over the XCDs
-  k_jr_count<<<grid1, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, nt, counts);
-  scan_u64(counts, (uint64_t)nb1 * nt, bsum, s);
+  if (exact) {
+    k_fill_u64<<<64, 256, 0, s>>>(L1.est, nb1);
+    k_jr_total<<<grid1, 256, 4 * (size_t)nb1, s>>>(recA, hdr, cap, nb1, span1, L1.est);
+  }
+  k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L1, L1.est + nb1, exact ? 1 : 0, cap);
+  const bool wide = n_slots > (1ull << 32);
   scatter_launch(nb1, [&](uint32_t sub, size_t lds) {
-    k_jr_scatter<1024><<<grid1, 1024, lds, s>>>(recA, hdr, cap, nb1, span1, nt, counts, recB, sub);
+    auto k = nb1 <= 1024 ? (wide ? k_jr_scatter<1024, 1, true> : k_jr_scatter<1024, 1, false>)
+                         : (wide ? k_jr_scatter<1024, 2, true> : k_jr_scatter<1024, 2, false>);
+    k<<<grid1, 1024, lds, s>>>(recA, hdr, cap, span1, L1, recB, tally, n_slots, sub);
   });
-  BucketMap M{};
+  Level M = L1;
   const unsigned long long* sorted = recB;
-  if (!J.two_level) {
-    M.offs = counts; M.tb = nullptr; M.nt = nt; M.nb = nb1;
-  } else {
+  if (J.two_level) {
     // level 2: each coarse range of recB, tile by tile, into its buckets -> recA
     const uint32_t fpc = (uint32_t)J.fpc, nc = (uint32_t)J.nc;
-    const uint64_t n2 = (nt + nc + 1) * fpc;
+    const uint64_t nb2 = (uint64_t)nc * fpc;
+    const Level L2 = level_at(ws + J.lvl2, nb2, nb2);
     const unsigned grid2 = (unsigned)((nt + nc + kXcds - 1) / kXcds * kXcds);  // >= level-2 tiles
-    k_jr_dir<<<1, 1024, 0, s>>>(counts, hdr, cap, nc, nt, tb);
-    k_fill_u64<<<256, 256, 0, s>>>(counts2, n2);
     const UDiv span2 = make_udiv((uint32_t)kBucketSlots);
-    k_jr_count2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, span2, counts2);
-    scan_u64(counts2, n2, bsum, s);
+    k_jr_dir<<<1, 1024, 0, s>>>(L1, nc, tb);
+    if (exact) {
+      k_fill_u64<<<256, 256, 0, s>>>(L2.est, nb2);
+      k_jr_total2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, fpc, nc, L1, tb, span2, L2.est);
+    }
+    k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L2, L1.est + nb1, exact ? 1 : 0, cap);
     scatter_launch(fpc, [&](uint32_t sub, size_t lds) {
-      k_jr_scatter2<1024><<<grid2, 1024, lds, s>>>(recB, hdr, cap, fpc, nc, nt, counts, tb, counts2, span2, recA, sub);
+      auto k = wide ? k_jr_scatter2<1024, true> : k_jr_scatter2<1024, false>;
+      k<<<grid2, 1024, lds, s>>>(recB, hdr, fpc, nc, L1, tb, L2, span2, recA, tally, n_slots, sub);
     });
-    M.offs = counts2; M.tb = tb; M.nt = nt; M.fpc = fpc; M.nc = nc; M.nb = nc * fpc;
+    M = L2;
     sorted = recA;
   }
-  k_jr_items<<<1, 1024, 0, s>>>(M, hdr, cap, parts);
-  k_jr_sum<<<(unsigned)c->n_cu, 1024, 4 * kBucketSlots, s>>>(sorted, hdr, cap, M, parts, n_slots, tally);
-  return hipGetLastError();
+  k_jr_items<<<1, 1024, 0, s>>>(M, L1, J.two_level ? (uint32_t)J.fpc : 0u, ch_len == 0 ? 1 : 0, hdr, cap, parts);
+  k_jr_sum<<<(unsigned)c->n_cu, 1024, 4 * kBucketSlots, s>>>(sorted, hdr, M, parts, n_slots, tally);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) ch = JrecChain{o.jrec_ws, cap, o.seed, o.n_total, first_id + n_packets, ch_len + 1};
+  return e;
 }
 
 }  // namespace mcrt
@@ -645,10 +769,7 @@ extern "C" int32_t mcrt_jrec_ws_bytes(const mcrt_ctx* ctx, uint64_t capacity, ui
   if (capacity < mcrt::kRecChunk || capacity > mcrt::kMaxRecords) return MCRT_E_INVALID;
   if (ctx->d.max_level > 7 || n_slots >= (1ull << 40)) return MCRT_E_UNSUPPORTED;
   const mcrt::JrecLayout J = mcrt::jrec_layout(n_slots, capacity);
-  const uint64_t nb1 = J.two_level ? J.nc : J.n_buckets;
-  if (J.n_buckets > mcrt::kMaxBuckets || nb1 * J.n_tiles > (1ull << 26) ||
-      (J.two_level && (J.n_tiles + J.nc + 1) * J.fpc > (1ull << 26)))
-    return MCRT_E_UNSUPPORTED;
+  if (J.n_buckets > mcrt::kMaxBuckets) return MCRT_E_UNSUPPORTED;
   *bytes = J.total;
   return MCRT_OK;
 }

@@ -886,7 +886,7 @@ hipError_t launch_t(mcrt_ctx* c, uint64_t first_id, uint64_t n, const mcrt_run_o
   }
   if (peel) k_peel<R><<<(unsigned)(c->n_cu * 4), 256, 0, s>>>(P);
   if (defer) {
-    const hipError_t e = launch_jrec_accumulate(c, o, t.jq, s);
+    const hipError_t e = launch_jrec_accumulate(c, o, first_id, n, t.jq, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

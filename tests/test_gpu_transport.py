@@ -578,3 +578,41 @@ def test_deferred_tally_equals_atomic(precision, capacity, nb, nl):
     for k in ("nabs", "sed", "jq", "counters"):
         assert np.array_equal(a[k], b[k]), k
     e.set_deferred_tally(0)
+
+
+def _jrec_overflow(e):
+    # records of the last id range that fell past their bucket regions and
+    # were added to the tally directly (header word 2 of the workspace)
+    return int(e._jrec[0][:64].view(torch.int64)[2].item())
+
+
+@pytest.mark.parametrize("nb,nl", [(16, 32), (72, 200)])
+def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
+    # consecutive id ranges of one pass: the first two count their records
+    # for their bucket regions, the later ones size them from the totals of
+    # the ranges before.  A workspace barely above a range's records shrinks
+    # those regions, so records past a region's end are added directly: the
+    # tally is still the atomic one bit for bit.  16^3 with 32 bins: one partition
+    # level; 72^3 with 200 bins: two.
+    n, step = 40000, 8000
+    w = synth.small_disk(n_packets=n, nl=nl, n_sizes=2, nb=nb)
+    w.precision = "f32"
+    base = oracle.Session(w, n_threads=8).transport(n=4000)["nabs"]
+    e = engine(w)
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    ref = e.new_tallies()
+    e.run(ref, 0, n, n, w.seed, frozen_nabs=base, flags=flags)
+    a = host(ref)
+    per_range = int(a["counters"][mcrt.CNT["jseg"]]) * step // n
+    capacity = (per_range + 4095) // 4096 * 4096
+    assert e.set_deferred_tally(capacity)
+    tal = e.new_tallies()
+    ovf = []
+    for first in range(0, n, step):
+        e.run(tal, first, step, n, w.seed, frozen_nabs=base, flags=flags)
+        ovf.append(_jrec_overflow(e))
+    b = host(tal)
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
+    assert ovf[0] == ovf[1] == 0 and sum(ovf[2:]) > 0, ovf
+    e.set_deferred_tally(0)
