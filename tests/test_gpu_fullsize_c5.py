@@ -12,9 +12,10 @@ checks sampled outputs one by one:
     anywhere in [0, 1e9) retrace the oracle's histories, PAH re-emission
     included;
   * temperatures of sampled cells of a seeded absorption field;
-  * with the frozen field, one id range of more than 2^32 segment records (64-bit
-    workspace offsets) gives the same tallies through records as through
-    per-segment atomics, bit for bit.
+  * with the frozen field, three consecutive id ranges of more than 2^32
+    segment records each (64-bit workspace offsets; the third sizes its bucket
+    regions from the two before) give the same tallies through records as
+    through per-segment atomics, bit for bit.
 """
 import numpy as np
 import pytest
@@ -133,25 +134,33 @@ def test_c5_sampled_temperatures(c5):
 
 
 def test_c5_deferred_tally_beyond_2_32_records_equals_atomic(c5):
-    # one id range whose segment records number more than 2^32: the
-    # workspace's offsets are 64-bit; the tally equals the per-segment atomic
-    # one bit for bit (compared on the device)
+    # three consecutive id ranges whose segment records number more than 2^32
+    # each: the workspace's offsets are 64-bit, and the third range sizes its
+    # bucket regions from the totals of the two before (the first two count
+    # theirs).  The tally equals the per-segment atomic one bit for bit
+    # (compared on the device), and the estimated regions hold all but a
+    # sliver of the third range's records.
     w, eng = c5["w"], c5["eng"]
     if "frozen" not in c5:
         c5["frozen"] = frozen_field(w, *stand_in_rows(w, c5))
     frozen = torch.as_tensor(c5["frozen"].reshape(-1).view(np.int64)).cuda()
     flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
-    n = 22_000_000
-    out = {}
+    n, first = 22_000_000, 300_000_000
+    out, ovf = {}, []
     for mode in ("deferred", "atomic"):          # the engine holds the fixture's workspace
         if mode == "atomic":
             eng.set_deferred_tally(0)
         tal = eng.new_tallies(tally_j=True)
-        eng.run(tal, 300_000_000, n, w.n_packets, w.seed, frozen_nabs=frozen, pah_rows=c5["rows"], flags=flags)
+        for k in range(3):
+            eng.run(tal, first + k * n, n, w.n_packets, w.seed, frozen_nabs=frozen, pah_rows=c5["rows"],
+                    flags=flags)
+            if mode == "deferred":
+                ovf.append(int(eng._jrec[0][:64].view(torch.int64)[2].item()))
         torch.cuda.synchronize()
         out[mode] = tal
     a, b = out["atomic"], out["deferred"]
     jseg = int(mcrt.u64_view(a["counters"])[mcrt.CNT["jseg"]])
-    assert (1 << 32) < jseg < c5["cap"], jseg
+    assert (1 << 32) < jseg // 3 < c5["cap"], jseg
+    assert ovf[0] == ovf[1] == 0 and ovf[2] < jseg // 3 // 1000, ovf
     for k in ("nabs", "sed", "jq", "counters"):
         assert torch.equal(a[k], b[k]), k
