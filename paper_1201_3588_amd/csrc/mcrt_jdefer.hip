@@ -174,17 +174,29 @@ __global__ void __launch_bounds__(256) k_jr_total(const unsigned long long* __re
     if (h[i]) atomicAdd(&est[i], (unsigned long long)h[i]);
 }
 
-// Block-wide inclusive scan of one u64 per thread (1024 threads) in s.
-__device__ __forceinline__ uint64_t scan1024(uint64_t x, uint64_t* s) {
-  s[threadIdx.x] = x;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint64_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
-    __syncthreads();
-    s[threadIdx.x] += y;
-    __syncthreads();
+// Block-wide exclusive scan of one u64 per thread (1024 threads): shuffles
+// within each wave, the 16 wave totals through part (LDS).  Returns the
+// thread's exclusive prefix; *total gets the block's sum.  Two barriers.
+__device__ __forceinline__ uint64_t scan1024(uint64_t x, uint64_t* part, uint64_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t inc = x;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
   }
-  return s[threadIdx.x];
+  if (lane == 63u) part[wave] = inc;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < 16; ++w) {
+    const uint64_t t = part[w];
+    before += w < wave ? t : 0ull;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
 }
 
 // Regions of one level (one block).  Exact totals are the sizes as they
@@ -198,26 +210,29 @@ __device__ __forceinline__ uint64_t scan1024(uint64_t x, uint64_t* s) {
 // exactly.  Sets the fill counters to the region starts.
 __global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr, uint64_t cap, Level L,
                                                  const unsigned long long* est_n, int exact, uint64_t space) {
-  __shared__ uint64_t s[1024];
+  __shared__ uint64_t part[16];
   const uint64_t n = n_records(hdr, cap);
-  const uint32_t nb = L.nb, per = (nb + 1023) / 1024, b0 = threadIdx.x * per;
-  const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
+  const uint32_t nb = L.nb;
   const uint64_t en = exact ? 0 : *est_n;
   const double f = en ? (double)n / (double)en : 0.0;
   auto base = [&](uint32_t b) -> uint64_t {
+    if (b >= nb) return 0;
     const uint64_t x = L.est[b];
     return exact ? x : (uint64_t)((double)x * f) + 1;
   };
-  uint64_t loc = 0;
-  for (uint32_t b = b0; b < b1; ++b) loc += base(b);
-  scan1024(loc, s);
-  const uint64_t W = s[1023];
+  // chunks of 1024 consecutive buckets, one per thread
+  uint64_t W = 0;
+  for (uint32_t c0 = 0; c0 < nb; c0 += 1024) {
+    uint64_t t;
+    scan1024(base(c0 + threadIdx.x), part, &t);
+    W += t;
+  }
   const uint64_t pads = exact ? 0 : (uint64_t)nb * kPad;
   // sizes: exact; base + kPad + a share of the room left; or shrunk
   const int mode = exact ? 0 : (W + pads <= space ? 1 : 2);
   const double g = mode == 1 ? (double)(space - W - pads) / (double)W : (double)space / (double)(W + pads);
-  __syncthreads();
   auto size = [&](uint32_t b) -> uint64_t {
+    if (b >= nb) return 0;
     const uint64_t w = base(b);
     if (mode == 0) return w;
     if (mode == 1) {
@@ -227,15 +242,18 @@ __global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr,
     const uint64_t x = (uint64_t)((double)(w + kPad) * g);
     return x ? x - 1 : 0;
   };
-  loc = 0;
-  for (uint32_t b = b0; b < b1; ++b) loc += size(b);
-  uint64_t run = scan1024(loc, s) - loc;
-  for (uint32_t b = b0; b < b1; ++b) {
+  uint64_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nb; c0 += 1024) {
+    const uint32_t b = c0 + threadIdx.x;
     const uint64_t z = size(b);
-    L.start[b] = run;
-    L.size[b] = z;
-    L.fill[b] = run;
-    run += z;
+    uint64_t t;
+    const uint64_t at = carry + scan1024(z, part, &t);
+    if (b < nb) {
+      L.start[b] = at;
+      L.size[b] = z;
+      L.fill[b] = at;
+    }
+    carry += t;
   }
 }
 
@@ -491,34 +509,29 @@ __device__ __forceinline__ uint64_t next_estimate(uint64_t t, uint64_t p, uint64
 __global__ void __launch_bounds__(1024) k_jr_items(const Level M, const Level L1, uint32_t fpc, int first,
                                                   unsigned long long* hdr, uint64_t cap,
                                                   uint32_t* __restrict__ parts) {
-  __shared__ uint32_t s[1024];
+  __shared__ uint64_t part[16];
   const uint64_t n = n_records(hdr, cap);
   const uint64_t n_prev = first ? 0 : L1.est[L1.nb];     // read by all before the barriers below
   const uint32_t nb = M.nb;
-  const uint32_t per = (nb + 1023) / 1024;
-  const uint32_t b0 = threadIdx.x * per;
-  uint32_t loc = 0;
-  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) loc += (uint32_t)((filled(M, b) + kPart - 1) / kPart);
-  s[threadIdx.x] = loc;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
-    __syncthreads();
-    s[threadIdx.x] += y;
-    __syncthreads();
-  }
-  uint32_t run = s[threadIdx.x] - loc;
-  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) {
-    parts[b] = run;
-    run += (uint32_t)((filled(M, b) + kPart - 1) / kPart);
-    uint64_t t = M.fill[b] - M.start[b];
-    if (fpc) {
-      const uint32_t c = b / fpc;
-      const uint64_t t1 = L1.fill[c] - L1.start[c], h1 = filled(L1, c);
-      if (t1 > h1 && h1) t = (uint64_t)((double)t * (double)t1 / (double)h1);
+  uint64_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nb; c0 += 1024) {           // chunks of consecutive buckets
+    const uint32_t b = c0 + threadIdx.x;
+    uint64_t x = 0;
+    if (b < nb) {
+      x = (filled(M, b) + kPart - 1) / kPart;
+      uint64_t t = M.fill[b] - M.start[b];
+      if (fpc) {
+        const uint32_t c = b / fpc;
+        const uint64_t t1 = L1.fill[c] - L1.start[c], h1 = filled(L1, c);
+        if (t1 > h1 && h1) t = (uint64_t)((double)t * (double)t1 / (double)h1);
+      }
+      M.est[b] = next_estimate(t, M.prev[b], n, n_prev, first);
+      M.prev[b] = t;
     }
-    M.est[b] = next_estimate(t, M.prev[b], n, n_prev, first);
-    M.prev[b] = t;
+    uint64_t tot;
+    const uint64_t ex = scan1024(x, part, &tot);
+    if (b < nb) parts[b] = (uint32_t)(carry + ex);
+    carry += tot;
   }
   if (fpc) {
     for (uint32_t c = threadIdx.x; c < L1.nb; c += 1024) {
@@ -527,8 +540,9 @@ __global__ void __launch_bounds__(1024) k_jr_items(const Level M, const Level L1
       L1.prev[c] = t;
     }
   }
-  if (threadIdx.x == 1023) {
-    parts[nb] = s[1023];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    parts[nb] = (uint32_t)carry;
     L1.est[L1.nb] = n;
     hdr[1] = 0ull;
   }
