@@ -609,6 +609,7 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const uint64_t ns = base >= n_slots ? 0 : (n_slots - base < kBucketSlots ? n_slots - base : kBucketSlots);
+    const __amdgpu_buffer_rsrc_t words = __builtin_amdgcn_make_buffer_rsrc(jq + base, (short)0, (int)(8 * ns), 0x00020000);
     for (uint32_t i0 = threadIdx.x; i0 < ns; i0 += 8 * 1024) {
       uint32_t v[8];
       unsigned long long old[8];
@@ -622,13 +623,17 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
         for (int q = 0; q < 8; ++q)
           if (v[q]) atomicAdd(&jq[base + i0 + q * 1024], (unsigned long long)v[q]);
       } else {
-        // the tally words' loads all in flight before the first store:
-        // unconditional (past ns: word i0 again), since loads under a branch
-        // make every store wait for all earlier memory operations
+        // the tally words' loads all in flight before the first store, with
+        // no branch (a load under a branch makes every store wait for all
+        // earlier memory operations): buffer loads over the bucket's words,
+        // whose offset is out of range for a word this item adds nothing to
+        // (such a load reads no memory and returns 0; a range adds to about
+        // a third of the words)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const uint32_t i = i0 + q * 1024;
-          old[q] = jq[base + (i < ns ? i : i0)];
+          old[q] = __builtin_bit_cast(unsigned long long,
+                                      __builtin_amdgcn_raw_buffer_load_b64(words, v[q] ? 8u * i : 0xffffffffu, 0, 0));
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
