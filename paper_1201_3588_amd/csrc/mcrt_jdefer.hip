@@ -35,9 +35,12 @@ constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
 constexpr int kLoads = 16;                  // record loads per thread in flight (count, sum)
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
 constexpr uint64_t kPad = 1024;             // records added to every estimated region
-// a scatter block's 1024 threads claim for at most two buckets each: one
-// level has at most kOneLevelMax buckets, two levels at most 1024 per range
-static_assert(kOneLevelMax <= 2048 && kMaxBuckets <= 1024 * 1024, "bucket counts per scatter block");
+// A scatter block has kScatterNT threads, two blocks per CU; each thread
+// claims for at most three buckets: one level has at most kOneLevelMax
+// buckets, two levels at most 1024 per range
+constexpr int kScatterNT = 512;
+static_assert(kOneLevelMax <= 3 * kScatterNT && kMaxBuckets <= 1024 * 1024 && 1024 <= 2 * kScatterNT,
+              "bucket counts per scatter block");
 
 // Unsigned 32-bit division by an invariant divisor as a multiply-high, two
 // shifts and an add (Granlund & Montgomery, "Division by invariant integers
@@ -439,7 +442,7 @@ __device__ __forceinline__ void scatter_setup(const Level& L, uint32_t b0, uint3
 
 // level 1: tile t of src into the regions of L's buckets in dst
 template <int NT, int OWN, bool WIDE>
-__global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __restrict__ src, unsigned long long* hdr,
+__global__ void __launch_bounds__(NT, 4) k_jr_scatter(const unsigned long long* __restrict__ src, unsigned long long* hdr,
                                                     uint64_t cap, UDiv span, const Level L,
                                                     unsigned long long* __restrict__ dst,
                                                     unsigned long long* __restrict__ jq, uint64_t n_slots,
@@ -464,8 +467,8 @@ __global__ void __launch_bounds__(NT) k_jr_scatter(const unsigned long long* __r
 
 // level 2: level-2 tile g (tile k of coarse range c's region in src) into the
 // regions of c's fpc buckets of L2 in dst
-template <int NT, bool WIDE>
-__global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __restrict__ src, unsigned long long* hdr,
+template <int NT, int OWN, bool WIDE>
+__global__ void __launch_bounds__(NT, 4) k_jr_scatter2(const unsigned long long* __restrict__ src, unsigned long long* hdr,
                                                      uint32_t fpc, uint32_t nc, const Level L1,
                                                      const uint32_t* __restrict__ tb, const Level L2, UDiv span,
                                                      unsigned long long* __restrict__ dst,
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(NT) k_jr_scatter2(const unsigned long long* __
   const uint32_t b0 = c * fpc;
   scatter_setup<NT>(L2, b0, fpc, lim, pre);
   uint32_t ovf = 0;
-  scatter_range<NT, 1, WIDE>(src, a, e, (uint64_t)b0 * kBucketSlots, span, fpc, L2.fill + b0, run, lim, pre, srt, part,
+  scatter_range<NT, OWN, WIDE>(src, a, e, (uint64_t)b0 * kBucketSlots, span, fpc, L2.fill + b0, run, lim, pre, srt, part,
                        dst, jq, n_slots, sub, ovf);
   if (ovf) atomicAdd(&hdr[2], (unsigned long long)ovf);
 }
@@ -699,15 +702,17 @@ Level level_at(unsigned char* base, uint64_t nb, uint64_t est_words) {
   return L;
 }
 
-// one scatter launch: one 1024-thread block per CU with the largest
-// power-of-two sub-tile (<= 16384 records) whose sort buffer fits beside the
-// bucket arrays in 160 KB of LDS.  Longer sub-tiles mean longer runs of
-// each bucket's stores, which pays more than two smaller blocks per CU
-// overlapping their loads and sorts (7 % on the scatter of the flared disk).
+// one scatter launch: two 512-thread blocks per CU (each at most 128
+// registers per thread), with the largest power-of-two sub-tile (<= 8192
+// records, 16 per thread) whose sort buffer and bucket arrays fit both blocks
+// in 160 KB of LDS.  One block's LDS sort then overlaps the other's loads and
+// stores.  On the 256^3 disk the level-1 scatter takes 21 % less time than
+// one 1024-thread block per CU on sub-tiles of 16384 records; four 256-thread
+// blocks on 4096 take 30 % more (a bucket's runs get too short).
 template <typename F>
 void scatter_launch(uint64_t nb, F launch) {
-  uint32_t sub = 16384;
-  while (sub > 1024 && scatter_lds(sub, nb) + 256 > 160 * 1024) sub >>= 1;
+  uint32_t sub = 16 * kScatterNT;
+  while (sub > 1024 && 2 * (scatter_lds(sub, nb) + 256) > 160 * 1024) sub >>= 1;
   launch(sub, scatter_lds(sub, nb));
 }
 
@@ -747,9 +752,11 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t 
   k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L1, L1.est + nb1, exact ? 1 : 0, cap);
   const bool wide = n_slots > (1ull << 32);
   scatter_launch(nb1, [&](uint32_t sub, size_t lds) {
-    auto k = nb1 <= 1024 ? (wide ? k_jr_scatter<1024, 1, true> : k_jr_scatter<1024, 1, false>)
-                         : (wide ? k_jr_scatter<1024, 2, true> : k_jr_scatter<1024, 2, false>);
-    k<<<grid1, 1024, lds, s>>>(recA, hdr, cap, span1, L1, recB, tally, n_slots, sub);
+    constexpr int T = kScatterNT;
+    auto k = nb1 <= T       ? (wide ? k_jr_scatter<T, 1, true> : k_jr_scatter<T, 1, false>)
+             : nb1 <= 2 * T ? (wide ? k_jr_scatter<T, 2, true> : k_jr_scatter<T, 2, false>)
+                            : (wide ? k_jr_scatter<T, 3, true> : k_jr_scatter<T, 3, false>);
+    k<<<grid1, T, lds, s>>>(recA, hdr, cap, span1, L1, recB, tally, n_slots, sub);
   });
   Level M = L1;
   const unsigned long long* sorted = recB;
@@ -767,8 +774,10 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t 
     }
     k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L2, L1.est + nb1, exact ? 1 : 0, cap);
     scatter_launch(fpc, [&](uint32_t sub, size_t lds) {
-      auto k = wide ? k_jr_scatter2<1024, true> : k_jr_scatter2<1024, false>;
-      k<<<grid2, 1024, lds, s>>>(recB, hdr, fpc, nc, L1, tb, L2, span2, recA, tally, n_slots, sub);
+      constexpr int T = kScatterNT;
+      auto k = fpc <= T ? (wide ? k_jr_scatter2<T, 1, true> : k_jr_scatter2<T, 1, false>)
+                        : (wide ? k_jr_scatter2<T, 2, true> : k_jr_scatter2<T, 2, false>);
+      k<<<grid2, T, lds, s>>>(recB, hdr, fpc, nc, L1, tb, L2, span2, recA, tally, n_slots, sub);
     });
     M = L2;
     sorted = recA;

@@ -586,14 +586,15 @@ def _jrec_overflow(e):
     return int(e._jrec[0][:64].view(torch.int64)[2].item())
 
 
-@pytest.mark.parametrize("nb,nl", [(16, 32), (72, 200)])
+@pytest.mark.parametrize("nb,nl", [(16, 32), (56, 200), (64, 200), (72, 200)])
 def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
     # consecutive id ranges of one pass: the first two count their records
     # for their bucket regions, the later ones size them from the totals of
     # the ranges before.  A workspace barely above a range's records shrinks
     # those regions, so records past a region's end are added directly: the
     # tally is still the atomic one bit for bit.  16^3 with 32 bins: one partition
-    # level; 72^3 with 200 bins: two.
+    # level of 4 buckets; 56^3 and 64^3 with 200 bins: one level of 865 and
+    # 1290 buckets (a scatter thread claims for two and three); 72^3: two.
     n, step = 40000, 8000
     w = synth.small_disk(n_packets=n, nl=nl, n_sizes=2, nb=nb)
     w.precision = "f32"
