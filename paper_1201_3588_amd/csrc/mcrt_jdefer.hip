@@ -35,12 +35,10 @@ constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
 constexpr int kLoads = 16;                  // record loads per thread in flight (count, sum)
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
 constexpr uint64_t kPad = 1024;             // records added to every estimated region
-// A scatter block has kScatterNT threads, two blocks per CU; each thread
-// claims for at most three buckets: one level has at most kOneLevelMax
-// buckets, two levels at most 1024 per range
-constexpr int kScatterNT = 512;
-static_assert(kOneLevelMax <= 3 * kScatterNT && kMaxBuckets <= 1024 * 1024 && 1024 <= 2 * kScatterNT,
-              "bucket counts per scatter block");
+// A scatter block has 512 threads (two blocks per CU, up to 806 buckets) or
+// 1024 (one per CU); each thread claims for at most two buckets: one level
+// has at most kOneLevelMax buckets, two levels at most 1024 per range
+static_assert(kOneLevelMax <= 2 * 1024 && kMaxBuckets <= 1024 * 1024, "bucket counts per scatter block");
 
 // Unsigned 32-bit division by an invariant divisor as a multiply-high, two
 // shifts and an add (Granlund & Montgomery, "Division by invariant integers
@@ -702,19 +700,29 @@ Level level_at(unsigned char* base, uint64_t nb, uint64_t est_words) {
   return L;
 }
 
-// one scatter launch: two 512-thread blocks per CU (each at most 128
-// registers per thread), with the largest power-of-two sub-tile (<= 8192
-// records, 16 per thread) whose sort buffer and bucket arrays fit both blocks
-// in 160 KB of LDS.  One block's LDS sort then overlaps the other's loads and
-// stores.  On the 256^3 disk the level-1 scatter takes 21 % less time than
-// one 1024-thread block per CU on sub-tiles of 16384 records; four 256-thread
-// blocks on 4096 take 30 % more (a bucket's runs get too short).
+// One scatter launch (each thread at most 128 registers, 16 records per
+// sub-tile).  Where sub-tiles of 8192 records fit two blocks' LDS (160 KB per
+// CU; up to 806 buckets), two 512-thread blocks per CU: one block's LDS sort
+// then overlaps the other's loads and stores.  On the 256^3 disk the level-1
+// scatter takes 21 % less time than one 1024-thread block per CU on
+// sub-tiles of 16384 records; four 256-thread blocks on 4096 take 30 % more
+// (a bucket's runs get too short).  More buckets: one 1024-thread block per
+// CU with the largest power-of-two sub-tile (<= 16384) that fits.
 template <typename F>
 void scatter_launch(uint64_t nb, F launch) {
-  uint32_t sub = 16 * kScatterNT;
-  while (sub > 1024 && 2 * (scatter_lds(sub, nb) + 256) > 160 * 1024) sub >>= 1;
-  launch(sub, scatter_lds(sub, nb));
+  if (2 * (scatter_lds(8192, nb) + 256) <= 160 * 1024) {
+    launch(512, 8192u, scatter_lds(8192, nb));
+    return;
+  }
+  uint32_t sub = 16384;
+  while (sub > 1024 && scatter_lds(sub, nb) + 256 > 160 * 1024) sub >>= 1;
+  launch(1024, sub, scatter_lds(sub, nb));
 }
+
+template <int NT, int OWN>
+auto scatter1_kernel(bool wide) { return wide ? k_jr_scatter<NT, OWN, true> : k_jr_scatter<NT, OWN, false>; }
+template <int NT, int OWN>
+auto scatter2_kernel(bool wide) { return wide ? k_jr_scatter2<NT, OWN, true> : k_jr_scatter2<NT, OWN, false>; }
 
 }  // namespace
 
@@ -751,12 +759,11 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t 
   }
   k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L1, L1.est + nb1, exact ? 1 : 0, cap);
   const bool wide = n_slots > (1ull << 32);
-  scatter_launch(nb1, [&](uint32_t sub, size_t lds) {
-    constexpr int T = kScatterNT;
-    auto k = nb1 <= T       ? (wide ? k_jr_scatter<T, 1, true> : k_jr_scatter<T, 1, false>)
-             : nb1 <= 2 * T ? (wide ? k_jr_scatter<T, 2, true> : k_jr_scatter<T, 2, false>)
-                            : (wide ? k_jr_scatter<T, 3, true> : k_jr_scatter<T, 3, false>);
-    k<<<grid1, T, lds, s>>>(recA, hdr, cap, span1, L1, recB, tally, n_slots, sub);
+  scatter_launch(nb1, [&](int nt, uint32_t sub, size_t lds) {
+    const bool two = nb1 > (uint32_t)nt;                       // buckets per thread
+    auto k = nt == 512 ? (two ? scatter1_kernel<512, 2>(wide) : scatter1_kernel<512, 1>(wide))
+                       : (two ? scatter1_kernel<1024, 2>(wide) : scatter1_kernel<1024, 1>(wide));
+    k<<<grid1, nt, lds, s>>>(recA, hdr, cap, span1, L1, recB, tally, n_slots, sub);
   });
   Level M = L1;
   const unsigned long long* sorted = recB;
@@ -773,11 +780,11 @@ hipError_t launch_jrec_accumulate(mcrt_ctx* c, const mcrt_run_opts& o, uint64_t 
       k_jr_total2<<<grid2, 256, 4 * (size_t)fpc, s>>>(recB, fpc, nc, L1, tb, span2, L2.est);
     }
     k_jr_plan<<<1, 1024, 0, s>>>(hdr, cap, L2, L1.est + nb1, exact ? 1 : 0, cap);
-    scatter_launch(fpc, [&](uint32_t sub, size_t lds) {
-      constexpr int T = kScatterNT;
-      auto k = fpc <= T ? (wide ? k_jr_scatter2<T, 1, true> : k_jr_scatter2<T, 1, false>)
-                        : (wide ? k_jr_scatter2<T, 2, true> : k_jr_scatter2<T, 2, false>);
-      k<<<grid2, T, lds, s>>>(recB, hdr, fpc, nc, L1, tb, L2, span2, recA, tally, n_slots, sub);
+    scatter_launch(fpc, [&](int nt, uint32_t sub, size_t lds) {
+      const bool two = fpc > (uint32_t)nt;
+      auto k = nt == 512 ? (two ? scatter2_kernel<512, 2>(wide) : scatter2_kernel<512, 1>(wide))
+                         : (two ? scatter2_kernel<1024, 2>(wide) : scatter2_kernel<1024, 1>(wide));
+      k<<<grid2, nt, lds, s>>>(recB, hdr, fpc, nc, L1, tb, L2, span2, recA, tally, n_slots, sub);
     });
     M = L2;
     sorted = recA;

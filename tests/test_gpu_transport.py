@@ -586,15 +586,16 @@ def _jrec_overflow(e):
     return int(e._jrec[0][:64].view(torch.int64)[2].item())
 
 
-@pytest.mark.parametrize("nb,nl", [(16, 32), (56, 200), (64, 200), (72, 200)])
+@pytest.mark.parametrize("nb,nl", [(16, 32), (48, 200), (56, 200), (64, 200), (72, 200)])
 def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
     # consecutive id ranges of one pass: the first two count their records
     # for their bucket regions, the later ones size them from the totals of
     # the ranges before.  A workspace barely above a range's records shrinks
     # those regions, so records past a region's end are added directly: the
     # tally is still the atomic one bit for bit.  16^3 with 32 bins: one partition
-    # level of 4 buckets; 56^3 and 64^3 with 200 bins: one level of 865 and
-    # 1290 buckets (a scatter thread claims for two and three); 72^3: two.
+    # level of 4 buckets; 48^3, 56^3 and 64^3 with 200 bins: one level of 545,
+    # 865 and 1290 buckets (scatter blocks of 512 threads claiming for two
+    # buckets each, of 1024 claiming for one and for two); 72^3: two levels.
     n, step = 40000, 8000
     w = synth.small_disk(n_packets=n, nl=nl, n_sizes=2, nb=nb)
     w.precision = "f32"
