@@ -161,6 +161,15 @@ __device__ __forceinline__ int locate(const TP<R>& P, int F0, int F1, int F2, in
   return e;
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -356,11 +365,10 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   // frequent counters in registers, rare ones in LDS
   uint32_t c_cross = 0, c_jseg = 0, c_zero = 0;
   auto bump = [&](int k) { atomicAdd(&s_cnt[k], 1u); };
-  // deferred path tally: this lane's pending record, and the wave's current
-  // chunk of the record buffer [rcur, rcur + rleft) (wave-uniform); once the
-  // buffer is exhausted (rfull) the wave adds to the tally directly
-  unsigned long long prec = 0;
-  bool hrec = false, rfull = false;
+  // deferred path tally: the wave's current chunk of the record buffer
+  // [rcur, rcur + rleft) (wave-uniform); once the buffer is exhausted (rfull)
+  // the wave adds to the tally directly
+  bool rfull = false;
   unsigned long long* s_rec = s_stage + (threadIdx.x >> 6) * kStage;   // this wave's staging buffer
   uint32_t s_fill = 0u;                                                // records in it (wave-uniform)
   bool hold = false;          // at an interaction point, waiting for the wave's batch
@@ -368,24 +376,12 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
   auto gx = [&](int lo, R u) { return (double)lo * (double)inv_nf + (double)u; };
 
   for (;;) {
-    if (DEFER) {
-      // every lane is here (loop head): the pending records of the wave go to
-      // its LDS staging buffer, which is copied to the record buffer in bulk
-      // when it cannot take another full wave of records.  A record store per
-      // step would be waited for by the step's next wait on memory (vector
-      // memory operations are counted in issue order), a write round trip
-      // each step; LDS stores are not.
-      const unsigned long long rm = __ballot(hrec);
-      if (rm) {
-        if (s_fill + 64u > kStage) {
-          flush_records<R>(s_rec, s_fill, rcur, rleft, rfull);
-          s_fill = 0u;
-        }
-        const uint32_t rank = (uint32_t)__popcll(rm & lt_mask);
-        if (hrec) s_rec[s_fill + rank] = prec;
-        s_fill += (uint32_t)__popcll(rm);
-        hrec = false;
-      }
+    if (DEFER && s_fill + 64u > kStage) {
+      // every lane is here (loop head): the wave's staged records go to the
+      // record buffer in bulk when the staging area could not take another
+      // full wave of them
+      flush_records<R>(s_rec, s_fill, rcur, rleft, rfull);
+      s_fill = 0u;
     }
     if (!exhausted || q_next < q_end) {
       const unsigned long long dead = __ballot(!alive);
@@ -451,114 +447,151 @@ __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P)
       if (exhausted && q_next >= q_end) break;
       continue;
     }
-    if (alive && !hold) {
-      // ---- one segment: exit distance from the current leaf (lowest axis wins ties)
-      const int span = 1 << (L - lev);
-      const R side = (R)span * inv_nf;
-      R tex = (R)INFINITY;
-      int ax = -1;
-      if (sizeof(R) == 4) {
-        // FP32: the distance to the face the direction points to, per axis,
-        // by the direction's reciprocals (one rounding more than a division,
-        // well inside FP32 geometry tolerance), negative distances clamped to
-        // 0; an axis not moved along gives +inf or NaN, and the minimum skips
-        // a NaN.  The lowest axis wins ties.  No branches.
-        auto dist = [](R w, R r) { const R x = w * r; return !(x <= R(0)) ? x : R(0); };
-        const R t0 = dist(d0 > R(0) ? side - u0 : -u0, r0);
-        const R t1 = dist(d1 > R(0) ? side - u1 : -u1, r1);
-        const R t2 = dist(d2 > R(0) ? side - u2 : -u2, r2);
-        tex = fmin(t0, fmin(t1, t2));
-        ax = t0 == tex ? 0 : (t1 == tex ? 1 : 2);
-      } else {
-        // FP64: divide, as the definition does
-        R t;
-        if (d0 != R(0)) {
-          t = (d0 > R(0) ? side - u0 : -u0) / d0;
-          t = t < R(0) ? R(0) : t;
-          if (t < tex) { tex = t; ax = 0; }
-        }
-        if (d1 != R(0)) {
-          t = (d1 > R(0) ? side - u1 : -u1) / d1;
-          t = t < R(0) ? R(0) : t;
-          if (t < tex) { tex = t; ax = 1; }
-        }
-        if (d2 != R(0)) {
-          t = (d2 > R(0) ? side - u2 : -u2) / d2;
-          t = t < R(0) ? R(0) : t;
-          if (t < tex) { tex = t; ax = 2; }
-        }
-      }
-      const bool dusty = dens > R(0);
-      const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)s_kext[j] * P.h)
-                                     : (R)(dens * s_kext[j]);
+    // ---- the march: each live lane that is not held steps segment by
+    // segment until it holds at an interaction point or leaves the grid, and
+    // the wave stops marching once enough lanes hold for a batch, enough lanes
+    // are dead for a refill, or the staging area could not take another
+    // wave's records.  A lane's state is updated in place here (a lane leaves
+    // the loop instead of skipping a block in it).
+    {
+      int n_alive = __popcll(__ballot(alive));
+      int n_hold = __popcll(__ballot(hold));
+      const bool can_refill = !exhausted || q_next < q_end;
+      uint32_t fill = s_fill;
+      if (alive && !hold) {
+        for (;;) {
+          unsigned long long prec = 0;
+          bool hrec = false;
+          // ---- one segment: exit distance from the current leaf (lowest axis wins ties)
+          const int span = 1 << (L - lev);
+          const R side = (R)span * inv_nf;
+          R tex = (R)INFINITY;
+          int ax = -1;
+          if (sizeof(R) == 4) {
+            // FP32: the distance to the face the direction points to, per axis,
+            // by the direction's reciprocals (one rounding more than a division,
+            // well inside FP32 geometry tolerance), negative distances clamped to
+            // 0; an axis not moved along gives +inf or NaN, and the minimum skips
+            // a NaN.  The lowest axis wins ties.  No branches.
+            auto dist = [](R w, R r) { const R x = w * r; return !(x <= R(0)) ? x : R(0); };
+            const R t0 = dist(d0 > R(0) ? side - u0 : -u0, r0);
+            const R t1 = dist(d1 > R(0) ? side - u1 : -u1, r1);
+            const R t2 = dist(d2 > R(0) ? side - u2 : -u2, r2);
+            tex = fmin(t0, fmin(t1, t2));
+            ax = t0 == tex ? 0 : (t1 == tex ? 1 : 2);
+          } else {
+            // FP64: divide, as the definition does
+            R t;
+            if (d0 != R(0)) {
+              t = (d0 > R(0) ? side - u0 : -u0) / d0;
+              t = t < R(0) ? R(0) : t;
+              if (t < tex) { tex = t; ax = 0; }
+            }
+            if (d1 != R(0)) {
+              t = (d1 > R(0) ? side - u1 : -u1) / d1;
+              t = t < R(0) ? R(0) : t;
+              if (t < tex) { tex = t; ax = 1; }
+            }
+            if (d2 != R(0)) {
+              t = (d2 > R(0) ? side - u2 : -u2) / d2;
+              t = t < R(0) ? R(0) : t;
+              if (t < tex) { tex = t; ax = 2; }
+            }
+          }
+          const bool dusty = dens > R(0);
+          const R alpha = sizeof(R) == 8 ? (R)((double)dens * (double)s_kext[j] * P.h)
+                                         : (R)(dens * s_kext[j]);
 
-      if (alpha > R(0) && tau < alpha * tex) {
-        // ---- interaction inside this cell
-        const R s = tau / alpha;
-        u0 += s * d0; u1 += s * d1; u2 += s * d2;
-        if (tally_j && dusty) {
-          // lengths are below 2^24 units of the finest cell / 2^16
-          const unsigned long long q = (unsigned long long)(uint32_t)rrint(s * P.qscale);
-          if (DEFER) {
-            prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell) << kRecValBits) | q;
-            hrec = true;
+          if (alpha > R(0) && tau < alpha * tex) {
+            // ---- interaction inside this cell
+            const R s = tau / alpha;
+            u0 += s * d0; u1 += s * d1; u2 += s * d2;
+            if (tally_j && dusty) {
+              // lengths are below 2^24 units of the finest cell / 2^16
+              const unsigned long long q = (unsigned long long)(uint32_t)rrint(s * P.qscale);
+              if (DEFER) {
+                prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell)
+                        << kRecValBits) | q;
+                hrec = true;
+              } else {
+                atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+              }
+              c_jseg++;
+            }
+            hold = true;
           } else {
-            atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+            // ---- cross the face into the neighbour
+            if (alpha > R(0)) tau -= alpha * tex;
+            if (tally_j && dusty) {
+              // lengths are below 2^24 units of the finest cell / 2^16
+              const unsigned long long q = (unsigned long long)(uint32_t)rrint(tex * P.qscale);
+              if (DEFER) {
+                prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell)
+                        << kRecValBits) | q;
+                hrec = true;
+              } else {
+                atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+              }
+              c_jseg++;
+            }
+            c_cross++;
+            if (tex == R(0)) c_zero++;
+            u0 += tex * d0; u1 += tex * d1; u2 += tex * d2;
+            const R nf = (R)(1 << L);
+            int G0, G1, G2;
+            {
+              const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
+              G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
+              G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
+              G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
+            }
+            if (ax == 0) {
+              u0 = d0 > R(0) ? side : R(0);
+              G0 = d0 > R(0) ? lo0 + span : lo0 - 1;
+            } else if (ax == 1) {
+              u1 = d1 > R(0) ? side : R(0);
+              G1 = d1 > R(0) ? lo1 + span : lo1 - 1;
+            } else {
+              u2 = d2 > R(0) ? side : R(0);
+              G2 = d2 > R(0) ? lo2 + span : lo2 - 1;
+            }
+            const int o0 = lo0, o1 = lo1, o2 = lo2;
+            cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
+            if (cell < 0) {
+              bump(1);
+              alive = false;
+              escape_tally(d0, d1, d2, j);
+              if (IMG) image_tally(gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
+              if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
+            } else {
+              // re-base the local position on the new leaf (exact integer offsets)
+              u0 += (R)(o0 - lo0) * inv_nf;
+              u1 += (R)(o1 - lo1) * inv_nf;
+              u2 += (R)(o2 - lo2) * inv_nf;
+              if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+            }
           }
-          c_jseg++;
-        }
-        hold = true;
-      } else {
-        // ---- cross the face into the neighbour
-        if (alpha > R(0)) tau -= alpha * tex;
-        if (tally_j && dusty) {
-          // lengths are below 2^24 units of the finest cell / 2^16
-          const unsigned long long q = (unsigned long long)(uint32_t)rrint(tex * P.qscale);
+
           if (DEFER) {
-            prec = ((unsigned long long)((uint64_t)(uint32_t)j * (uint64_t)P.n_cells + (uint32_t)cell) << kRecValBits) | q;
-            hrec = true;
-          } else {
-            atomicAdd(&P.jq[(int64_t)j * P.n_cells + cell], q);
+            // the marching lanes' records go to the wave's LDS staging area,
+            // in lane order.  A record store to global memory per step would
+            // be waited for by the step's next wait on memory (vector memory
+            // operations are counted in issue order): a write round trip per
+            // step, which an LDS store is not.
+            const unsigned long long rm = __ballot(hrec);
+            if (hrec) s_rec[fill + (uint32_t)__popcll(rm & lt_mask)] = prec;
+            fill += (uint32_t)__popcll(rm);
           }
-          c_jseg++;
-        }
-        c_cross++;
-        if (tex == R(0)) c_zero++;
-        u0 += tex * d0; u1 += tex * d1; u2 += tex * d2;
-        const R nf = (R)(1 << L);
-        int G0, G1, G2;
-        {
-          const int f0 = (int)rfloor(u0 * nf), f1 = (int)rfloor(u1 * nf), f2 = (int)rfloor(u2 * nf);
-          G0 = lo0 + (f0 < 0 ? 0 : (f0 > span - 1 ? span - 1 : f0));
-          G1 = lo1 + (f1 < 0 ? 0 : (f1 > span - 1 ? span - 1 : f1));
-          G2 = lo2 + (f2 < 0 ? 0 : (f2 > span - 1 ? span - 1 : f2));
-        }
-        if (ax == 0) {
-          u0 = d0 > R(0) ? side : R(0);
-          G0 = d0 > R(0) ? lo0 + span : lo0 - 1;
-        } else if (ax == 1) {
-          u1 = d1 > R(0) ? side : R(0);
-          G1 = d1 > R(0) ? lo1 + span : lo1 - 1;
-        } else {
-          u2 = d2 > R(0) ? side : R(0);
-          G2 = d2 > R(0) ? lo2 + span : lo2 - 1;
-        }
-        const int o0 = lo0, o1 = lo1, o2 = lo2;
-        cell = locate(P, G0, G1, G2, lev, lo0, lo1, lo2, dens);
-        if (cell < 0) {
-          bump(1);
-          alive = false;
-          escape_tally(d0, d1, d2, j);
-          if (IMG) image_tally(gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, j);
-          if (TRACE) record(P, kidx, 4, -1, j, gx(o0, u0), gx(o1, u1), gx(o2, u2), d0, d1, d2, tau);
-        } else {
-          // re-base the local position on the new leaf (exact integer offsets)
-          u0 += (R)(o0 - lo0) * inv_nf;
-          u1 += (R)(o1 - lo1) * inv_nf;
-          u2 += (R)(o2 - lo2) * inv_nf;
-          if (TRACE) record(P, kidx, 1, cell, j, gx(lo0, u0), gx(lo1, u1), gx(lo2, u2), d0, d1, d2, tau);
+          n_hold += __popcll(__ballot(hold));
+          n_alive -= __popcll(__ballot(!alive));
+          if (!alive || hold) break;
+          if (n_hold * kHoldFrac >= n_alive || (can_refill && 64 - n_alive >= kRefillMin) ||
+              (DEFER && fill + 64u > kStage))
+            break;
         }
       }
+      // lanes left the march at different steps: the last count is the largest
+      if (DEFER) s_fill = wave_max_u32(fill);
     }
 
     // ---- the wave's held interactions, once enough lanes hold
