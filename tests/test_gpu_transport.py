@@ -588,9 +588,9 @@ def _jrec_overflow(e):
 
 @pytest.mark.parametrize("nb,nl", [(16, 32), (48, 200), (56, 200), (64, 200), (72, 200)])
 def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
-    # consecutive id ranges of one pass: the first two count their records
-    # for their bucket regions, the later ones size them from the totals of
-    # the ranges before.  A workspace barely above a range's records shrinks
+    # consecutive id ranges of one pass: the first counts its records for
+    # its bucket regions, the later ones size them from the totals of the
+    # ranges before.  A workspace barely above a range's records shrinks
     # those regions, so records past a region's end are added directly: the
     # tally is still the atomic one bit for bit.  16^3 with 32 bins: one partition
     # level of 4 buckets; 48^3, 56^3 and 64^3 with 200 bins: one level of 545,
@@ -616,5 +616,5 @@ def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
     b = host(tal)
     for k in ("nabs", "sed", "jq", "counters"):
         assert np.array_equal(a[k], b[k]), k
-    assert ovf[0] == ovf[1] == 0 and sum(ovf[2:]) > 0, ovf
+    assert ovf[0] == 0 and sum(ovf[1:]) > 0, ovf
     e.set_deferred_tally(0)
