@@ -308,8 +308,13 @@ int32_t mcrt_thin_field(mcrt_ctx *ctx, float *J_out, hipStream_t stream);
  * then adds them with streaming partition passes (two levels for tallies of
  * more than 1536 * 40704 words) and LDS sums, on the same stream; the tally
  * is identical to the one of the atomic path (integer sums).  Segments beyond
- * jrec_capacity records are added directly (still exact).  Workspace bytes
- * for a capacity (16 bytes per record plus small tables): *bytes;
+ * jrec_capacity records are added directly (still exact).  The workspace also
+ * keeps per-bucket record totals from run to run: a run that continues the
+ * last one of the context on the same workspace (the next packet ids, same
+ * seed, n_total and capacity) sizes its partition from them instead of
+ * counting its records (a matter of speed only: the tally stays exact).
+ * Runs that overlap on one workspace race.  Workspace bytes for a capacity
+ * (16 bytes per record plus small tables): *bytes;
  * MCRT_E_INVALID for capacity outside [4096, 2^35],
  * MCRT_E_UNSUPPORTED when the grid is deeper than 7 levels or the tally has
  * more than 2^20 * 40704 words.  No device work. */

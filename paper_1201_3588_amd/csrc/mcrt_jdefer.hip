@@ -33,7 +33,7 @@ namespace mcrt {
 namespace {
 
 constexpr uint64_t kPart = 1ull << 20;      // records per summing work item
-constexpr int kLoads = 16;                  // record loads per thread in flight (count, sum)
+constexpr int kLoads = 16;                  // record loads per thread in flight (counting passes, sum)
 constexpr unsigned long long kValMask = (1ull << kRecValBits) - 1ull;
 constexpr uint64_t kPad = 1024;             // records added to every estimated region
 // A scatter block has 512 threads (two blocks per CU, up to 806 buckets) or
@@ -121,9 +121,9 @@ __device__ __forceinline__ bool tile2(const uint32_t* tb, uint32_t nc, uint32_t 
 
 // Blocks are dealt to the chip's 8 XCDs round-robin (block b to XCD b mod 8).
 // The tile of block b among `used` tiles, chosen so that each XCD takes one
-// contiguous range of tiles: the runs of a bucket in neighbouring tiles meet
-// in one cache line, which is then completed in one L2 instead of two (the
-// same holds for neighbouring words of the per-tile counts).  The grid needs
+// contiguous range of tiles: the level-2 tiles of one coarse range then run
+// on one XCD, whose L2 completes the cache lines where their runs of a bucket
+// meet and takes the atomics on that range's fill counters.  The grid needs
 // at least 8 ceil(used / 8) blocks; false for a block without a tile.
 constexpr uint64_t kXcds = 8;
 
@@ -441,8 +441,8 @@ __device__ __forceinline__ void scatter_setup(const Level& L, uint32_t b0, uint3
 
 // level 1: tile t of src into the regions of L's buckets in dst
 template <int NT, int OWN, bool WIDE>
-__global__ void __launch_bounds__(NT, 4) k_jr_scatter(const unsigned long long* __restrict__ src, unsigned long long* hdr,
-                                                    uint64_t cap, UDiv span, const Level L,
+__global__ void __launch_bounds__(NT, 4) k_jr_scatter(const unsigned long long* __restrict__ src,
+                                                       unsigned long long* hdr, uint64_t cap, UDiv span, const Level L,
                                                     unsigned long long* __restrict__ dst,
                                                     unsigned long long* __restrict__ jq, uint64_t n_slots,
                                                     uint32_t sub) {
@@ -467,8 +467,9 @@ __global__ void __launch_bounds__(NT, 4) k_jr_scatter(const unsigned long long* 
 // level 2: level-2 tile g (tile k of coarse range c's region in src) into the
 // regions of c's fpc buckets of L2 in dst
 template <int NT, int OWN, bool WIDE>
-__global__ void __launch_bounds__(NT, 4) k_jr_scatter2(const unsigned long long* __restrict__ src, unsigned long long* hdr,
-                                                     uint32_t fpc, uint32_t nc, const Level L1,
+__global__ void __launch_bounds__(NT, 4) k_jr_scatter2(const unsigned long long* __restrict__ src,
+                                                        unsigned long long* hdr, uint32_t fpc, uint32_t nc,
+                                                        const Level L1,
                                                      const uint32_t* __restrict__ tb, const Level L2, UDiv span,
                                                      unsigned long long* __restrict__ dst,
                                                      unsigned long long* __restrict__ jq, uint64_t n_slots,
@@ -485,8 +486,8 @@ __global__ void __launch_bounds__(NT, 4) k_jr_scatter2(const unsigned long long*
   const uint32_t b0 = c * fpc;
   scatter_setup<NT>(L2, b0, fpc, lim, pre);
   uint32_t ovf = 0;
-  scatter_range<NT, OWN, WIDE>(src, a, e, (uint64_t)b0 * kBucketSlots, span, fpc, L2.fill + b0, run, lim, pre, srt, part,
-                       dst, jq, n_slots, sub, ovf);
+  scatter_range<NT, OWN, WIDE>(src, a, e, (uint64_t)b0 * kBucketSlots, span, fpc, L2.fill + b0, run, lim, pre, srt,
+                               part, dst, jq, n_slots, sub, ovf);
   if (ovf) atomicAdd(&hdr[2], (unsigned long long)ovf);
 }
 
@@ -611,7 +612,8 @@ __global__ void __launch_bounds__(1024) k_jr_sum(const unsigned long long* __res
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const uint64_t ns = base >= n_slots ? 0 : (n_slots - base < kBucketSlots ? n_slots - base : kBucketSlots);
-    const __amdgpu_buffer_rsrc_t words = __builtin_amdgcn_make_buffer_rsrc(jq + base, (short)0, (int)(8 * ns), 0x00020000);
+    const __amdgpu_buffer_rsrc_t words =
+        __builtin_amdgcn_make_buffer_rsrc(jq + base, (short)0, (int)(8 * ns), 0x00020000);
     for (uint32_t i0 = threadIdx.x; i0 < ns; i0 += 8 * 1024) {
       uint32_t v[8];
       unsigned long long old[8];
