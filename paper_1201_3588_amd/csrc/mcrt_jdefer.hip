@@ -217,10 +217,13 @@ __global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr,
   const uint32_t nb = L.nb;
   const uint64_t en = exact ? 0 : *est_n;
   const double f = en ? (double)n / (double)en : 0.0;
+  // each base at most `space`, so that no sum below can wrap whatever the
+  // workspace holds (a workspace reallocated at the same address leaves
+  // arbitrary estimates: they cost speed, never bounds)
   auto base = [&](uint32_t b) -> uint64_t {
     if (b >= nb) return 0;
     const uint64_t x = L.est[b];
-    return exact ? x : (uint64_t)((double)x * f) + 1;
+    return exact ? (x < space ? x : space) : (uint64_t)fmin((double)x * f, (double)space) + 1;
   };
   // chunks of 1024 consecutive buckets, one per thread
   uint64_t W = 0;
@@ -229,9 +232,10 @@ __global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr,
     scan1024(base(c0 + threadIdx.x), part, &t);
     W += t;
   }
-  const uint64_t pads = exact ? 0 : (uint64_t)nb * kPad;
-  // sizes: exact; base + kPad + a share of the room left; or shrunk
-  const int mode = exact ? 0 : (W + pads <= space ? 1 : 2);
+  const uint64_t pad = exact ? 0 : kPad, pads = (uint64_t)nb * pad;
+  // sizes: exact; base + kPad + a share of the room left; or, when they would
+  // not fit, shrunk in proportion (W + pads <= 2^56: no wrap)
+  const int mode = W + pads <= space ? (exact ? 0 : 1) : 2;
   const double g = mode == 1 ? (double)(space - W - pads) / (double)W : (double)space / (double)(W + pads);
   auto size = [&](uint32_t b) -> uint64_t {
     if (b >= nb) return 0;
@@ -239,9 +243,9 @@ __global__ void __launch_bounds__(1024) k_jr_plan(const unsigned long long* hdr,
     if (mode == 0) return w;
     if (mode == 1) {
       const uint64_t x = (uint64_t)((double)w * g);
-      return w + kPad + (x ? x - 1 : 0);
+      return w + pad + (x ? x - 1 : 0);
     }
-    const uint64_t x = (uint64_t)((double)(w + kPad) * g);
+    const uint64_t x = (uint64_t)((double)(w + pad) * g);
     return x ? x - 1 : 0;
   };
   uint64_t carry = 0;

@@ -618,3 +618,32 @@ def test_deferred_tally_chain_of_ranges_equals_atomic(nb, nl):
         assert np.array_equal(a[k], b[k]), k
     assert ovf[0] == 0 and sum(ovf[1:]) > 0, ovf
     e.set_deferred_tally(0)
+
+
+def test_deferred_tally_chain_with_arbitrary_workspace_contents():
+    # a chain of ranges whose workspace is overwritten with arbitrary bytes
+    # between ranges (as when it is freed and allocated again at the same
+    # address): the next range sizes its regions from whatever the workspace
+    # holds, the regions still fit the record arrays, and the tally is the
+    # atomic one bit for bit (two partition levels)
+    n, step = 40000, 8000
+    w = synth.small_disk(n_packets=n, nl=200, n_sizes=2, nb=72)
+    w.precision = "f32"
+    base = oracle.Session(w, n_threads=8).transport(n=4000)["nabs"]
+    e = engine(w)
+    flags = mcrt.FLAG_TALLY_J | mcrt.FLAG_FROZEN_T
+    ref = e.new_tallies()
+    e.run(ref, 0, n, n, w.seed, frozen_nabs=base, flags=flags)
+    assert e.set_deferred_tally(1 << 22)
+    tal = e.new_tallies()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    ws = e._jrec[0]
+    for first in range(0, n, step):
+        if first >= 2 * step:
+            ws.copy_(torch.randint(0, 256, ws.shape, dtype=torch.uint8, device="cuda", generator=g))
+        e.run(tal, first, step, n, w.seed, frozen_nabs=base, flags=flags)
+    a, b = host(ref), host(tal)
+    for k in ("nabs", "sed", "jq", "counters"):
+        assert np.array_equal(a[k], b[k]), k
+    e.set_deferred_tally(0)
