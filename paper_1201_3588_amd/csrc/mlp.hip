@@ -52,17 +52,25 @@ struct GemmP {
   int ldz;
   int kchunk;           // EPI_F32 split over K: blockIdx.z takes [z kchunk, (z+1) kchunk)
   float* part;          // and writes its partial product to part[z][M][N] (null: no split)
+  int va, vb;           // A, B allow 16-byte loads (16-byte aligned base, ld a multiple of 8)
 };
 
 constexpr int BM = 64, BN = 64, BK = 32, PADK = 40;
 
-// 64 x 32 tile of X(r, k) (r = row of the tile, k contiguous in LDS)
+// 64 x 32 tile of X(r, k) (r = row of the tile, k contiguous in LDS).  Each
+// thread reads 8 consecutive elements: one 16-byte load where the operand
+// allows it (vec) and the 8 lie inside it, else element by element with
+// zeros outside (the same values either way).
 __device__ __forceinline__ void load_tile(uint16_t (*S)[PADK], const uint16_t* __restrict__ G, int ld,
-                                          bool kmajor, int r0, int k0, int R, int K) {
+                                          bool kmajor, int r0, int k0, int R, int K, bool vec) {
   const int t = threadIdx.x;
   if (!kmajor) {                 // G[r*ld + k]: 8 consecutive k per thread
     const int r = t >> 2, kc = (t & 3) * 8;
     const int gr = r0 + r;
+    if (vec && gr < R && k0 + kc + 8 <= K) {
+      *reinterpret_cast<u16x8*>(&S[r][kc]) = *reinterpret_cast<const u16x8*>(G + (int64_t)gr * ld + k0 + kc);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int gk = k0 + kc + i;
@@ -71,6 +79,12 @@ __device__ __forceinline__ void load_tile(uint16_t (*S)[PADK], const uint16_t* _
   } else {                       // G[k*ld + r]: 8 consecutive r per thread
     const int kr = t >> 3, rc = (t & 7) * 8;
     const int gk = k0 + kr;
+    if (vec && gk < K && r0 + rc + 8 <= R) {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(G + (int64_t)gk * ld + r0 + rc);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[rc + i][kr] = v[i];
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int gr = r0 + rc + i;
@@ -91,8 +105,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmP p) {
   const int kend = split ? min(p.K, kbeg + p.kchunk) : p.K;
   f32x16 acc = {};
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    load_tile(As, p.A, p.lda, p.ta != 0, m0, k0, p.M, kend);
-    load_tile(Bs, p.B, p.ldb, p.tb == 0, n0, k0, p.N, kend);
+    load_tile(As, p.A, p.lda, p.ta != 0, m0, k0, p.M, kend, p.va != 0);
+    load_tile(Bs, p.B, p.ldb, p.tb == 0, n0, k0, p.N, kend, p.vb != 0);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
@@ -124,8 +138,13 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmP p) {
   }
 }
 
+// an operand allows 16-byte loads of 8 consecutive elements
+bool vec_ok(const uint16_t* G, int ld) { return ld % 8 == 0 && (reinterpret_cast<uintptr_t>(G) & 15u) == 0; }
+
 template <int EPI>
-hipError_t gemm(const GemmP& p, hipStream_t s) {
+hipError_t gemm(GemmP p, hipStream_t s) {
+  p.va = vec_ok(p.A, p.lda);
+  p.vb = vec_ok(p.B, p.ldb);
   dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM);
   k_gemm<EPI><<<grid, 256, 0, s>>>(p);
   return hipGetLastError();
@@ -152,6 +171,8 @@ hipError_t gemm_f32_split(GemmP p, float* part, hipStream_t s) {
   p.kchunk = ((p.K + ks - 1) / ks + BK - 1) / BK * BK;
   ks = (p.K + p.kchunk - 1) / p.kchunk;
   p.part = part;
+  p.va = vec_ok(p.A, p.lda);
+  p.vb = vec_ok(p.B, p.ldb);
   dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM, ks);
   k_gemm<EPI_F32><<<grid, 256, 0, s>>>(p);
   const int64_t mn = (int64_t)p.M * p.N;
