@@ -5,13 +5,15 @@
 // the packet to the cell tally and re-emits it isotropically at a frequency
 // drawn from the cell temperature before the absorption.
 //
-// Execution: a persistent pool.  Every lane of a wave64 carries one packet;
-// when packets end, the wave refills its dead lanes with new packet ids from a
-// global counter (one atomic per wave).  Random numbers come from Philox keyed
-// by packet id, so a packet's history does not depend on which lane runs it.
-// Geometry runs in R (float or double) on base-cube units, with the current
-// cell held as integer finest-level coordinates so face crossings never lose
-// the packet; tallies are 64-bit integer atomics.
+// Execution: a persistent pool.  Every lane of a wave64 carries one packet and
+// marches it cell after cell; when packets end, the wave refills its dead
+// lanes with new packet ids from a global counter (one atomic per wave).
+// Random numbers come from Philox keyed by packet id, so a packet's history
+// does not depend on which lane runs it.  Geometry runs in R (float or double)
+// on base-cube units, with the current cell held as integer finest-level
+// coordinates so face crossings never lose the packet; tallies are 64-bit
+// integer sums (atomics, or for the path tally records added after the
+// kernel).
 #include "mcrt_internal.h"
 
 namespace mcrt {
@@ -320,7 +322,8 @@ constexpr int kRefillMin = 32;
 // rounding scales with the cell, not with the distance from the grid origin;
 // crossing into a neighbour re-bases u by an exact integer offset.
 // With the deferred path tally (DEFER) the record logic needs more registers:
-// five waves per SIMD without spills beat six or seven with them.
+// five waves per SIMD (a few loop-invariant words spilled, read back only off
+// the march) beat six or seven with more spills.
 template <typename R, bool TRACE, bool IMG, bool DEFER>
 __global__ void __launch_bounds__(256, DEFER ? 5 : 7) k_transport(const TP<R> P) {
   extern __shared__ double smem[];
